@@ -1,0 +1,258 @@
+/*
+ * md.h -- C ABI of the MI355X (gfx950) Lennard-Jones MD hot path.
+ *
+ * The method is that of Watanabe, Suzuki and Ito, "Efficient Implementations
+ * of Molecular Dynamics Simulations for Lennard-Jones Systems": a truncated LJ
+ * potential (Sec. 2.1), an inexclusive cell grid built by counting sort
+ * (Sec. 2.2), a pair list with a search length rs > rc reused for several steps
+ * (Sec. 2.3), a key-sorted pair list and force loop (Sec. 2.4, Sec. 3.1), a
+ * cell-order re-sort of the particle arrays (Sec. 3.3) and a second-order
+ * symplectic integrator in a periodic box (Sec. 4.5).
+ *
+ * General rules
+ *   - Every pointer argument named as "device" is a device (HBM) address on the
+ *     current HIP device; "host" pointers are ordinary host memory.
+ *   - The caller allocates and frees every buffer, including the workspace;
+ *     the library never allocates device memory.
+ *   - All work is enqueued on the given hipStream_t.  Only md_prepare and
+ *     md_step synchronise that stream (they read device flags); every other
+ *     call is asynchronous and returns only errors detectable on the host.
+ *   - Return value: MD_OK (0) or a negative MD_ERR_* code; md_last_error()
+ *     then returns a message (thread-local, valid until the next call).
+ *   - Argument checks run on the host before any launch, so a call that fails
+ *     validation enqueues nothing.
+ *
+ * Units: reduced LJ units, unit mass.
+ *
+ * Layouts (n = number of particles, slots are the current array positions):
+ *   pos     device double[n][4]   (x, y, z, 0) per slot; 0 <= x < L required
+ *                                 where noted (md_step maintains it)
+ *   vel     device double[3][n]   x block, then y block, then z block
+ *   force   device double[3][n] (MD_FP64) or float[3][n] (MD_MIXED)
+ *   u, Hu   device double[3][n]   (adjoint vectors)
+ */
+#ifndef MD355_MD_H
+#define MD355_MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MD_OK             0
+#define MD_ERR_ARG       (-1)  /* null pointer, n <= 0 or n >= 2^27, bad parameter   */
+#define MD_ERR_BOX       (-2)  /* fewer than 3 or more than 1023 cells on an axis     */
+#define MD_ERR_CAPACITY  (-3)  /* pair list does not fit: see md_pairlist.status     */
+#define MD_ERR_NONFINITE (-4)  /* a force or energy became inf/NaN                    */
+#define MD_ERR_HIP       (-5)  /* HIP launch/runtime failure                          */
+#define MD_ERR_WORKSPACE (-6)  /* workspace smaller than md_workspace_bytes()         */
+
+/* precision modes */
+#define MD_FP64  0   /* every pair term and sum in FP64                              */
+#define MD_MIXED 1   /* pair displacement, force and per-particle sums in FP32;
+                        positions, velocities, integration and global sums in FP64 */
+
+#define MD_MAX_N ((int64_t)1 << 27)   /* slots are stored in 27 bits of a list entry */
+
+/* Model and run parameters.
+ *   V(r) = 4 eps [ (sigma/r)^12 - (sigma/r)^6 + c2 (r/sigma)^2 + c0 ] for r < rc,
+ *   with c2, c0 fixed by V(rc) = V'(rc) = 0 (Sec. 2.1, eq. lj_cutoff); rc and rs
+ *   are absolute lengths.  Pairs with r < rs are listed (Sec. 2.3); the list is
+ *   rebuilt when some particle has moved more than (rs - rc)/2 since the last
+ *   build (the search-length figure of Sec. 2.3).  Cells per axis are
+ *   floor(L / rs) (cell side >= rs, Sec. 2.2).
+ *   resort_every: re-sort the particle arrays into cell order at every k-th
+ *   rebuild (Sec. 3.3; 0 = never, 1 = every rebuild). */
+typedef struct md_params {
+    int64_t n;
+    double  box[3];
+    double  eps, sigma;
+    double  rc, rs;
+    double  dt;
+    int32_t precision;     /* MD_FP64 or MD_MIXED */
+    int32_t resort_every;
+} md_params;
+
+/* Cell grid (Sec. 2.2): GridParticleNumber = count, GridPointer = start,
+ * GridList = order.  Cell id of a slot: (cx * ny + cy) * nz + cz with
+ * cx = min(floor(x * nx / L), nx - 1).
+ *   cell_of   device int32[n]      cell id of each slot
+ *   cell_xyz  device int32[n]      packed cell coords cx | cy << 10 | cz << 20
+ *   count     device int32[nc]     particles per cell
+ *   start     device int32[nc+1]   exclusive prefix sum of count; start[nc] = n
+ *   order     device int32[n]      slots sorted by cell, stable (ascending slot
+ *                                  within a cell)
+ *   sorted    host flag: 1 when the slots themselves are in cell order (after a
+ *             re-sort), so that cell c holds slots start[c] .. start[c+1]-1; the
+ *             library sets it, md_bin_cells clears it.                       */
+typedef struct md_cells {
+    int32_t  ncell[3];
+    int32_t  sorted;
+    int32_t* cell_of;
+    int32_t* cell_xyz;
+    int32_t* count;
+    int32_t* start;
+    int32_t* order;
+} md_cells;
+
+/* Key-sorted pair list (Sec. 2.4: KeyPointer / SortedList), full (both
+ * directions): the row of key slot i is nbr[offsets[i] .. offsets[i]+counts[i]).
+ * Each entry is (partner slot) | (stencil code << 27), where the stencil code
+ * (sx+1)*9 + (sy+1)*3 + (sz+1) names the neighbour cell of the partner relative
+ * to the key's cell at build time (s in {-1,0,1}^3).  Rows list partners in
+ * stencil-code order, then ascending slot.  Rows of the keys of cell c live in
+ * the block nbr[c*cell_stride .. (c+1)*cell_stride).
+ *   offsets   device int64[n]
+ *   counts    device int32[n]
+ *   nbr       device uint32[capacity], capacity >= nc * cell_stride
+ *   status    device int64[4]: [0] total entries, [1] largest per-cell block,
+ *             [2] 1 if some cell block overflowed cell_stride (list invalid),
+ *             [3] reserved.                                               */
+typedef struct md_pairlist {
+    int64_t*  offsets;
+    int32_t*  counts;
+    uint32_t* nbr;
+    int64_t   cell_stride;
+    int64_t   capacity;
+    int64_t*  status;
+} md_pairlist;
+
+/* Per-kernel-class timers filled by md_step when md_state.timers != NULL:
+ * HIP-event time summed over launches, in milliseconds. */
+enum { MD_T_FORCE = 0, MD_T_INTEGRATE, MD_T_BIN, MD_T_RESORT, MD_T_BUILD, MD_T_REDUCE, MD_T_COUNT };
+typedef struct md_timers {
+    double  ms[MD_T_COUNT];
+    int64_t launches[MD_T_COUNT];
+} md_timers;
+
+/* Whole simulation state for md_prepare / md_step / md_energy.
+ *   pos, vel, id: current arrays; pos_alt, vel_alt, id_alt: targets of the
+ *   re-sort, swapped with the current ones by the library (read the pointers
+ *   back after a call).  pos_ref: device double[3][n], positions at the last
+ *   build.  pos32: device float[n][4], MD_MIXED only: coordinates relative to
+ *   each slot's cell corner at the last build (NULL in MD_FP64).
+ *   energy: device double[8]: KE, PE, W, E at the last sampled step, then
+ *   max squared displacement, reserved.
+ *   flags: device int64[8]: [0] non-finite force seen, others reserved.
+ *   host_scratch: host int64[16] (pinned recommended) for flag read-back.
+ *   ws: device workspace of ws_bytes >= md_workspace_bytes().
+ *   step, rebuilds, resorts: host counters; phase: 0 = (q, v, F) at a whole
+ *   step, 1 = stopped after a drift (resumed by the next md_step), 2 = arrays
+ *   re-sorted by md_resort (md_prepare needed). */
+typedef struct md_state {
+    double*   pos;
+    double*   vel;
+    void*     force;
+    double*   pos_ref;
+    float*    pos32;
+    int32_t*  id;
+    double*   pos_alt;
+    double*   vel_alt;
+    int32_t*  id_alt;
+    md_cells    cells;
+    md_pairlist list;
+    double*   energy;
+    int64_t*  flags;
+    int64_t*  host_scratch;
+    void*     ws;
+    size_t    ws_bytes;
+    md_timers* timers;
+    int64_t   step;
+    int64_t   rebuilds;
+    int64_t   resorts;
+    int32_t   phase;
+    int32_t   list_valid;
+} md_state;
+
+/* Host-only: cells per axis for these parameters.  MD_ERR_BOX when an axis
+ * has fewer than 3 or more than 1023 cells. */
+int md_cell_dims(const md_params* p, int32_t ncell[3]);
+
+/* Host-only: device workspace bytes needed by every call below for p. */
+size_t md_workspace_bytes(const md_params* p);
+
+/* Cell grid of pos (Sec. 2.2): label each slot with its cell, count per cell,
+ * prefix-sum the counts, place slots by cell in ascending slot order.
+ * pos: device double[n][4] with 0 <= x < L.  Fills cells (which must point to
+ * arrays of the sizes in md_cells) and clears cells->sorted.  Results are
+ * deterministic and equal to a sequential stable counting sort. */
+int md_bin_cells(const md_params* p, const double* pos, md_cells* cells,
+                 void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Re-sort (Sec. 3.3): permute st->pos, vel, id into cell order using
+ * st->cells (from md_bin_cells on st->pos), writing the *_alt arrays and then
+ * swapping the pointers; rewrites cells->cell_of / cell_xyz in the new slot
+ * order, sets cells->sorted, copies the positions into pos_ref and, in mixed
+ * mode, fills pos32.  cells->order keeps the old slot of each new slot.
+ * The pair list and the forces then refer to the old order: md_step refuses
+ * to run until md_prepare has been called again (md_step re-sorts by itself
+ * at rebuilds when resort_every > 0). */
+int md_resort(const md_params* p, md_state* st, hipStream_t stream);
+
+/* Pair list (Sec. 2.3-2.4): for every slot i, all partners j != i whose
+ * minimum-image distance satisfies r^2 < rs^2, with
+ *   d = q_j - q_i per axis, d -= L * rint(d / L),
+ *   r^2 = fma(dz, dz, fma(dy, dy, dx * dx))   (FP64, bit-exact),
+ * found among the 27 cells around the key's cell.  cells must come from
+ * md_bin_cells (and md_resort, if applied) on the same pos.  Overflow of a cell
+ * block is reported in list->status ([2] = 1, [1] = the stride needed). */
+int md_build_pairlist(const md_params* p, const double* pos, const md_cells* cells,
+                      md_pairlist* list, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Forces (Sec. 3.1-3.2): for every listed pair with r < rc (strict;
+ * branch-free select), F_i -= g d with d = q_j - q_i and g = -V'(r)/r.
+ * force: device double[3][n] (MD_FP64) or float[3][n] (MD_MIXED).
+ * pe_w: device double[2] receiving PE = sum_pairs V and the virial
+ * W = sum_pairs g r^2, or NULL to skip the energy terms.  pos may have moved
+ * since the list was built as long as no particle moved more than (rs-rc)/2. */
+int md_forces(const md_params* p, const double* pos, const md_cells* cells,
+              const md_pairlist* list, void* force, double* pe_w,
+              void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Bin, (re-sort if resort_every > 0), build the list and evaluate forces and
+ * energies at the current positions; leaves st at phase 0.  Synchronises.
+ * MD_ERR_CAPACITY: st->list.status holds the stride needed. */
+int md_prepare(const md_params* p, md_state* st, hipStream_t stream);
+
+/* nsteps of velocity Verlet (kick-drift-kick, unit mass; Sec. 4.5):
+ *   v += (dt/2) F;  q = wrap(q + dt v);  [rebuild if max displacement since
+ *   the last build exceeds (rs - rc)/2];  F = F(q);  v += (dt/2) F.
+ * Every sample_every steps (counted from st->step) the row
+ * energy_log[k][0..3] = (KE, PE, W, KE + PE) is written (device double
+ * array; NULL to skip; sample_every <= 0 samples nothing).  Synchronises once
+ * per step to read the rebuild flag.  On MD_ERR_CAPACITY the state stops in
+ * phase 1 with st->step steps done; grow the list and call md_step again.
+ * MD_ERR_NONFINITE stops after the step that produced a non-finite force. */
+int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_every,
+            double* energy_log, hipStream_t stream);
+
+/* Kinetic, potential, virial and total energy at the current state:
+ * out: device double[4] = (KE, PE, W, KE + PE).  Recomputes the forces. */
+int md_energy(const md_params* p, md_state* st, double* out, hipStream_t stream);
+
+/* Hessian-vector product of U = sum_pairs V (adjoint of the force field):
+ * Hu_i = sum_j d^2U/dq_i dq_j u_j, over listed pairs with r < rc, FP64.
+ * dparam: device double[2] = u . dF/d(eps, sigma) (F = -grad U), or NULL.
+ * u, Hu: device double[3][n]. */
+int md_hvp(const md_params* p, const double* pos, const md_cells* cells,
+           const md_pairlist* list, const double* u, double* Hu, double* dparam,
+           void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* dU/deps and dU/dsigma of the potential energy (FP64), into device double[2]. */
+int md_param_grad(const md_params* p, const double* pos, const md_cells* cells,
+                  const md_pairlist* list, double* dU, void* ws, size_t ws_bytes,
+                  hipStream_t stream);
+
+/* Message for the last non-OK status on this thread. */
+const char* md_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MD355_MD_H */

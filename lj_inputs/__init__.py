@@ -17,6 +17,7 @@ import numpy as np
 
 __all__ = [
     "fcc_lattice",
+    "fcc_lattice_box",
     "maxwell_boltzmann",
     "fixed_speed_velocities",
     "jittered_fcc",
@@ -70,6 +71,18 @@ def maxwell_boltzmann(n: int, T: float = 1.0, seed: int = 0):
     return np.ascontiguousarray(v * scale)
 
 
+def fcc_lattice_box(nx: int, ny: int, nz: int, rho: float = 0.5):
+    """fcc lattice of nx x ny x nz unit cells (an anisotropic periodic box).
+    Returns (pos[N,3], L[3]); same site order and basis as fcc_lattice."""
+    a = lattice_constant(rho)
+    ix, iy, iz = np.meshgrid(np.arange(nx, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                             np.arange(nz, dtype=np.float64), indexing="ij")
+    corners = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1)
+    basis = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5]])
+    pos = (corners[:, None, :] + basis[None, :, :]).reshape(-1, 3) * a
+    return np.ascontiguousarray(pos), [nx * a, ny * a, nz * a]
+
+
 def fixed_speed_velocities(n: int, speed: float = 0.9, seed: int = 0):
     """Velocities of fixed magnitude in random directions (Sec. 4.5 benchmark
     conditions use |v| = 0.9).  No momentum removal, as in the benchmark."""
@@ -79,11 +92,12 @@ def fixed_speed_velocities(n: int, speed: float = 0.9, seed: int = 0):
     return np.ascontiguousarray(u * speed)
 
 
-def wrap_into_box(pos: np.ndarray, L: float) -> np.ndarray:
-    """Place coordinates in [0, L) (input preparation only)."""
+def wrap_into_box(pos: np.ndarray, L) -> np.ndarray:
+    """Place coordinates in [0, L) (input preparation only); L scalar or per axis."""
+    L = np.asarray(L, dtype=np.float64)
     p = np.mod(pos, L)
-    p[p >= L] -= L
-    p[p < 0.0] += L
+    p = np.where(p >= L, p - L, p)
+    p = np.where(p < 0.0, p + L, p)
     return np.ascontiguousarray(p)
 
 

@@ -1,0 +1,593 @@
+// C-ABI entry points: argument validation on the host, derived geometry,
+// workspace layout and the step loop that sequences the kernels.
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <utility>
+
+#include "md_internal.h"
+
+namespace md {
+
+static thread_local char g_err[512] = "";
+
+static int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char* where)
+{
+    return fail(MD_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define MD_HIP(expr, where)                        \
+    do {                                           \
+        hipError_t e__ = (expr);                   \
+        if (e__ != hipSuccess) return hip_fail(e__, where); \
+    } while (0)
+
+static int check_params(const md_params* p, int32_t nc[3])
+{
+    if (!p) return fail(MD_ERR_ARG, "params is NULL");
+    if (p->n <= 0 || p->n >= MD_MAX_N) return fail(MD_ERR_ARG, "n = %lld outside [1, 2^27)", (long long)p->n);
+    for (int k = 0; k < 3; ++k)
+        if (!(p->box[k] > 0.0) || !std::isfinite(p->box[k])) return fail(MD_ERR_ARG, "box[%d] must be > 0", k);
+    if (!(p->eps > 0.0) || !(p->sigma > 0.0)) return fail(MD_ERR_ARG, "eps and sigma must be > 0");
+    if (!(p->rc > 0.0) || !(p->rs >= p->rc)) return fail(MD_ERR_ARG, "need 0 < rc <= rs");
+    if (p->precision != MD_FP64 && p->precision != MD_MIXED) return fail(MD_ERR_ARG, "precision must be 0 or 1");
+    if (p->resort_every < 0) return fail(MD_ERR_ARG, "resort_every must be >= 0");
+    for (int k = 0; k < 3; ++k) {
+        const double m = std::floor(p->box[k] / p->rs);
+        if (m < 3.0) return fail(MD_ERR_BOX, "axis %d has %.0f cells (< 3): box too small for rs", k, m);
+        if (m > 1023.0) return fail(MD_ERR_BOX, "axis %d has %.0f cells (> 1023)", k, m);
+        nc[k] = (int32_t)m;
+    }
+    if ((int64_t)nc[0] * nc[1] * nc[2] >= ((int64_t)1 << 31)) return fail(MD_ERR_BOX, "too many cells");
+    return MD_OK;
+}
+
+Geo make_geo(const md_params& p, const int32_t nc[3])
+{
+    Geo g;
+    g.n = p.n;
+    g.ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    g.exact_all = 0;
+    for (int k = 0; k < 3; ++k) {
+        g.nc[k] = nc[k];
+        g.L[k] = p.box[k];
+        g.invL[k] = 1.0 / p.box[k];
+        g.inv[k] = (double)nc[k] / p.box[k];
+        g.cs[k] = p.box[k] / (double)nc[k];
+        if (nc[k] < 5) g.exact_all = 1;
+    }
+    return g;
+}
+
+LJ make_lj(const md_params& p)
+{
+    LJ lj;
+    const double e = p.eps, s = p.sigma, rc = p.rc;
+    const double x = s / rc;
+    const double x2 = x * x, x6 = x2 * x2 * x2, x8 = x6 * x2, x12 = x6 * x6, x14 = x12 * x2;
+    const double c2 = 6.0 * x14 - 3.0 * x8;   // V'(rc) = 0
+    const double c0 = -7.0 * x12 + 4.0 * x6;  // V(rc) = 0
+    const double s2 = s * s, s6 = s2 * s2 * s2, s12 = s6 * s6;
+    lj.rc2 = rc * rc;
+    lj.A = 48.0 * e * s12;
+    lj.B = 24.0 * e * s6;
+    lj.C8 = 8.0 * e * c2 / s2;
+    lj.A4 = 4.0 * e * s12;
+    lj.B4 = 4.0 * e * s6;
+    lj.C2 = 4.0 * e * c2 / s2;
+    lj.C0 = 4.0 * e * c0;
+    lj.eps = e;
+    lj.sigma = s;
+    const double rc2 = rc * rc, rc6 = rc2 * rc2 * rc2, rc8 = rc6 * rc2, rc12 = rc6 * rc6, rc14 = rc12 * rc2;
+    lj.rc6i = 1.0 / rc6;
+    lj.rc8i = 1.0 / rc8;
+    lj.rc12i = 1.0 / rc12;
+    lj.rc14i = 1.0 / rc14;
+    // C8 = 48 eps s^12 rc^-14 - 24 eps s^6 rc^-8, so sigma dC8/dsigma:
+    lj.Cs = 12.0 * 48.0 * e * s12 / rc14 - 6.0 * 24.0 * e * s6 / rc8;
+    return lj;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+WsLayout ws_layout(int64_t n, int64_t ncell)
+{
+    WsLayout L;
+    L.nbs = ceil_div(ncell, kScanItems);
+    L.nbf = ceil_div(n, kKeysPerBlock);
+    L.nbi = ceil_div(n, kStreamBlock);
+    size_t off = 0;
+    L.rank = off;      off = align256(off + sizeof(int32_t) * (size_t)n);
+    L.bsum = off;      off = align256(off + sizeof(int32_t) * (size_t)(L.nbs + 1));
+    L.cell_rows = off; off = align256(off + sizeof(int32_t) * (size_t)ncell);
+    L.part_a = off;    off = align256(off + sizeof(double) * 2 * (size_t)L.nbf);
+    L.part_b = off;    off = align256(off + sizeof(double) * (size_t)L.nbi);
+    L.pos32 = off;     off = align256(off + 16 * (size_t)n);
+    L.scal = off;      off = align256(off + sizeof(double) * 16);
+    L.total = off;
+    return L;
+}
+
+struct Ctx {
+    int32_t nc[3];
+    Geo g;
+    LJ lj;
+    WsLayout W;
+};
+
+static int setup(const md_params* p, Ctx& c)
+{
+    int rc = check_params(p, c.nc);
+    if (rc != MD_OK) return rc;
+    c.g = make_geo(*p, c.nc);
+    c.lj = make_lj(*p);
+    c.W = ws_layout(p->n, c.g.ncell);
+    return MD_OK;
+}
+
+static int check_ws(const Ctx& c, const void* ws, size_t ws_bytes)
+{
+    if (!ws) return fail(MD_ERR_ARG, "workspace is NULL");
+    if (ws_bytes < c.W.total)
+        return fail(MD_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, c.W.total);
+    return MD_OK;
+}
+
+static int check_cells(const Ctx& c, const md_cells* cells)
+{
+    if (!cells || !cells->cell_of || !cells->cell_xyz || !cells->count || !cells->start || !cells->order)
+        return fail(MD_ERR_ARG, "cells has a NULL array");
+    return MD_OK;
+}
+
+static int check_list(const Ctx& c, const md_pairlist* list)
+{
+    if (!list || !list->offsets || !list->counts || !list->nbr || !list->status)
+        return fail(MD_ERR_ARG, "pair list has a NULL array");
+    if (list->cell_stride <= 0) return fail(MD_ERR_ARG, "cell_stride must be > 0");
+    if (list->capacity < c.g.ncell * list->cell_stride)
+        return fail(MD_ERR_ARG, "capacity %lld < ncell * cell_stride = %lld", (long long)list->capacity,
+                    (long long)(c.g.ncell * list->cell_stride));
+    return MD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// timers
+// ---------------------------------------------------------------------------
+// Up to two launches of each kernel class are timed between two host waits
+// (md_step waits once or twice per step, so every launch is covered).
+struct Timer {
+    md_timers* t;
+    bool ok;
+    int n[MD_T_COUNT];
+};
+
+static hipEvent_t g_ev[MD_T_COUNT][2][2];
+static bool g_ev_made = false;
+
+static void timer_begin(Timer& T, md_timers* t)
+{
+    T.t = t;
+    T.ok = t != nullptr;
+    for (int k = 0; k < MD_T_COUNT; ++k) T.n[k] = 0;
+    if (!T.ok || g_ev_made) return;
+    for (int a = 0; a < MD_T_COUNT; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int e = 0; e < 2; ++e)
+                if (hipEventCreate(&g_ev[a][b][e]) != hipSuccess) {
+                    T.ok = false;
+                    return;
+                }
+    g_ev_made = true;
+}
+
+static void tick(Timer& T, int cls, int which, hipStream_t s)
+{
+    if (!T.ok) return;
+    const int k = T.n[cls];
+    if (k >= 2) return;
+    (void)hipEventRecord(g_ev[cls][k][which], s);
+    if (which == 1) T.n[cls] = k + 1;
+}
+
+// call after the stream has been synchronised
+static void timer_collect(Timer& T)
+{
+    if (!T.ok) return;
+    for (int c = 0; c < MD_T_COUNT; ++c) {
+        for (int k = 0; k < T.n[c]; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, g_ev[c][k][0], g_ev[c][k][1]) == hipSuccess) {
+                T.t->ms[c] += ms;
+                T.t->launches[c] += 1;
+            }
+        }
+        T.n[c] = 0;
+    }
+}
+
+}  // namespace md
+
+using namespace md;
+
+extern "C" {
+
+const char* md_last_error(void) { return g_err; }
+
+int md_cell_dims(const md_params* p, int32_t ncell[3])
+{
+    if (!ncell) return fail(MD_ERR_ARG, "ncell is NULL");
+    int32_t nc[3];
+    int rc = check_params(p, nc);
+    if (rc != MD_OK) return rc;
+    for (int k = 0; k < 3; ++k) ncell[k] = nc[k];
+    return MD_OK;
+}
+
+size_t md_workspace_bytes(const md_params* p)
+{
+    int32_t nc[3];
+    if (check_params(p, nc) != MD_OK) return 0;
+    return ws_layout(p->n, (int64_t)nc[0] * nc[1] * nc[2]).total;
+}
+
+int md_bin_cells(const md_params* p, const double* pos, md_cells* cells, void* ws, size_t ws_bytes,
+                 hipStream_t stream)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if (!pos) return fail(MD_ERR_ARG, "pos is NULL");
+    if ((rc = check_cells(c, cells)) != MD_OK) return rc;
+    if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
+    for (int k = 0; k < 3; ++k) cells->ncell[k] = c.nc[k];
+    int64_t* err = (int64_t*)((char*)ws + c.W.scal);
+    MD_HIP(launch_fill_i32((int32_t*)err, 0, 2, stream), "md_bin_cells/clear");
+    MD_HIP(launch_bin(c.g, pos, *cells, ws, c.W, err, stream), "md_bin_cells");
+    cells->sorted = 0;
+    return MD_OK;
+}
+
+int md_build_pairlist(const md_params* p, const double* pos, const md_cells* cells, md_pairlist* list,
+                      void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if (!pos) return fail(MD_ERR_ARG, "pos is NULL");
+    if ((rc = check_cells(c, cells)) != MD_OK) return rc;
+    if ((rc = check_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
+    MD_HIP(launch_build(c.g, p->rs, pos, *cells, *list, ws, c.W, stream), "md_build_pairlist");
+    return MD_OK;
+}
+
+int md_forces(const md_params* p, const double* pos, const md_cells* cells, const md_pairlist* list,
+              void* force, double* pe_w, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if (!pos || !force) return fail(MD_ERR_ARG, "pos or force is NULL");
+    if ((rc = check_cells(c, cells)) != MD_OK) return rc;
+    if ((rc = check_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
+    char* w = (char*)ws;
+    float* pos32 = nullptr;
+    if (p->precision == MD_MIXED) {
+        pos32 = (float*)(w + c.W.pos32);
+        MD_HIP(launch_ref_copy(c.g, pos, cells->cell_xyz, nullptr, pos32, stream), "md_forces/pos32");
+    }
+    ForceOut out;
+    out.force = force;
+    out.part = pe_w ? (double*)(w + c.W.part_a) : nullptr;
+    out.flags = (int64_t*)(w + c.W.scal) + 2;
+    MD_HIP(launch_forces(c.g, c.lj, p->precision, pos, pos32, cells->cell_xyz, *list, out, stream),
+           "md_forces");
+    if (pe_w) MD_HIP(launch_reduce_pair(out.part, c.W.nbf, 1.0, 1.0, pe_w, stream), "md_forces/reduce");
+    return MD_OK;
+}
+
+int md_hvp(const md_params* p, const double* pos, const md_cells* cells, const md_pairlist* list,
+           const double* u, double* Hu, double* dparam, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if (!pos || !u || !Hu) return fail(MD_ERR_ARG, "pos, u or Hu is NULL");
+    if ((rc = check_cells(c, cells)) != MD_OK) return rc;
+    if ((rc = check_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
+    double* part = dparam ? (double*)((char*)ws + c.W.part_a) : nullptr;
+    MD_HIP(launch_hvp(c.g, c.lj, pos, cells->cell_xyz, *list, u, Hu, part, stream), "md_hvp");
+    if (dparam) MD_HIP(launch_reduce_pair(part, c.W.nbf, 1.0, 1.0, dparam, stream), "md_hvp/reduce");
+    return MD_OK;
+}
+
+int md_param_grad(const md_params* p, const double* pos, const md_cells* cells, const md_pairlist* list,
+                  double* dU, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if (!pos || !dU) return fail(MD_ERR_ARG, "pos or dU is NULL");
+    if ((rc = check_cells(c, cells)) != MD_OK) return rc;
+    if ((rc = check_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
+    double* part = (double*)((char*)ws + c.W.part_a);
+    MD_HIP(launch_param_grad(c.g, c.lj, pos, cells->cell_xyz, *list, part, stream), "md_param_grad");
+    MD_HIP(launch_reduce_pair(part, c.W.nbf, 1.0, 1.0, dU, stream), "md_param_grad/reduce");
+    return MD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// state-level calls
+// ---------------------------------------------------------------------------
+static int check_state(const Ctx& c, const md_params* p, md_state* st)
+{
+    if (!st) return fail(MD_ERR_ARG, "state is NULL");
+    if (!st->pos || !st->vel || !st->force || !st->pos_ref || !st->id || !st->energy || !st->flags)
+        return fail(MD_ERR_ARG, "state has a NULL array");
+    if (p->precision == MD_MIXED && !st->pos32) return fail(MD_ERR_ARG, "mixed precision needs pos32");
+    if (p->resort_every > 0 && (!st->pos_alt || !st->vel_alt || !st->id_alt))
+        return fail(MD_ERR_ARG, "re-sorting needs pos_alt, vel_alt and id_alt");
+    int rc = check_cells(c, &st->cells);
+    if (rc != MD_OK) return rc;
+    if ((rc = check_list(c, &st->list)) != MD_OK) return rc;
+    return check_ws(c, st->ws, st->ws_bytes);
+}
+
+// bin + optional re-sort + reference copy + list build (no wait)
+static int rebuild(const Ctx& c, const md_params* p, md_state* st, bool allow_resort, Timer& T,
+                   hipStream_t s)
+{
+    int64_t* err = (int64_t*)((char*)st->ws + c.W.scal);
+    tick(T, MD_T_BIN, 0, s);
+    MD_HIP(launch_bin(c.g, st->pos, st->cells, st->ws, c.W, err, s), "rebuild/bin");
+    tick(T, MD_T_BIN, 1, s);
+    for (int k = 0; k < 3; ++k) st->cells.ncell[k] = c.nc[k];
+    st->cells.sorted = 0;
+    const bool resort = allow_resort && p->resort_every > 0 && (st->rebuilds % p->resort_every) == 0;
+    if (resort) {
+        tick(T, MD_T_RESORT, 0, s);
+        MD_HIP(launch_resort(c.g, st->cells.order, st->pos, st->vel, st->id, st->pos_alt, st->vel_alt,
+                             st->id_alt, st->pos_ref, p->precision == MD_MIXED ? st->pos32 : nullptr,
+                             st->cells.cell_of, st->cells.cell_xyz, s),
+               "rebuild/resort");
+        tick(T, MD_T_RESORT, 1, s);
+        std::swap(st->pos, st->pos_alt);
+        std::swap(st->vel, st->vel_alt);
+        std::swap(st->id, st->id_alt);
+        st->cells.sorted = 1;
+        st->resorts += 1;
+    } else {
+        MD_HIP(launch_ref_copy(c.g, st->pos, st->cells.cell_xyz, st->pos_ref,
+                               p->precision == MD_MIXED ? st->pos32 : nullptr, s),
+               "rebuild/ref");
+    }
+    tick(T, MD_T_BUILD, 0, s);
+    MD_HIP(launch_build(c.g, p->rs, st->pos, st->cells, st->list, st->ws, c.W, s), "rebuild/build");
+    tick(T, MD_T_BUILD, 1, s);
+    return MD_OK;
+}
+
+// wait for the stream and read, in one copy: list status [0..3], cell-grid
+// error flags [4..5], force flags [6], max squared displacement bits [7]
+static int read_flags(const Ctx& c, md_state* st, hipStream_t s, int64_t out[8])
+{
+    int64_t* scal = (int64_t*)((char*)st->ws + c.W.scal);
+    MD_HIP(launch_gather_flags(st->list.status, scal, st->flags, st->energy, scal + 8, s), "flags/gather");
+    int64_t local[16];
+    int64_t* dst = st->host_scratch ? st->host_scratch : local;
+    MD_HIP(hipMemcpyAsync(dst, scal + 8, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s), "flags/copy");
+    MD_HIP(hipStreamSynchronize(s), "flags/sync");
+    for (int k = 0; k < 8; ++k) out[k] = dst[k];
+    return MD_OK;
+}
+
+static int force_eval(const Ctx& c, const md_params* p, md_state* st, bool energy, Timer& T, hipStream_t s)
+{
+    ForceOut out;
+    out.force = st->force;
+    out.part = energy ? (double*)((char*)st->ws + c.W.part_a) : nullptr;
+    out.flags = st->flags;
+    tick(T, MD_T_FORCE, 0, s);
+    MD_HIP(launch_forces(c.g, c.lj, p->precision, st->pos, p->precision == MD_MIXED ? st->pos32 : nullptr,
+                         st->cells.cell_xyz, st->list, out, s),
+           "forces");
+    tick(T, MD_T_FORCE, 1, s);
+    return MD_OK;
+}
+
+static IntArgs int_args(const Ctx& c, const md_params* p, md_state* st, bool ke)
+{
+    IntArgs a;
+    a.pos = st->pos;
+    a.vel = st->vel;
+    a.force = st->force;
+    a.pos_ref = st->pos_ref;
+    a.pos32 = st->pos32;
+    a.cell_xyz = st->cells.cell_xyz;
+    a.part_ke = ke ? (double*)((char*)st->ws + c.W.part_b) : nullptr;
+    a.max_d2 = (unsigned long long*)(st->energy + 4);
+    a.dt = p->dt;
+    a.precision = p->precision;
+    return a;
+}
+
+static int check_status(const int64_t f[8], const md_state* st)
+{
+    if (f[2] != 0)
+        return fail(MD_ERR_CAPACITY, "pair list overflow: a cell needs %lld entries, cell_stride is %lld",
+                    (long long)f[1], (long long)st->list.cell_stride);
+    if (f[4] & 2) return fail(MD_ERR_ARG, "positions outside [0, L) given to the cell grid");
+    if (f[6] & 1) return fail(MD_ERR_NONFINITE, "non-finite force");
+    return MD_OK;
+}
+
+int md_resort(const md_params* p, md_state* st, hipStream_t stream)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if ((rc = check_state(c, p, st)) != MD_OK) return rc;
+    if (!st->pos_alt || !st->vel_alt || !st->id_alt) return fail(MD_ERR_ARG, "re-sort needs *_alt arrays");
+    MD_HIP(launch_resort(c.g, st->cells.order, st->pos, st->vel, st->id, st->pos_alt, st->vel_alt, st->id_alt,
+                         st->pos_ref, p->precision == MD_MIXED ? st->pos32 : nullptr, st->cells.cell_of,
+                         st->cells.cell_xyz, stream),
+           "md_resort");
+    std::swap(st->pos, st->pos_alt);
+    std::swap(st->vel, st->vel_alt);
+    std::swap(st->id, st->id_alt);
+    st->cells.sorted = 1;
+    st->resorts += 1;
+    st->list_valid = 0;
+    st->phase = 2;  // forces now belong to the old slot order: md_prepare must run
+    return MD_OK;
+}
+
+int md_prepare(const md_params* p, md_state* st, hipStream_t s)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if ((rc = check_state(c, p, st)) != MD_OK) return rc;
+    Timer T;
+    timer_begin(T, nullptr);
+    MD_HIP(launch_fill_i32((int32_t*)st->flags, 0, 2, s), "prepare/flags");
+    MD_HIP(launch_fill_i32((int32_t*)((char*)st->ws + c.W.scal), 0, 4, s), "prepare/err");
+    if ((rc = rebuild(c, p, st, true, T, s)) != MD_OK) return rc;
+    st->rebuilds += 1;
+    int64_t f[8];
+    if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
+    if ((rc = check_status(f, st)) != MD_OK) {
+        st->list_valid = 0;
+        return rc;
+    }
+    st->list_valid = 1;
+    if ((rc = force_eval(c, p, st, true, T, s)) != MD_OK) return rc;
+    IntArgs a = int_args(c, p, st, true);
+    MD_HIP(launch_integrate(c.g, INT_KE, a, s), "prepare/ke");
+    MD_HIP(launch_reduce_energy((double*)((char*)st->ws + c.W.part_a), c.W.nbf,
+                                (double*)((char*)st->ws + c.W.part_b), c.W.nbi, st->energy, nullptr, s),
+           "prepare/reduce");
+    if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
+    if ((rc = check_status(f, st)) != MD_OK) return rc;
+    st->phase = 0;
+    return MD_OK;
+}
+
+int md_energy(const md_params* p, md_state* st, double* out, hipStream_t s)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if ((rc = check_state(c, p, st)) != MD_OK) return rc;
+    if (!out) return fail(MD_ERR_ARG, "out is NULL");
+    if (!st->list_valid) return fail(MD_ERR_ARG, "state has no valid pair list (call md_prepare)");
+    Timer T;
+    timer_begin(T, nullptr);
+    if ((rc = force_eval(c, p, st, true, T, s)) != MD_OK) return rc;
+    IntArgs a = int_args(c, p, st, true);
+    MD_HIP(launch_integrate(c.g, INT_KE, a, s), "energy/ke");
+    MD_HIP(launch_reduce_energy((double*)((char*)st->ws + c.W.part_a), c.W.nbf,
+                                (double*)((char*)st->ws + c.W.part_b), c.W.nbi, st->energy, out, s),
+           "energy/reduce");
+    return MD_OK;
+}
+
+int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_every, double* energy_log,
+            hipStream_t s)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if ((rc = check_state(c, p, st)) != MD_OK) return rc;
+    if (!(p->dt > 0.0)) return fail(MD_ERR_ARG, "dt must be > 0");
+    if (nsteps < 0) return fail(MD_ERR_ARG, "nsteps must be >= 0");
+    // forces must exist for the current positions (md_prepare); a list that
+    // was invalidated since (re-sized by the caller) is rebuilt before use
+    if (st->rebuilds == 0 || st->phase == 2)
+        return fail(MD_ERR_ARG, "state not prepared (call md_prepare)");
+    if (nsteps == 0) return MD_OK;
+    const double half_skin = 0.5 * (p->rs - p->rc);
+    const double thr2 = half_skin * half_skin;
+    Timer T;
+    timer_begin(T, st->timers);
+    double* part_pw = (double*)((char*)st->ws + c.W.part_a);
+    double* part_ke = (double*)((char*)st->ws + c.W.part_b);
+    int64_t k_log = 0;
+    int64_t done = 0;
+    bool need_drift = st->phase == 0;
+    while (done < nsteps) {
+        const int64_t step_no = st->step + 1;
+        const bool sample = sample_every > 0 && (step_no % sample_every) == 0;
+        if (need_drift) {
+            // first half kick and drift of this step (the previous step ended
+            // with a completed kick, or this is the first step of the call)
+            MD_HIP(launch_fill_i32((int32_t*)(st->energy + 4), 0, 2, s), "step/maxd2");
+            tick(T, MD_T_INTEGRATE, 0, s);
+            MD_HIP(launch_integrate(c.g, INT_KD, int_args(c, p, st, false), s), "step/kd");
+            tick(T, MD_T_INTEGRATE, 1, s);
+            st->phase = 1;
+        }
+        int64_t f[8];
+        if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
+        timer_collect(T);
+        double maxd2;
+        std::memcpy(&maxd2, &f[7], sizeof(double));
+        if (!st->list_valid || maxd2 > thr2) {
+            if ((rc = rebuild(c, p, st, true, T, s)) != MD_OK) return rc;
+            st->rebuilds += 1;
+            if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
+            timer_collect(T);
+            if (f[2] != 0) {
+                st->list_valid = 0;
+                return check_status(f, st);
+            }
+            st->list_valid = 1;
+        }
+        if ((rc = force_eval(c, p, st, sample, T, s)) != MD_OK) return rc;
+        // second half kick of this step, fused with the next step's first half
+        // kick and drift unless this is the last step of the call
+        const bool last = done + 1 == nsteps;
+        IntArgs a = int_args(c, p, st, sample);
+        MD_HIP(launch_fill_i32((int32_t*)(st->energy + 4), 0, 2, s), "step/maxd2");
+        tick(T, MD_T_INTEGRATE, 0, s);
+        MD_HIP(launch_integrate(c.g, last ? INT_K : INT_KKD, a, s), "step/kick");
+        tick(T, MD_T_INTEGRATE, 1, s);
+        if (sample) {
+            tick(T, MD_T_REDUCE, 0, s);
+            MD_HIP(launch_reduce_energy(part_pw, c.W.nbf, part_ke, c.W.nbi, st->energy,
+                                        energy_log ? energy_log + 4 * k_log : nullptr, s),
+                   "step/reduce");
+            tick(T, MD_T_REDUCE, 1, s);
+            ++k_log;
+        }
+        st->step += 1;
+        ++done;
+        st->phase = last ? 0 : 1;
+        need_drift = false;
+        if (last) {
+            if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
+            timer_collect(T);
+            if ((rc = check_status(f, st)) != MD_OK) return rc;
+        } else if (f[6] & 1) {
+            return check_status(f, st);
+        }
+    }
+    return MD_OK;
+}
+
+}  // extern "C"

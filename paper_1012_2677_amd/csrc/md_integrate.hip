@@ -1,0 +1,286 @@
+// Velocity-Verlet integration (Sec. 4.5: second-order symplectic, periodic on
+// all axes) with the half-skin rebuild trigger (Sec. 2.3, search-length figure),
+// and the fixed-order FP64 reductions of energy and list statistics.
+//
+// One thread per slot streams pos, vel, force and pos_ref (SoA, coalesced);
+// the kernel is bound by HBM bandwidth.  Between two force evaluations the
+// two half kicks of consecutive steps are applied in one pass (kick, kick,
+// drift), keeping them as two separate roundings so the result is the same as
+// two separate passes.  Block maxima of the squared displacement since the last
+// build go to one atomic max (exact, order independent); kinetic-energy block
+// sums go to a partials array reduced later in a fixed order (deterministic).
+
+#include "md_internal.h"
+
+namespace md {
+
+__device__ __forceinline__ double wrap_coord(double x, double L, double invL)
+{
+    double y = x - L * floor(x * invL);
+    if (y >= L) y -= L;
+    if (y < 0.0) y += L;
+    return y;
+}
+
+__device__ __forceinline__ float local_coord_i(double x, int c, double cs, double L, double invL)
+{
+    double l = x - (double)c * cs;
+    l -= L * rint((l - 0.5 * cs) * invL);
+    return (float)l;
+}
+
+template <int MODE, bool KE, bool MIXED>
+__global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = g.n;
+    const bool valid = i < n;
+    const double h = 0.5 * a.dt;
+    double ke = 0.0, d2 = 0.0;
+    if (valid) {
+        double vx = a.vel[i], vy = a.vel[n + i], vz = a.vel[2 * n + i];
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        if (MODE != INT_KE) {
+            if (MIXED) {
+                const float* F = (const float*)a.force;
+                fx = F[i];
+                fy = F[n + i];
+                fz = F[2 * n + i];
+            } else {
+                const double* F = (const double*)a.force;
+                fx = F[i];
+                fy = F[n + i];
+                fz = F[2 * n + i];
+            }
+            vx = vx + h * fx;
+            vy = vy + h * fy;
+            vz = vz + h * fz;
+        }
+        if (KE) ke = vx * vx + vy * vy + vz * vz;
+        if (MODE == INT_KKD) {
+            vx = vx + h * fx;
+            vy = vy + h * fy;
+            vz = vz + h * fz;
+        }
+        if (MODE == INT_KD || MODE == INT_KKD) {
+            double4* P = (double4*)a.pos;
+            double4 p = P[i];
+            p.x = wrap_coord(p.x + a.dt * vx, g.L[0], g.invL[0]);
+            p.y = wrap_coord(p.y + a.dt * vy, g.L[1], g.invL[1]);
+            p.z = wrap_coord(p.z + a.dt * vz, g.L[2], g.invL[2]);
+            P[i] = p;
+            double ex = p.x - a.pos_ref[i], ey = p.y - a.pos_ref[n + i], ez = p.z - a.pos_ref[2 * n + i];
+            ex -= g.L[0] * rint(ex * g.invL[0]);
+            ey -= g.L[1] * rint(ey * g.invL[1]);
+            ez -= g.L[2] * rint(ez * g.invL[2]);
+            d2 = ex * ex + ey * ey + ez * ez;
+            if (MIXED) {
+                const int32_t c = a.cell_xyz[i];
+                ((float4*)a.pos32)[i] =
+                    make_float4(local_coord_i(p.x, c & 1023, g.cs[0], g.L[0], g.invL[0]),
+                                local_coord_i(p.y, (c >> 10) & 1023, g.cs[1], g.L[1], g.invL[1]),
+                                local_coord_i(p.z, (c >> 20) & 1023, g.cs[2], g.L[2], g.invL[2]), 0.0f);
+            }
+        }
+        if (MODE != INT_KE) {
+            a.vel[i] = vx;
+            a.vel[n + i] = vy;
+            a.vel[2 * n + i] = vz;
+        }
+    }
+    __shared__ double s_v[kStreamBlock / 64];
+    if (MODE == INT_KD || MODE == INT_KKD) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) d2 = fmax(d2, __shfl_xor(d2, o, 64));
+        if ((threadIdx.x & 63) == 0) s_v[threadIdx.x >> 6] = d2;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = 0.0;
+#pragma unroll
+            for (int w = 0; w < kStreamBlock / 64; ++w) m = fmax(m, s_v[w]);
+            atomicMax(a.max_d2, (unsigned long long)__double_as_longlong(m));
+        }
+        __syncthreads();
+    }
+    if (KE) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) ke += __shfl_xor(ke, o, 64);
+        if ((threadIdx.x & 63) == 0) s_v[threadIdx.x >> 6] = ke;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < kStreamBlock / 64; ++w) s += s_v[w];
+            a.part_ke[blockIdx.x] = 0.5 * s;
+        }
+    }
+}
+
+template <int MODE, bool KE>
+static void launch_int_mode(const Geo& g, const IntArgs& a, hipStream_t s)
+{
+    const dim3 grid((unsigned)ceil_div(g.n, kStreamBlock)), block(kStreamBlock);
+    if (a.precision == MD_MIXED)
+        hipLaunchKernelGGL((k_integrate<MODE, KE, true>), grid, block, 0, s, g, a);
+    else
+        hipLaunchKernelGGL((k_integrate<MODE, KE, false>), grid, block, 0, s, g, a);
+}
+
+hipError_t launch_integrate(const Geo& g, IntMode mode, const IntArgs& a, hipStream_t s)
+{
+    const bool ke = a.part_ke != nullptr;
+    switch (mode) {
+    case INT_KD: launch_int_mode<INT_KD, false>(g, a, s); break;
+    case INT_KKD:
+        if (ke) launch_int_mode<INT_KKD, true>(g, a, s);
+        else launch_int_mode<INT_KKD, false>(g, a, s);
+        break;
+    case INT_K:
+        if (ke) launch_int_mode<INT_K, true>(g, a, s);
+        else launch_int_mode<INT_K, false>(g, a, s);
+        break;
+    case INT_KE: launch_int_mode<INT_KE, true>(g, a, s); break;
+    }
+    return hipGetLastError();
+}
+
+// ---- fixed-order reductions -------------------------------------------------
+__device__ __forceinline__ double block_sum_1024(double v)
+{
+    __shared__ double s_w[kReduceBlock / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kReduceBlock / 64; ++w) t += s_w[w];
+    __syncthreads();
+    return t;
+}
+
+// energy[0..3] = (KE, PE, W, KE + PE); also into log_row when given.
+__global__ __launch_bounds__(kReduceBlock) void k_reduce_energy(const double* __restrict__ part_pw, int64_t nbf,
+                                                                const double* __restrict__ part_ke, int64_t nbi,
+                                                                double* __restrict__ energy,
+                                                                double* __restrict__ log_row)
+{
+    double pe = 0.0, w = 0.0, ke = 0.0;
+    for (int64_t b = threadIdx.x; b < nbf; b += kReduceBlock) {
+        pe += part_pw[2 * b];
+        w += part_pw[2 * b + 1];
+    }
+    for (int64_t b = threadIdx.x; b < nbi; b += kReduceBlock) ke += part_ke[b];
+    pe = block_sum_1024(pe);
+    w = block_sum_1024(w);
+    ke = block_sum_1024(ke);
+    if (threadIdx.x == 0) {
+        energy[0] = ke;
+        energy[1] = pe;
+        energy[2] = w;
+        energy[3] = ke + pe;
+        if (log_row) {
+            log_row[0] = ke;
+            log_row[1] = pe;
+            log_row[2] = w;
+            log_row[3] = ke + pe;
+        }
+    }
+}
+
+hipError_t launch_reduce_energy(const double* part_pw, int64_t nbf, const double* part_ke, int64_t nbi,
+                                double* energy, double* log_row, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_energy, dim3(1), dim3(kReduceBlock), 0, s, part_pw, nbf, part_ke, nbi,
+                       energy, log_row);
+    return hipGetLastError();
+}
+
+// out2[k] = scale_k * sum_b part[2b + k]
+__global__ __launch_bounds__(kReduceBlock) void k_reduce_pair(const double* __restrict__ part, int64_t nb,
+                                                              double s0, double s1, double* __restrict__ out2)
+{
+    double a = 0.0, b = 0.0;
+    for (int64_t k = threadIdx.x; k < nb; k += kReduceBlock) {
+        a += part[2 * k];
+        b += part[2 * k + 1];
+    }
+    a = block_sum_1024(a);
+    b = block_sum_1024(b);
+    if (threadIdx.x == 0) {
+        out2[0] = s0 * a;
+        out2[1] = s1 * b;
+    }
+}
+
+hipError_t launch_reduce_pair(const double* part, int64_t nb, double scale0, double scale1, double* out2,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_pair, dim3(1), dim3(kReduceBlock), 0, s, part, nb, scale0, scale1, out2);
+    return hipGetLastError();
+}
+
+// status[0] = total entries, status[1] = largest cell block (stride needed)
+__global__ __launch_bounds__(kReduceBlock) void k_list_stats(const int32_t* __restrict__ rows, int64_t ncell,
+                                                             int64_t* __restrict__ status)
+{
+    __shared__ long long s_sum[kReduceBlock / 64], s_max[kReduceBlock / 64];
+    long long sum = 0, mx = 0;
+    for (int64_t c = threadIdx.x; c < ncell; c += kReduceBlock) {
+        const long long r = rows[c];
+        sum += r;
+        mx = r > mx ? r : mx;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sum += __shfl_xor(sum, o, 64);
+        const long long y = __shfl_xor(mx, o, 64);
+        mx = y > mx ? y : mx;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_sum[threadIdx.x >> 6] = sum;
+        s_max[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long ts = 0, tm = 0;
+        for (int w = 0; w < kReduceBlock / 64; ++w) {
+            ts += s_sum[w];
+            tm = s_max[w] > tm ? s_max[w] : tm;
+        }
+        status[0] = ts;
+        status[1] = tm;
+    }
+}
+
+hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t stride, int64_t* status,
+                             hipStream_t s)
+{
+    (void)stride;
+    hipLaunchKernelGGL(k_list_stats, dim3(1), dim3(kReduceBlock), 0, s, cell_rows, ncell, status);
+    return hipGetLastError();
+}
+
+__global__ void k_gather_flags(const int64_t* __restrict__ status, const int64_t* __restrict__ err,
+                               const int64_t* __restrict__ flags, const double* __restrict__ energy,
+                               int64_t* __restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    out[0] = status[0];
+    out[1] = status[1];
+    out[2] = status[2];
+    out[3] = status[3];
+    out[4] = err[0];
+    out[5] = err[1];
+    out[6] = flags[0];
+    out[7] = __double_as_longlong(energy[4]);
+}
+
+hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags,
+                               const double* energy, int64_t* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_flags, dim3(1), dim3(64), 0, s, status, err, flags, energy, out);
+    return hipGetLastError();
+}
+
+}  // namespace md

@@ -1,0 +1,183 @@
+// Internal declarations of the gfx950 LJ hot path: launch geometry, workspace
+// layout, kernel argument blocks and the launchers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "md.h"
+
+namespace md {
+
+// ---------------------------------------------------------------------------
+// Launch configuration
+// ---------------------------------------------------------------------------
+constexpr int kStreamBlock = 256;        // streaming kernels (label, integrate, ...)
+constexpr int kScanItems = 1024;         // items per block of the three-phase scan
+constexpr int kForceBlock = 256;         // force / adjoint kernels
+#ifndef MD_LANES_PER_KEY
+#define MD_LANES_PER_KEY 8
+#endif
+#ifndef MD_FORCE_UNROLL
+#define MD_FORCE_UNROLL 4
+#endif
+constexpr int kLanesPerKey = MD_LANES_PER_KEY;   // lanes cooperating on one key's row
+constexpr int kForceUnroll = MD_FORCE_UNROLL;    // row entries in flight per lane
+constexpr int kKeysPerBlock = kForceBlock / kLanesPerKey;
+constexpr int kBuildChunks = 8;          // candidates held in registers: 8 x 64
+constexpr int kReduceBlock = 1024;
+
+constexpr uint32_t kSlotMask = (1u << 27) - 1u;
+constexpr int kCodeShift = 27;
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// Geometry derived on the host from md_params (FP64, computed once)
+// ---------------------------------------------------------------------------
+struct Geo {
+    int64_t n;
+    int32_t nc[3];
+    int64_t ncell;
+    double L[3];
+    double invL[3];   // 1 / L
+    double inv[3];    // nc / L   (cell label scale)
+    double cs[3];     // L / nc   (cell side)
+    int32_t exact_all;  // some axis has fewer than 5 cells: always take minimum images
+};
+
+// LJ coefficients in the form the kernels evaluate:
+//   g(r)  = r^-2 r^-6 (A r^-6 - B) - C8                 (= -V'(r)/r)
+//   V(r)  = r^-6 (A4 r^-6 - B4) + C2 r^2 + C0
+//   g'(s) = dg/d(r^2) = r^-4 r^-6 (-7 A r^-6 + 4 B)
+// with A = 48 eps sig^12, B = 24 eps sig^6, C8 = 8 eps c2 / sig^2,
+//      A4 = 4 eps sig^12, B4 = 4 eps sig^6, C2 = 4 eps c2 / sig^2, C0 = 4 eps c0.
+struct LJ {
+    double rc2;
+    double A, B, C8;
+    double A4, B4, C2, C0;
+    double eps, sigma;
+    double Cs;        // sigma * dC8/dsigma
+    double rc6i, rc8i, rc12i, rc14i;  // rc^-6, rc^-8, rc^-12, rc^-14
+};
+
+Geo make_geo(const md_params& p, const int32_t nc[3]);
+LJ make_lj(const md_params& p);
+
+// ---------------------------------------------------------------------------
+// Workspace layout (all offsets 256-byte aligned)
+// ---------------------------------------------------------------------------
+struct WsLayout {
+    size_t rank;       // int32[n]       atomic ranks during binning
+    size_t bsum;       // int32[nbs+1]   scan block sums
+    size_t cell_rows;  // int32[ncell]   entries per cell block (pair list)
+    size_t part_a;     // double[2*nbf]  per-block partial sums (force kernels)
+    size_t part_b;     // double[nbi]    per-block partial sums (streaming kernels)
+    size_t pos32;      // float4[n]      mixed-mode local coordinates (md_forces)
+    size_t scal;       // double[16]     small device scalars
+    size_t total;
+    int64_t nbs;       // scan blocks
+    int64_t nbf;       // force-kernel blocks
+    int64_t nbi;       // streaming-kernel blocks
+};
+WsLayout ws_layout(int64_t n, int64_t ncell);
+
+// ---------------------------------------------------------------------------
+// Small device helpers
+// ---------------------------------------------------------------------------
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD one
+// contiguous range of logical blocks so neighbouring tiles share an L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
+{
+    const int64_t q = nb >> 3, r = nb & 7;
+    const int64_t x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+__device__ __forceinline__ int cell_coord(double x, double inv, int n)
+{
+    int c = (int)(x * inv);
+    c = c > n - 1 ? n - 1 : c;
+    return c < 0 ? 0 : c;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// 1/x in FP64 from the hardware reciprocal estimate and two Newton steps.
+__device__ __forceinline__ double rcp64(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (each returns hipGetLastError() of its launches)
+// ---------------------------------------------------------------------------
+// md_cells.hip
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
+hipError_t launch_bin(const Geo& g, const double* pos, const md_cells& cells, void* ws,
+                      const WsLayout& L, int64_t* err_flags, hipStream_t s);
+hipError_t launch_resort(const Geo& g, const int32_t* order, const double* pos, const double* vel,
+                         const int32_t* id, double* pos_alt, double* vel_alt, int32_t* id_alt,
+                         double* pos_ref, float* pos32, int32_t* cell_of, int32_t* cell_xyz,
+                         hipStream_t s);
+hipError_t launch_ref_copy(const Geo& g, const double* pos, const int32_t* cell_xyz, double* pos_ref,
+                           float* pos32, hipStream_t s);
+
+// md_pairlist.hip
+hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cells& cells,
+                        const md_pairlist& list, void* ws, const WsLayout& L, hipStream_t s);
+
+// md_forces.hip
+struct ForceOut {
+    void* force;        // [3][n] double or float
+    double* part;       // per-block (PE, W) partials, or nullptr
+    int64_t* flags;     // [0] |= 1 on a non-finite force
+};
+hipError_t launch_forces(const Geo& g, const LJ& lj, int precision, const double* pos,
+                         const float* pos32, const int32_t* cell_xyz, const md_pairlist& list,
+                         const ForceOut& out, hipStream_t s);
+
+// md_integrate.hip
+enum IntMode { INT_KD = 0, INT_KKD = 1, INT_K = 2, INT_KE = 3 };
+struct IntArgs {
+    double* pos;
+    double* vel;
+    const void* force;
+    const double* pos_ref;
+    float* pos32;
+    const int32_t* cell_xyz;
+    double* part_ke;                // per-block KE partials (or nullptr)
+    unsigned long long* max_d2;     // atomic max of squared displacement bits
+    double dt;
+    int precision;
+};
+hipError_t launch_integrate(const Geo& g, IntMode mode, const IntArgs& a, hipStream_t s);
+hipError_t launch_reduce_energy(const double* part_pw, int64_t nbf, const double* part_ke,
+                                int64_t nbi, double* energy, double* log_row, hipStream_t s);
+hipError_t launch_reduce_pair(const double* part, int64_t nb, double scale0, double scale1,
+                              double* out2, hipStream_t s);
+hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags,
+                               const double* energy, int64_t* out, hipStream_t s);
+hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t stride,
+                             int64_t* status, hipStream_t s);
+
+// md_adjoint.hip
+hipError_t launch_hvp(const Geo& g, const LJ& lj, const double* pos, const int32_t* cell_xyz,
+                      const md_pairlist& list, const double* u, double* Hu, double* part,
+                      hipStream_t s);
+hipError_t launch_param_grad(const Geo& g, const LJ& lj, const double* pos,
+                             const int32_t* cell_xyz, const md_pairlist& list, double* part,
+                             hipStream_t s);
+
+}  // namespace md

@@ -1,0 +1,251 @@
+// Pair-list construction (Sec. 2.3 bookkeeping with search length rs; Sec. 2.4
+// key-sorted list), one 64-lane wavefront per cell.
+//
+// The wave stages the particles of the 27 surrounding cells (~300 at
+// rho = 0.5) in its registers, one candidate per lane per 64-chunk.  It then
+// walks the keys of its own cell: each lane tests its candidates against the
+// key with the exact FP64 predicate, a ballot gives the passing lanes, and the
+// prefix popcount below each lane gives its output position, so every row is
+// written compactly in candidate order (stencil code, then ascending slot)
+// with no atomics.  Rows of one cell are packed one after another into the
+// cell's block of the list; the block base is the cell id times a fixed stride,
+// so cells never have to wait for each other.
+//
+// The work is ALU bound (about 300 FP64 distance tests per particle).
+
+#include "md_internal.h"
+
+namespace md {
+
+struct BuildArgs {
+    const double4* pos;
+    const int32_t* start;
+    const int32_t* count;
+    const int32_t* order;   // nullptr when the slots are already in cell order
+    int32_t nc[3];
+    int64_t ncell;
+    double L[3], invL[3];
+    double rs2;
+    int32_t exact_all;
+    int64_t stride;
+    uint32_t* nbr;
+    int64_t* offsets;
+    int32_t* counts;
+    int32_t* cell_rows;
+    int64_t* status;
+};
+
+// r^2 of the pinned predicate: d = q_j - q_i, optional minimum image,
+// r2 = fma(dz, dz, fma(dy, dy, dx * dx)).
+template <bool MINIMG>
+__device__ __forceinline__ double pair_r2(const BuildArgs& a, double xj, double yj, double zj, double xi,
+                                          double yi, double zi)
+{
+    double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+    if (MINIMG) {
+        dx = dx - a.L[0] * rint(dx * a.invL[0]);
+        dy = dy - a.L[1] * rint(dy * a.invL[1]);
+        dz = dz - a.L[2] * rint(dz * a.invL[2]);
+    }
+    return __builtin_fma(dz, dz, __builtin_fma(dy, dy, __dmul_rn(dx, dx)));
+}
+
+// Row header of one key.  When the cell block overflows, the row is clipped to
+// the entries actually stored, so an invalid (overflowed) list still only
+// references written, in-range entries.
+__device__ __forceinline__ void write_row(const BuildArgs& a, int32_t kslot, int64_t base, int64_t used,
+                                          int64_t wpos)
+{
+    const int64_t start = used < a.stride ? used : a.stride;
+    const int64_t room = a.stride - start;
+    a.offsets[kslot] = base + start;
+    a.counts[kslot] = (int32_t)(wpos < room ? wpos : room);
+}
+
+// Keys of one cell against candidates held in registers (at most NCH*64).
+template <bool MINIMG, int NCH>
+__device__ __forceinline__ int64_t rows_from_registers(const BuildArgs& a, int64_t base, int T, int own_start,
+                                                      int own_cnt, const double* cx, const double* cy,
+                                                      const double* cz, const uint32_t* meta)
+{
+    int64_t used = 0;
+    for (int kk = 0; kk < own_cnt; ++kk) {
+        const int kidx = own_start + kk;
+        const int32_t kslot = a.order ? a.order[kidx] : kidx;
+        const double4 kp = a.pos[kslot];
+        int64_t wpos = 0;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            if (ch * 64 < T) {
+                const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
+                const bool pass = meta[ch] != 0xFFFFFFFFu && r2 < a.rs2 &&
+                                  (int32_t)(meta[ch] & kSlotMask) != kslot;
+                const uint64_t m = __ballot(pass);
+                if (pass) {
+                    const int64_t w = used + wpos + mbcnt64(m);
+                    if (w < a.stride) a.nbr[base + w] = meta[ch];
+                }
+                wpos += __popcll(m);
+            }
+        }
+        if (lane_id() == 0) write_row(a, kslot, base, used, wpos);
+        used += wpos;
+    }
+    return used;
+}
+
+// Same rows, candidates re-read from memory for every key (neighbourhoods with
+// more than NCH*64 particles: never at liquid densities, kept for generality).
+template <bool MINIMG>
+__device__ int64_t rows_from_memory(const BuildArgs& a, int64_t base, int T, int own_start, int own_cnt,
+                                    const int* s_pref, const int* s_nstart)
+{
+    int64_t used = 0;
+    for (int kk = 0; kk < own_cnt; ++kk) {
+        const int kidx = own_start + kk;
+        const int32_t kslot = a.order ? a.order[kidx] : kidx;
+        const double4 kp = a.pos[kslot];
+        int64_t wpos = 0;
+        for (int t0 = 0; t0 < T; t0 += 64) {
+            const int t = t0 + (int)lane_id();
+            bool pass = false;
+            uint32_t meta = 0;
+            if (t < T) {
+                int q = 0;
+                while (s_pref[q + 1] <= t) ++q;
+                const int idx = s_nstart[q] + (t - s_pref[q]);
+                const int32_t slot = a.order ? a.order[idx] : idx;
+                const double4 p = a.pos[slot];
+                const double r2 = pair_r2<MINIMG>(a, p.x, p.y, p.z, kp.x, kp.y, kp.z);
+                pass = r2 < a.rs2 && slot != kslot;
+                meta = (uint32_t)slot | ((uint32_t)q << kCodeShift);
+            }
+            const uint64_t m = __ballot(pass);
+            if (pass) {
+                const int64_t w = used + wpos + mbcnt64(m);
+                if (w < a.stride) a.nbr[base + w] = meta;
+            }
+            wpos += __popcll(m);
+        }
+        if (lane_id() == 0) write_row(a, kslot, base, used, wpos);
+        used += wpos;
+    }
+    return used;
+}
+
+template <int NCH>
+__global__ __launch_bounds__(64) void k_build(BuildArgs a)
+{
+    const int64_t c = xcd_remap(blockIdx.x, gridDim.x);
+    if (c >= a.ncell) return;
+    const int lane = (int)threadIdx.x;
+    const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
+    const int cz = (int)(c % nz);
+    const int cy = (int)((c / nz) % ny);
+    const int cx = (int)(c / ((int64_t)nz * ny));
+
+    __shared__ int s_nstart[27];
+    __shared__ int s_pref[28];
+    int cnt = 0, st = 0;
+    if (lane < 27) {
+        int ax = cx + lane / 9 - 1, ay = cy + (lane / 3) % 3 - 1, az = cz + lane % 3 - 1;
+        ax += ax < 0 ? nx : 0;
+        ax -= ax >= nx ? nx : 0;
+        ay += ay < 0 ? ny : 0;
+        ay -= ay >= ny ? ny : 0;
+        az += az < 0 ? nz : 0;
+        az -= az >= nz ? nz : 0;
+        const int64_t nb = ((int64_t)ax * ny + ay) * nz + az;
+        st = a.start[nb];
+        cnt = a.count[nb];
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane < 27) {
+        s_nstart[lane] = st;
+        s_pref[lane + 1] = incl;
+    }
+    if (lane == 0) s_pref[0] = 0;
+    __syncthreads();
+
+    const int T = s_pref[27];
+    const int own_start = s_nstart[13];
+    const int own_cnt = s_pref[14] - s_pref[13];
+    const bool minimg = a.exact_all || cx == 0 || cx == nx - 1 || cy == 0 || cy == ny - 1 || cz == 0 ||
+                        cz == nz - 1;
+    const int64_t base = c * a.stride;
+    int64_t used;
+
+    if (T <= NCH * 64) {
+        double px[NCH], py[NCH], pz[NCH];
+        uint32_t meta[NCH];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int t = ch * 64 + lane;
+            px[ch] = py[ch] = pz[ch] = 0.0;
+            meta[ch] = 0xFFFFFFFFu;
+            if (t < T) {
+                // neighbour cell holding candidate t: binary search in the prefix
+                int lo = 0, hi = 27;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_pref[mid] <= t) lo = mid; else hi = mid;
+                }
+                const int idx = s_nstart[lo] + (t - s_pref[lo]);
+                const int32_t slot = a.order ? a.order[idx] : idx;
+                const double4 p = a.pos[slot];
+                px[ch] = p.x;
+                py[ch] = p.y;
+                pz[ch] = p.z;
+                meta[ch] = (uint32_t)slot | ((uint32_t)lo << kCodeShift);
+            }
+        }
+        used = minimg ? rows_from_registers<true, NCH>(a, base, T, own_start, own_cnt, px, py, pz, meta)
+                      : rows_from_registers<false, NCH>(a, base, T, own_start, own_cnt, px, py, pz, meta);
+    } else {
+        used = minimg ? rows_from_memory<true>(a, base, T, own_start, own_cnt, s_pref, s_nstart)
+                      : rows_from_memory<false>(a, base, T, own_start, own_cnt, s_pref, s_nstart);
+    }
+    if (lane == 0) {
+        a.cell_rows[c] = used > 0x7FFFFFFF ? 0x7FFFFFFF : (int32_t)used;
+        if (used > a.stride) atomicOr((unsigned long long*)&a.status[2], 1ull);
+    }
+}
+
+hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cells& cells,
+                        const md_pairlist& list, void* ws, const WsLayout& L, hipStream_t s)
+{
+    BuildArgs a;
+    a.pos = (const double4*)pos;
+    a.start = cells.start;
+    a.count = cells.count;
+    a.order = cells.sorted ? nullptr : cells.order;
+    for (int k = 0; k < 3; ++k) {
+        a.nc[k] = g.nc[k];
+        a.L[k] = g.L[k];
+        a.invL[k] = g.invL[k];
+    }
+    a.ncell = g.ncell;
+    a.rs2 = rs * rs;
+    a.exact_all = g.exact_all;
+    a.stride = list.cell_stride;
+    a.nbr = list.nbr;
+    a.offsets = list.offsets;
+    a.counts = list.counts;
+    a.cell_rows = (int32_t*)((char*)ws + L.cell_rows);
+    a.status = list.status;
+    // status[2] (overflow) is cleared by the statistics kernel of the previous
+    // build or by the caller; clear it here on the stream before the build.
+    hipError_t e = launch_fill_i32((int32_t*)list.status, 0, 8, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_build<kBuildChunks>, dim3((unsigned)g.ncell), dim3(64), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_list_stats(a.cell_rows, g.ncell, list.cell_stride, list.status, s);
+}
+
+}  // namespace md

@@ -1,0 +1,271 @@
+"""Device buffers (torch, used only for memory and streams) around the C ABI.
+
+`Grid` and `PairList` own the arrays of md_cells / md_pairlist; `Engine` owns a
+whole md_state and runs md_prepare / md_step.  Nothing here computes the
+method: every step runs in the HIP library.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def make_params(n, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precision="fp64",
+                resort_every=1) -> A.MdParams:
+    p = A.MdParams()
+    p.n = int(n)
+    b = np.broadcast_to(np.asarray(box, dtype=np.float64), (3,))
+    for k in range(3):
+        p.box[k] = float(b[k])
+    p.eps, p.sigma, p.rc, p.rs, p.dt = float(eps), float(sigma), float(rc), float(rs), float(dt)
+    p.precision = A.MD_MIXED if precision in ("mixed", A.MD_MIXED) else A.MD_FP64
+    p.resort_every = int(resort_every)
+    return p
+
+
+def stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Workspace:
+    def __init__(self, params: A.MdParams, device):
+        self.nbytes = A.md_workspace_bytes(params)
+        self.buf = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
+
+    @property
+    def ptr(self) -> int:
+        return self.buf.data_ptr()
+
+
+class Grid:
+    """md_cells arrays for n particles."""
+
+    def __init__(self, params: A.MdParams, device):
+        self.ncell = A.md_cell_dims(params)
+        nc = int(np.prod(self.ncell))
+        n = params.n
+        i32 = dict(dtype=torch.int32, device=device)
+        self.cell_of = torch.empty(n, **i32)
+        self.cell_xyz = torch.empty(n, **i32)
+        self.count = torch.empty(nc, **i32)
+        self.start = torch.empty(nc + 1, **i32)
+        self.order = torch.empty(n, **i32)
+        self.c = A.MdCells()
+        self.fill(self.c)
+
+    def fill(self, c: A.MdCells):
+        for k in range(3):
+            c.ncell[k] = self.ncell[k]
+        c.cell_of = self.cell_of.data_ptr()
+        c.cell_xyz = self.cell_xyz.data_ptr()
+        c.count = self.count.data_ptr()
+        c.start = self.start.data_ptr()
+        c.order = self.order.data_ptr()
+
+
+def default_cell_stride(params: A.MdParams, ncell) -> int:
+    """Entries reserved per cell: twice the mean (cell occupancy times the mean
+    number of partners within rs) plus 64, rounded up to 64."""
+    vol = params.box[0] * params.box[1] * params.box[2]
+    rho = params.n / vol
+    per_cell = params.n / float(np.prod(ncell))
+    mean = per_cell * rho * (4.0 / 3.0) * math.pi * params.rs ** 3
+    return int(64 * math.ceil((2.0 * mean + 64.0) / 64.0))
+
+
+class PairList:
+    """md_pairlist arrays; the capacity is ncell * cell_stride entries."""
+
+    def __init__(self, params: A.MdParams, ncell, device, cell_stride: int | None = None):
+        n = params.n
+        self.ncell = ncell
+        self.device = device
+        self.offsets = torch.empty(n, dtype=torch.int64, device=device)
+        self.counts = torch.empty(n, dtype=torch.int32, device=device)
+        self.status = torch.zeros(4, dtype=torch.int64, device=device)
+        self.l = A.MdPairlist()
+        self.resize(cell_stride or default_cell_stride(params, ncell))
+
+    def resize(self, cell_stride: int):
+        self.cell_stride = int(cell_stride)
+        cap = int(np.prod(self.ncell)) * self.cell_stride
+        self.nbr = None
+        self.nbr = torch.empty(cap, dtype=torch.int32, device=self.device)
+        self.fill(self.l)
+
+    def fill(self, l: A.MdPairlist):
+        l.offsets = self.offsets.data_ptr()
+        l.counts = self.counts.data_ptr()
+        l.nbr = self.nbr.data_ptr()
+        l.cell_stride = self.cell_stride
+        l.capacity = self.nbr.numel()
+        l.status = self.status.data_ptr()
+
+    def grow_for(self, needed: int):
+        self.resize(int(64 * math.ceil(1.25 * needed / 64.0)))
+
+    def rows(self):
+        """Host copy of the list: (offsets, counts, entries) as numpy arrays."""
+        return (self.offsets.cpu().numpy(), self.counts.cpu().numpy(), self.nbr.cpu().numpy().view(np.uint32))
+
+
+class Engine:
+    """One simulation state on one GPU.
+
+    pos, vel: (N, 3) arrays (any array type numpy accepts), positions in
+    [0, L)^3.  precision: "fp64" or "mixed".  resort_every: re-sort the particle
+    arrays into cell order at every k-th rebuild (0 = never).
+    """
+
+    def __init__(self, pos, vel, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precision="fp64",
+                 resort_every=1, device="cuda", cell_stride=None, timers=False):
+        pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64))
+        vel = np.ascontiguousarray(np.asarray(vel, dtype=np.float64))
+        n = pos.shape[0]
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.params = make_params(n, box, eps=eps, sigma=sigma, rc=rc, rs=rs, dt=dt, precision=precision,
+                                  resort_every=resort_every)
+        self.n = n
+        self.mixed = self.params.precision == A.MD_MIXED
+        dev = self.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.grid = Grid(self.params, dev)
+        self.plist = PairList(self.params, self.grid.ncell, dev, cell_stride)
+        self.ws = Workspace(self.params, dev)
+        p4 = np.zeros((n, 4))
+        p4[:, :3] = pos
+        self.pos = torch.from_numpy(p4).to(dev)
+        self.vel = torch.from_numpy(np.ascontiguousarray(vel.T)).to(dev)
+        self.id = torch.arange(n, dtype=torch.int32, device=dev)
+        resort = resort_every > 0
+        self.pos_alt = torch.empty_like(self.pos) if resort else None
+        self.vel_alt = torch.empty_like(self.vel) if resort else None
+        self.id_alt = torch.empty_like(self.id) if resort else None
+        self.force = torch.zeros((3, n), dtype=torch.float32 if self.mixed else torch.float64, device=dev)
+        self.pos_ref = torch.empty((3, n), **f64)
+        self.pos32 = torch.empty((n, 4), dtype=torch.float32, device=dev) if self.mixed else None
+        self.energy = torch.zeros(8, **f64)
+        self.flags = torch.zeros(8, dtype=torch.int64, device=dev)
+        self.host_scratch = torch.zeros(16, dtype=torch.int64, pin_memory=True)
+        self.timers = A.MdTimers() if timers else None
+        s = A.MdState()
+        s.pos, s.vel, s.force = _ptr(self.pos), _ptr(self.vel), _ptr(self.force)
+        s.pos_ref, s.pos32, s.id = _ptr(self.pos_ref), _ptr(self.pos32), _ptr(self.id)
+        s.pos_alt, s.vel_alt, s.id_alt = _ptr(self.pos_alt), _ptr(self.vel_alt), _ptr(self.id_alt)
+        self.grid.fill(s.cells)
+        self.plist.fill(s.list)
+        s.energy, s.flags = _ptr(self.energy), _ptr(self.flags)
+        s.host_scratch = _ptr(self.host_scratch)
+        s.ws, s.ws_bytes = self.ws.ptr, self.ws.nbytes
+        s.timers = C_pointer(self.timers)
+        self.state = s
+        self.prepared = False
+
+    # -- pointer bookkeeping after the library swapped re-sort buffers ---------
+    def _sync_pointers(self):
+        s = self.state
+        if self.pos_alt is not None and s.pos == self.pos_alt.data_ptr():
+            self.pos, self.pos_alt = self.pos_alt, self.pos
+            self.vel, self.vel_alt = self.vel_alt, self.vel
+            self.id, self.id_alt = self.id_alt, self.id
+
+    def stream(self) -> int:
+        return stream_handle(self.device)
+
+    def prepare(self):
+        with torch.cuda.device(self.device):
+            for _ in range(4):
+                try:
+                    A.md_prepare(self.params, self.state, self.stream())
+                    break
+                except A.MdError as e:
+                    self._sync_pointers()
+                    if e.code != A.MD_ERR_CAPACITY:
+                        raise
+                    self.plist.grow_for(int(self.plist.status[1].item()))
+                    self.plist.fill(self.state.list)
+            self._sync_pointers()
+        self.prepared = True
+
+    def step(self, nsteps: int, sample_every: int = 0):
+        """Advance nsteps; returns the energy log (k, 4) = (KE, PE, W, E) as numpy,
+        one row for every step number (counted from the start) divisible by
+        sample_every."""
+        if not self.prepared:
+            self.prepare()
+        se = int(sample_every)
+        log = torch.zeros((nsteps // se + 2 if se > 0 else 1, 4), dtype=torch.float64, device=self.device)
+        rows = []
+        done = 0
+        with torch.cuda.device(self.device):
+            while done < nsteps:
+                before = int(self.state.step)
+                err = None
+                try:
+                    A.md_step(self.params, self.state, nsteps - done, se, log.data_ptr(), self.stream())
+                except A.MdError as e:
+                    err = e
+                self._sync_pointers()
+                after = int(self.state.step)
+                if se > 0:
+                    rows.append(log[: after // se - before // se].cpu())
+                done += after - before
+                if err is not None:
+                    if err.code != A.MD_ERR_CAPACITY:
+                        raise err
+                    self.plist.grow_for(int(self.plist.status[1].item()))
+                    self.plist.fill(self.state.list)
+        return torch.cat(rows).numpy() if rows else np.zeros((0, 4))
+
+    def energies(self):
+        """(KE, PE, W, E) at the current state (recomputes forces)."""
+        out = torch.zeros(4, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            A.md_energy(self.params, self.state, out.data_ptr(), self.stream())
+        return out.cpu().numpy()
+
+    # -- views in original particle order ----------------------------------------
+    def _inverse(self):
+        ids = self.id.long()
+        inv = torch.empty_like(ids)
+        inv[ids] = torch.arange(self.n, device=self.device)
+        return inv
+
+    def positions(self) -> np.ndarray:
+        return self.pos[:, :3][self._inverse()].cpu().numpy()
+
+    def velocities(self) -> np.ndarray:
+        return self.vel.T[self._inverse()].cpu().numpy()
+
+    def forces(self) -> np.ndarray:
+        return self.force.T[self._inverse()].double().cpu().numpy()
+
+    @property
+    def step_count(self) -> int:
+        return int(self.state.step)
+
+    @property
+    def rebuilds(self) -> int:
+        return int(self.state.rebuilds)
+
+    def timer_dict(self):
+        if self.timers is None:
+            return {}
+        return {name: (self.timers.ms[k], int(self.timers.launches[k])) for k, name in enumerate(A.TIMER_NAMES)}
+
+
+def C_pointer(t):
+    import ctypes
+
+    return ctypes.pointer(t) if t is not None else ctypes.POINTER(A.MdTimers)()

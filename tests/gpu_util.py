@@ -1,0 +1,118 @@
+"""Test-side helpers that drive the C ABI on the GPU and decode its outputs.
+
+Host logic only (decoding the documented list format); no method arithmetic.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+SLOT_MASK = (1 << 27) - 1
+
+
+def device():
+    return torch.device("cuda", 0)
+
+
+def to_pos4(q: np.ndarray) -> torch.Tensor:
+    p4 = np.zeros((q.shape[0], 4))
+    p4[:, :3] = q
+    return torch.from_numpy(p4).to(device())
+
+
+class Standalone:
+    """Grid + pair list + workspace for standalone entry-point calls."""
+
+    def __init__(self, q, L, *, rs=2.8, rc=2.5, eps=1.0, sigma=1.0, precision="fp64", cell_stride=None):
+        from paper_1012_2677_amd import _abi as A
+        from paper_1012_2677_amd.engine import Grid, PairList, Workspace, make_params, stream_handle
+
+        self.A = A
+        self.q = np.ascontiguousarray(q, dtype=np.float64)
+        self.n = self.q.shape[0]
+        self.params = make_params(self.n, L, eps=eps, sigma=sigma, rc=rc, rs=rs, precision=precision,
+                                  resort_every=0)
+        dev = device()
+        self.grid = Grid(self.params, dev)
+        self.plist = PairList(self.params, self.grid.ncell, dev, cell_stride)
+        self.ws = Workspace(self.params, dev)
+        self.pos = to_pos4(self.q)
+        self.stream = stream_handle(dev)
+
+    def bin(self):
+        self.A.md_bin_cells(self.params, self.pos.data_ptr(), self.grid.c, self.ws.ptr, self.ws.nbytes, self.stream)
+        torch.cuda.synchronize()
+        return (self.grid.cell_of.cpu().numpy(), self.grid.count.cpu().numpy(), self.grid.start.cpu().numpy(),
+                self.grid.order.cpu().numpy(), self.grid.cell_xyz.cpu().numpy())
+
+    def build(self, grow=True):
+        """Build the list; on overflow grow the cell stride and build again
+        (unless grow=False).  Returns the status array."""
+        for _ in range(3):
+            self.A.md_build_pairlist(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, self.ws.ptr,
+                                     self.ws.nbytes, self.stream)
+            torch.cuda.synchronize()
+            status = self.plist.status.cpu().numpy()
+            if status[2] == 0 or not grow:
+                return status
+            self.plist.grow_for(int(status[1]))
+        return status
+
+    def forces(self, energy=True):
+        dt = torch.float32 if self.params.precision == self.A.MD_MIXED else torch.float64
+        F = torch.zeros((3, self.n), dtype=dt, device=device())
+        pw = torch.zeros(2, dtype=torch.float64, device=device())
+        self.A.md_forces(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, F.data_ptr(),
+                         pw.data_ptr() if energy else None, self.ws.ptr, self.ws.nbytes, self.stream)
+        torch.cuda.synchronize()
+        return F.double().cpu().numpy().T.copy(), pw.cpu().numpy()
+
+    def hvp(self, u):
+        ut = torch.from_numpy(np.ascontiguousarray(u.T)).to(device())
+        Hu = torch.zeros_like(ut)
+        dp = torch.zeros(2, dtype=torch.float64, device=device())
+        self.A.md_hvp(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, ut.data_ptr(), Hu.data_ptr(),
+                      dp.data_ptr(), self.ws.ptr, self.ws.nbytes, self.stream)
+        torch.cuda.synchronize()
+        return Hu.cpu().numpy().T.copy(), dp.cpu().numpy()
+
+    def param_grad(self):
+        dU = torch.zeros(2, dtype=torch.float64, device=device())
+        self.A.md_param_grad(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, dU.data_ptr(),
+                             self.ws.ptr, self.ws.nbytes, self.stream)
+        torch.cuda.synchronize()
+        return dU.cpu().numpy()
+
+
+def decode_rows(offsets, counts, nbr):
+    """(key slot, partner slot, stencil code) for every entry of a full list."""
+    n = offsets.shape[0]
+    counts = counts.astype(np.int64)
+    keys = np.repeat(np.arange(n, dtype=np.int64), counts)
+    starts = np.repeat(offsets.astype(np.int64), counts)
+    within = np.arange(keys.shape[0], dtype=np.int64) - np.repeat(np.cumsum(counts) - counts, counts)
+    ent = nbr.view(np.uint32)[starts + within].astype(np.int64)
+    return keys, ent & SLOT_MASK, ent >> 27
+
+
+def pair_set_from_rows(keys, partners, ids=None):
+    """Unordered pairs (min id, max id) and a check that each appears twice."""
+    a = keys if ids is None else ids[keys]
+    b = partners if ids is None else ids[partners]
+    lo = np.minimum(a, b)
+    hi = np.maximum(a, b)
+    code = lo * (1 << 32) + hi
+    uniq, cnt = np.unique(code, return_counts=True)
+    return uniq, cnt
+
+
+def pair_codes(pairs):
+    p = np.asarray(pairs, dtype=np.int64)
+    return np.sort(np.minimum(p[:, 0], p[:, 1]) * (1 << 32) + np.maximum(p[:, 0], p[:, 1]))
+
+
+def force_error(F, Fref, S):
+    """max_i |F_i - Fref_i| / S_i with S_i the sum of pair-force magnitudes on i."""
+    err = np.linalg.norm(F - Fref, axis=1)
+    return float(np.max(err / np.maximum(S, 1e-300)))
