@@ -114,6 +114,7 @@ WsLayout ws_layout(int64_t n, int64_t ncell)
     L.part_a = off;    off = align256(off + sizeof(double) * 2 * (size_t)L.nbf);
     L.part_b = off;    off = align256(off + sizeof(double) * (size_t)L.nbi);
     L.pos32 = off;     off = align256(off + 16 * (size_t)n);
+    L.red = off;       off = align256(off + sizeof(int64_t) * 2 * 1024);
     L.scal = off;      off = align256(off + sizeof(double) * 16);
     L.total = off;
     return L;

@@ -46,7 +46,21 @@ __global__ __launch_bounds__(kStreamBlock) void k_label(Geo g, const double4* __
     const int32_t c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
     cell_of[i] = c;
     cell_xyz[i] = cx | (cy << 10) | (cz << 20);
-    rank[i] = atomicAdd(&count[c], 1);
+    // Slots in cell order (after a re-sort) put runs of equal cells in one
+    // wave: one atomic per distinct cell of the wave, ranks by lane order.
+    uint64_t todo = __ballot(1);
+    int32_t r = 0;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int32_t cl = __shfl(c, leader, 64);
+        const uint64_t same = __ballot(c == cl);
+        int32_t base = 0;
+        if ((int)lane_id() == leader) base = atomicAdd(&count[cl], (int32_t)__popcll(same));
+        base = __shfl(base, leader, 64);
+        if (c == cl) r = base + (int32_t)mbcnt64(same);
+        todo &= ~same;
+    }
+    rank[i] = r;
 }
 
 // ---- three-phase exclusive scan of int32 (block: 256 threads x 4 items) -----

@@ -220,13 +220,17 @@ hipError_t launch_reduce_pair(const double* part, int64_t nb, double scale0, dou
     return hipGetLastError();
 }
 
-// status[0] = total entries, status[1] = largest cell block (stride needed)
-__global__ __launch_bounds__(kReduceBlock) void k_list_stats(const int32_t* __restrict__ rows, int64_t ncell,
-                                                             int64_t* __restrict__ status)
+// status[0] = total entries, status[1] = largest cell block (stride needed):
+// per-block (sum, max) partials, then one block combines them in order.
+constexpr int kStatsBlocks = 1024;
+
+__global__ __launch_bounds__(kStreamBlock) void k_rows_partial(const int32_t* __restrict__ rows, int64_t ncell,
+                                                               long long* __restrict__ part)
 {
-    __shared__ long long s_sum[kReduceBlock / 64], s_max[kReduceBlock / 64];
+    __shared__ long long s_sum[kStreamBlock / 64], s_max[kStreamBlock / 64];
     long long sum = 0, mx = 0;
-    for (int64_t c = threadIdx.x; c < ncell; c += kReduceBlock) {
+    for (int64_t c = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x; c < ncell;
+         c += (int64_t)gridDim.x * kStreamBlock) {
         const long long r = rows[c];
         sum += r;
         mx = r > mx ? r : mx;
@@ -244,7 +248,38 @@ __global__ __launch_bounds__(kReduceBlock) void k_list_stats(const int32_t* __re
     __syncthreads();
     if (threadIdx.x == 0) {
         long long ts = 0, tm = 0;
-        for (int w = 0; w < kReduceBlock / 64; ++w) {
+        for (int w = 0; w < kStreamBlock / 64; ++w) {
+            ts += s_sum[w];
+            tm = s_max[w] > tm ? s_max[w] : tm;
+        }
+        part[2 * blockIdx.x] = ts;
+        part[2 * blockIdx.x + 1] = tm;
+    }
+}
+
+__global__ __launch_bounds__(kStatsBlocks) void k_rows_final(const long long* __restrict__ part, int nb,
+                                                             int64_t* __restrict__ status)
+{
+    __shared__ long long s_sum[kStatsBlocks / 64], s_max[kStatsBlocks / 64];
+    long long sum = 0, mx = 0;
+    if ((int)threadIdx.x < nb) {
+        sum = part[2 * threadIdx.x];
+        mx = part[2 * threadIdx.x + 1];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sum += __shfl_xor(sum, o, 64);
+        const long long y = __shfl_xor(mx, o, 64);
+        mx = y > mx ? y : mx;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_sum[threadIdx.x >> 6] = sum;
+        s_max[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long ts = 0, tm = 0;
+        for (int w = 0; w < kStatsBlocks / 64; ++w) {
             ts += s_sum[w];
             tm = s_max[w] > tm ? s_max[w] : tm;
         }
@@ -253,11 +288,13 @@ __global__ __launch_bounds__(kReduceBlock) void k_list_stats(const int32_t* __re
     }
 }
 
-hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t stride, int64_t* status,
+hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t* status, long long* part,
                              hipStream_t s)
 {
-    (void)stride;
-    hipLaunchKernelGGL(k_list_stats, dim3(1), dim3(kReduceBlock), 0, s, cell_rows, ncell, status);
+    const int nb = (int)(ceil_div(ncell, kStreamBlock) < kStatsBlocks ? ceil_div(ncell, kStreamBlock)
+                                                                     : kStatsBlocks);
+    hipLaunchKernelGGL(k_rows_partial, dim3(nb), dim3(kStreamBlock), 0, s, cell_rows, ncell, part);
+    hipLaunchKernelGGL(k_rows_final, dim3(1), dim3(kStatsBlocks), 0, s, (const long long*)part, nb, status);
     return hipGetLastError();
 }
 

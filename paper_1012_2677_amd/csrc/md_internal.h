@@ -76,6 +76,7 @@ struct WsLayout {
     size_t part_a;     // double[2*nbf]  per-block partial sums (force kernels)
     size_t part_b;     // double[nbi]    per-block partial sums (streaming kernels)
     size_t pos32;      // float4[n]      mixed-mode local coordinates (md_forces)
+    size_t red;        // int64[2*1024]  partials of the list statistics
     size_t scal;       // double[16]     small device scalars
     size_t total;
     int64_t nbs;       // scan blocks
@@ -169,8 +170,8 @@ hipError_t launch_reduce_pair(const double* part, int64_t nb, double scale0, dou
                               double* out2, hipStream_t s);
 hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags,
                                const double* energy, int64_t* out, hipStream_t s);
-hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t stride,
-                             int64_t* status, hipStream_t s);
+hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t* status, long long* part,
+                             hipStream_t s);
 
 // md_adjoint.hip
 hipError_t launch_hvp(const Geo& g, const LJ& lj, const double* pos, const int32_t* cell_xyz,

@@ -63,49 +63,49 @@ __device__ __forceinline__ void write_row(const BuildArgs& a, int32_t kslot, int
 }
 
 // Keys of one cell against candidates held in registers (at most NCH*64).
+// Empty candidate slots carry NaN coordinates, so r2 < rs2 fails for them in
+// both the plain and the minimum-image form of the test.
 template <bool MINIMG, int NCH>
-__device__ __forceinline__ int64_t rows_from_registers(const BuildArgs& a, int64_t base, int T, int own_start,
-                                                      int own_cnt, const double* cx, const double* cy,
-                                                      const double* cz, const uint32_t* meta)
+__device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, uint32_t* blk, uint32_t stride,
+                                                       int T, int own_cnt, const double4* s_key,
+                                                       const double* cx, const double* cy, const double* cz,
+                                                       const uint32_t* meta)
 {
-    int64_t used = 0;
+    uint32_t used = 0;
     for (int kk = 0; kk < own_cnt; ++kk) {
-        const int kidx = own_start + kk;
-        const int32_t kslot = a.order ? a.order[kidx] : kidx;
-        const double4 kp = a.pos[kslot];
-        int64_t wpos = 0;
+        const double4 kp = s_key[kk];
+        const int32_t kslot = (int32_t)__double_as_longlong(kp.w);
+        uint32_t wpos = 0;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             if (ch * 64 < T) {
                 const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
-                const bool pass = meta[ch] != 0xFFFFFFFFu && r2 < a.rs2 &&
-                                  (int32_t)(meta[ch] & kSlotMask) != kslot;
+                const bool pass = r2 < a.rs2 && (int32_t)(meta[ch] & kSlotMask) != kslot;
                 const uint64_t m = __ballot(pass);
-                if (pass) {
-                    const int64_t w = used + wpos + mbcnt64(m);
-                    if (w < a.stride) a.nbr[base + w] = meta[ch];
-                }
-                wpos += __popcll(m);
+                const uint32_t w = used + wpos + mbcnt64(m);
+                if (pass && w < stride) blk[w] = meta[ch];
+                wpos += (uint32_t)__popcll(m);
             }
         }
-        if (lane_id() == 0) write_row(a, kslot, base, used, wpos);
+        if (lane_id() == 0) write_row(a, kslot, (int64_t)(blk - a.nbr), used, wpos);
         used += wpos;
     }
     return used;
 }
 
 // Same rows, candidates re-read from memory for every key (neighbourhoods with
-// more than NCH*64 particles: never at liquid densities, kept for generality).
+// more than NCH*64 particles or cells with more than 64 particles: never at
+// liquid densities, kept for generality).
 template <bool MINIMG>
-__device__ int64_t rows_from_memory(const BuildArgs& a, int64_t base, int T, int own_start, int own_cnt,
-                                    const int* s_pref, const int* s_nstart)
+__device__ uint32_t rows_from_memory(const BuildArgs& a, uint32_t* blk, uint32_t stride, int T, int own_start,
+                                     int own_cnt, const int* s_pref, const int* s_nstart)
 {
-    int64_t used = 0;
+    uint32_t used = 0;
     for (int kk = 0; kk < own_cnt; ++kk) {
         const int kidx = own_start + kk;
         const int32_t kslot = a.order ? a.order[kidx] : kidx;
         const double4 kp = a.pos[kslot];
-        int64_t wpos = 0;
+        uint32_t wpos = 0;
         for (int t0 = 0; t0 < T; t0 += 64) {
             const int t = t0 + (int)lane_id();
             bool pass = false;
@@ -121,17 +121,17 @@ __device__ int64_t rows_from_memory(const BuildArgs& a, int64_t base, int T, int
                 meta = (uint32_t)slot | ((uint32_t)q << kCodeShift);
             }
             const uint64_t m = __ballot(pass);
-            if (pass) {
-                const int64_t w = used + wpos + mbcnt64(m);
-                if (w < a.stride) a.nbr[base + w] = meta;
-            }
-            wpos += __popcll(m);
+            const uint32_t w = used + wpos + mbcnt64(m);
+            if (pass && w < stride) blk[w] = meta;
+            wpos += (uint32_t)__popcll(m);
         }
-        if (lane_id() == 0) write_row(a, kslot, base, used, wpos);
+        if (lane_id() == 0) write_row(a, kslot, (int64_t)(blk - a.nbr), used, wpos);
         used += wpos;
     }
     return used;
 }
+
+constexpr int kMaxOwn = 64;   // own-cell particles kept in LDS for the key loop
 
 template <int NCH>
 __global__ __launch_bounds__(64) void k_build(BuildArgs a)
@@ -146,6 +146,7 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
 
     __shared__ int s_nstart[27];
     __shared__ int s_pref[28];
+    __shared__ double4 s_key[kMaxOwn];
     int cnt = 0, st = 0;
     if (lane < 27) {
         int ax = cx + lane / 9 - 1, ay = cy + (lane / 3) % 3 - 1, az = cz + lane % 3 - 1;
@@ -173,46 +174,53 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     __syncthreads();
 
     const int T = s_pref[27];
+    const int own_pref = s_pref[13];
     const int own_start = s_nstart[13];
-    const int own_cnt = s_pref[14] - s_pref[13];
+    const int own_cnt = s_pref[14] - own_pref;
     const bool minimg = a.exact_all || cx == 0 || cx == nx - 1 || cy == 0 || cy == ny - 1 || cz == 0 ||
                         cz == nz - 1;
-    const int64_t base = c * a.stride;
-    int64_t used;
+    uint32_t* blk = a.nbr + c * a.stride;
+    const uint32_t stride = (uint32_t)(a.stride < 0x7FFFFFFF ? a.stride : 0x7FFFFFFF);
+    uint32_t used = 0;
 
-    if (T <= NCH * 64) {
+    if (own_cnt > 0 && T <= NCH * 64 && own_cnt <= kMaxOwn) {
         double px[NCH], py[NCH], pz[NCH];
         uint32_t meta[NCH];
+        const double qnan = __longlong_as_double(0x7FF8000000000000LL);
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int t = ch * 64 + lane;
-            px[ch] = py[ch] = pz[ch] = 0.0;
-            meta[ch] = 0xFFFFFFFFu;
-            if (t < T) {
-                // neighbour cell holding candidate t: binary search in the prefix
-                int lo = 0, hi = 27;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_pref[mid] <= t) lo = mid; else hi = mid;
-                }
-                const int idx = s_nstart[lo] + (t - s_pref[lo]);
-                const int32_t slot = a.order ? a.order[idx] : idx;
-                const double4 p = a.pos[slot];
-                px[ch] = p.x;
-                py[ch] = p.y;
-                pz[ch] = p.z;
-                meta[ch] = (uint32_t)slot | ((uint32_t)lo << kCodeShift);
+            const int tt = t < T ? t : T - 1;   // in-range index; the result is discarded if t >= T
+            // neighbour cell holding candidate tt: binary search in the prefix
+            int lo = 0, hi = 27;
+#pragma unroll
+            for (int it = 0; it < 5; ++it) {
+                const int mid = (lo + hi) >> 1;
+                const bool le = s_pref[mid] <= tt;
+                lo = le ? mid : lo;
+                hi = le ? hi : mid;
             }
+            const int idx = s_nstart[lo] + (tt - s_pref[lo]);
+            const int32_t slot = a.order ? a.order[idx] : idx;
+            const double4 p = a.pos[slot];
+            const bool ok = t < T;
+            px[ch] = ok ? p.x : qnan;
+            py[ch] = ok ? p.y : qnan;
+            pz[ch] = ok ? p.z : qnan;
+            meta[ch] = (uint32_t)slot | ((uint32_t)lo << kCodeShift);
+            const int k = t - own_pref;
+            if (ok && k >= 0 && k < own_cnt) s_key[k] = make_double4(p.x, p.y, p.z, __longlong_as_double((long long)slot));
         }
-        used = minimg ? rows_from_registers<true, NCH>(a, base, T, own_start, own_cnt, px, py, pz, meta)
-                      : rows_from_registers<false, NCH>(a, base, T, own_start, own_cnt, px, py, pz, meta);
-    } else {
-        used = minimg ? rows_from_memory<true>(a, base, T, own_start, own_cnt, s_pref, s_nstart)
-                      : rows_from_memory<false>(a, base, T, own_start, own_cnt, s_pref, s_nstart);
+        __syncthreads();
+        used = minimg ? rows_from_registers<true, NCH>(a, blk, stride, T, own_cnt, s_key, px, py, pz, meta)
+                      : rows_from_registers<false, NCH>(a, blk, stride, T, own_cnt, s_key, px, py, pz, meta);
+    } else if (own_cnt > 0) {
+        used = minimg ? rows_from_memory<true>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart)
+                      : rows_from_memory<false>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart);
     }
     if (lane == 0) {
-        a.cell_rows[c] = used > 0x7FFFFFFF ? 0x7FFFFFFF : (int32_t)used;
-        if (used > a.stride) atomicOr((unsigned long long*)&a.status[2], 1ull);
+        a.cell_rows[c] = used > 0x7FFFFFFFu ? 0x7FFFFFFF : (int32_t)used;
+        if (used > stride) atomicOr((unsigned long long*)&a.status[2], 1ull);
     }
 }
 
@@ -245,7 +253,7 @@ hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cel
     hipLaunchKernelGGL(k_build<kBuildChunks>, dim3((unsigned)g.ncell), dim3(64), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_list_stats(a.cell_rows, g.ncell, list.cell_stride, list.status, s);
+    return launch_list_stats(a.cell_rows, g.ncell, list.status, (long long*)((char*)ws + L.red), s);
 }
 
 }  // namespace md
