@@ -176,6 +176,12 @@ int md_cell_dims(const md_params* p, int32_t ncell[3]);
 /* Host-only: device workspace bytes needed by every call below for p. */
 size_t md_workspace_bytes(const md_params* p);
 
+/* Periodic packing of user coordinates: pos[i] = (wrap(q[i][0]), wrap(q[i][1]),
+ * wrap(q[i][2]), 0) with wrap(x) = x - L floor(x / L) folded into [0, L)
+ * (periodic boundaries on all axes, Sec. 4.5).  q: device double[n][3];
+ * pos: device double[n][4] (may not alias q). */
+int md_pack_positions(const md_params* p, const double* q, double* pos, hipStream_t stream);
+
 /* Cell grid of pos (Sec. 2.2): label each slot with its cell, count per cell,
  * prefix-sum the counts, place slots by cell in ascending slot order.
  * pos: device double[n][4] with 0 <= x < L.  Fills cells (which must point to
@@ -242,6 +248,21 @@ int md_energy(const md_params* p, md_state* st, double* out, hipStream_t stream)
 int md_hvp(const md_params* p, const double* pos, const md_cells* cells,
            const md_pairlist* list, const double* u, double* Hu, double* dparam,
            void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One fused adjoint pass (FP64) for reverse-mode sweeps of the integrator:
+ *   out_i  = alpha out_i + beta (H u)_i + gamma F_i          (F = -grad U)
+ *   acc[k] += cu u . dF/dtheta_k + cU dU/dtheta_k            (theta = eps, sigma)
+ *   u_out_i = u_i + dt out_i   (the updated out; skipped when u_out is NULL)
+ * coef = {alpha, beta, gamma, cu, cU}; dt is p->dt.  The reverse of one
+ * velocity-Verlet step is two calls: the second kick at q' with
+ * (1, -h, -w, h, w) and u_out (the drift of the velocity adjoint), then the
+ * first kick at q with (1, -h, 0, h, 0), h = dt/2 and w the observable
+ * weight.  u, out, u_out: device double[3][n] (distinct); acc: device
+ * double[2], accumulated in a fixed order. */
+int md_adjoint_kick(const md_params* p, const double* pos, const md_cells* cells,
+                    const md_pairlist* list, const double* u, double* out, double* u_out,
+                    const double coef[5], double* acc, void* ws, size_t ws_bytes,
+                    hipStream_t stream);
 
 /* dU/deps and dU/dsigma of the potential energy (FP64), into device double[2]. */
 int md_param_grad(const md_params* p, const double* pos, const md_cells* cells,

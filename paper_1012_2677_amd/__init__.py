@@ -12,5 +12,7 @@ from ._abi import MdError
 _abi.lib()  # fail loudly when the HIP library is missing
 
 from .engine import Engine, Grid, PairList, Workspace, make_params, stream_handle  # noqa: E402
+from .autograd import Field, LJEnergy, TrajectoryMeanPE  # noqa: E402
 
-__all__ = ["Engine", "Grid", "PairList", "Workspace", "make_params", "stream_handle", "MdError"]
+__all__ = ["Engine", "Grid", "PairList", "Workspace", "make_params", "stream_handle", "MdError", "Field",
+           "LJEnergy", "TrajectoryMeanPE"]

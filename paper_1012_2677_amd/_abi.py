@@ -29,8 +29,8 @@ MD_MAX_N = 1 << 27
 MD_T_FORCE, MD_T_INTEGRATE, MD_T_BIN, MD_T_RESORT, MD_T_BUILD, MD_T_REDUCE, MD_T_COUNT = range(7)
 TIMER_NAMES = ["force", "integrate", "bin", "resort", "build", "reduce"]
 
-EXPORTED = ["md_cell_dims", "md_workspace_bytes", "md_bin_cells", "md_resort", "md_build_pairlist",
-            "md_forces", "md_prepare", "md_step", "md_energy", "md_hvp", "md_param_grad",
+EXPORTED = ["md_cell_dims", "md_workspace_bytes", "md_pack_positions", "md_bin_cells", "md_resort", "md_build_pairlist",
+            "md_forces", "md_prepare", "md_step", "md_energy", "md_hvp", "md_adjoint_kick", "md_param_grad",
             "md_last_error"]
 
 
@@ -88,6 +88,7 @@ def lib():
     sig = {
         "md_cell_dims": (C.c_int, [P(MdParams), P(C.c_int32)]),
         "md_workspace_bytes": (C.c_size_t, [P(MdParams)]),
+        "md_pack_positions": (C.c_int, [P(MdParams), vp, vp, vp]),
         "md_bin_cells": (C.c_int, [P(MdParams), vp, P(MdCells), vp, C.c_size_t, vp]),
         "md_resort": (C.c_int, [P(MdParams), P(MdState), vp]),
         "md_build_pairlist": (C.c_int, [P(MdParams), vp, P(MdCells), P(MdPairlist), vp, C.c_size_t, vp]),
@@ -96,6 +97,8 @@ def lib():
         "md_step": (C.c_int, [P(MdParams), P(MdState), C.c_int64, C.c_int64, vp, vp]),
         "md_energy": (C.c_int, [P(MdParams), P(MdState), vp, vp]),
         "md_hvp": (C.c_int, [P(MdParams), vp, P(MdCells), P(MdPairlist), vp, vp, vp, vp, C.c_size_t, vp]),
+        "md_adjoint_kick": (C.c_int, [P(MdParams), vp, P(MdCells), P(MdPairlist), vp, vp, vp,
+                                      P(C.c_double), vp, vp, C.c_size_t, vp]),
         "md_param_grad": (C.c_int, [P(MdParams), vp, P(MdCells), P(MdPairlist), vp, vp, C.c_size_t, vp]),
         "md_last_error": (C.c_char_p, []),
     }
@@ -128,6 +131,10 @@ def md_cell_dims(params: MdParams):
 
 def md_workspace_bytes(params: MdParams) -> int:
     return int(lib().md_workspace_bytes(C.byref(params)))
+
+
+def md_pack_positions(params, q, pos, stream):
+    return _check(lib().md_pack_positions(C.byref(params), q, pos, stream), "md_pack_positions")
 
 
 def md_bin_cells(params, pos, cells, ws, ws_bytes, stream):
@@ -164,6 +171,12 @@ def md_energy(params, state, out, stream):
 def md_hvp(params, pos, cells, plist, u, Hu, dparam, ws, ws_bytes, stream):
     return _check(lib().md_hvp(C.byref(params), pos, C.byref(cells), C.byref(plist), u, Hu, dparam, ws,
                                ws_bytes, stream), "md_hvp")
+
+
+def md_adjoint_kick(params, pos, cells, plist, u, out, u_out, coef, acc, ws, ws_bytes, stream):
+    c5 = (C.c_double * 5)(*[float(x) for x in coef])
+    return _check(lib().md_adjoint_kick(C.byref(params), pos, C.byref(cells), C.byref(plist), u, out, u_out, c5,
+                                        acc, ws, ws_bytes, stream), "md_adjoint_kick")
 
 
 def md_param_grad(params, pos, cells, plist, dU, ws, ws_bytes, stream):

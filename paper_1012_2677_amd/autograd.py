@@ -1,0 +1,213 @@
+"""Differentiation of the LJ hot path through torch.autograd.
+
+`LJEnergy`   (U, F) = (potential energy, forces) of positions q, with
+             gradients of any scalar of (U, F) with respect to q, eps, sigma.
+             Backward: dL/dq = -gU F - H gF (H = Hessian of U, so dF/dq = -H),
+             dL/dtheta = gU dU/dtheta + gF . dF/dtheta, all from the HIP adjoint
+             kernels (md_hvp, md_param_grad).
+`TrajectoryMeanPE`  O = (1/K) sum_{k=1..K} U(q_k) over K velocity-Verlet steps
+             from (q0, v0), differentiated with respect to q0 (v0 held fixed),
+             eps and sigma.  The forward pass stores (q, v) every `ckpt` steps;
+             the backward pass recomputes each segment from its checkpoint and
+             sweeps it in reverse (adjoint of velocity Verlet, below).
+
+Positions are (N, 3) float64 CUDA tensors in a periodic box; the wrap into the
+box is a relabelling of the same periodic point and is treated as the
+identity by the derivatives.  Re-sorting is disabled here, so slots are the
+caller's particle indices.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _abi as A
+from .engine import Engine, Grid, PairList, Workspace, make_params, stream_handle
+
+
+class Field:
+    """Grid, pair list and workspace for evaluating the force field and its
+    adjoint at arbitrary positions of N particles (FP64, no re-sort)."""
+
+    def __init__(self, n, box, eps, sigma, rc=2.5, rs=2.8, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.n = int(n)
+        self.box, self.rc, self.rs = box, float(rc), float(rs)
+        self.params = make_params(n, box, eps=float(eps), sigma=float(sigma), rc=rc, rs=rs,
+                                  precision="fp64", resort_every=0)
+        self.grid = Grid(self.params, self.device)
+        self.plist = PairList(self.params, self.grid.ncell, self.device)
+        self.ws = Workspace(self.params, self.device)
+        self.pos = torch.empty((self.n, 4), dtype=torch.float64, device=self.device)
+        self.out2 = torch.empty(2, dtype=torch.float64, device=self.device)
+
+    def set_params(self, eps, sigma):
+        self.params.eps = float(eps)
+        self.params.sigma = float(sigma)
+
+    def set_positions(self, q: torch.Tensor, rebuild: bool = True):
+        """Fold q into the box; bin it and build the pair list at rs unless
+        rebuild is False (then the list of the previous call is kept, which is
+        valid while no particle has moved more than (rs - rc)/2 since)."""
+        q = q.detach().to(self.device, torch.float64).contiguous()
+        st = stream_handle(self.device)
+        A.md_pack_positions(self.params, q.data_ptr(), self.pos.data_ptr(), st)
+        if not rebuild:
+            return
+        A.md_bin_cells(self.params, self.pos.data_ptr(), self.grid.c, self.ws.ptr, self.ws.nbytes, st)
+        for _ in range(4):
+            A.md_build_pairlist(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, self.ws.ptr,
+                                self.ws.nbytes, st)
+            status = self.plist.status.cpu()
+            if int(status[2]) == 0:
+                return
+            self.plist.grow_for(int(status[1]))
+        raise A.MdError(A.MD_ERR_CAPACITY, "Field.set_positions", "pair list did not fit")
+
+    def energy_forces(self):
+        """(U, W, F[N, 3]) at the current positions."""
+        F = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
+        A.md_forces(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, F.data_ptr(),
+                    self.out2.data_ptr(), self.ws.ptr, self.ws.nbytes, stream_handle(self.device))
+        pw = self.out2.clone()
+        return pw[0], pw[1], F.t()
+
+    def hvp(self, u: torch.Tensor):
+        """(H u [N, 3], u . dF/d(eps, sigma) [2]) at the current positions."""
+        ut = u.detach().to(self.device, torch.float64).t().contiguous()
+        Hu = torch.empty_like(ut)
+        A.md_hvp(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, ut.data_ptr(), Hu.data_ptr(),
+                 self.out2.data_ptr(), self.ws.ptr, self.ws.nbytes, stream_handle(self.device))
+        return Hu.t(), self.out2.clone()
+
+    def adjoint_kick(self, u: torch.Tensor, out: torch.Tensor, u_out, coef, acc: torch.Tensor):
+        """out = a out + b H u + c F;  acc += cu u.dF/dtheta + cU dU/dtheta;
+        u_out = u + dt out (if given).  u, out, u_out: [3, N] float64."""
+        A.md_adjoint_kick(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, u.data_ptr(), out.data_ptr(),
+                          None if u_out is None else u_out.data_ptr(), coef, acc.data_ptr(), self.ws.ptr,
+                          self.ws.nbytes, stream_handle(self.device))
+
+    def param_grad(self):
+        """(dU/deps, dU/dsigma) at the current positions."""
+        A.md_param_grad(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, self.out2.data_ptr(),
+                        self.ws.ptr, self.ws.nbytes, stream_handle(self.device))
+        return self.out2.clone()
+
+
+def _scalar(x) -> float:
+    return float(x.detach().cpu()) if torch.is_tensor(x) else float(x)
+
+
+class LJEnergy(torch.autograd.Function):
+    """(U, F) = LJEnergy.apply(q, eps, sigma, box, rc=2.5, rs=2.8)."""
+
+    @staticmethod
+    def forward(ctx, q, eps, sigma, box, rc=2.5, rs=2.8):
+        n = q.shape[0]
+        f = Field(n, box, _scalar(eps), _scalar(sigma), rc, rs, q.device)
+        f.set_positions(q)
+        U, _, F = f.energy_forces()
+        ctx.field = f
+        ctx.save_for_backward(F)
+        ctx.eps_like = eps if torch.is_tensor(eps) else None
+        ctx.sig_like = sigma if torch.is_tensor(sigma) else None
+        return U.to(q.dtype), F.contiguous()
+
+    @staticmethod
+    def backward(ctx, gU, gF):
+        (F,) = ctx.saved_tensors
+        f: Field = ctx.field
+        n = F.shape[0]
+        u = (gF if gF is not None else torch.zeros_like(F)).detach().to(torch.float64).t().contiguous()
+        wU = 0.0 if gU is None else float(gU.detach().cpu())
+        out = torch.empty((3, n), dtype=torch.float64, device=F.device)
+        acc = torch.zeros(2, dtype=torch.float64, device=F.device)
+        # dL/dq = -gU F - H gF;  dL/dtheta = gF . dF/dtheta + gU dU/dtheta
+        f.adjoint_kick(u, out, None, (0.0, -1.0, -wU, 1.0, wU), acc)
+        ge = acc[0].to(ctx.eps_like) if ctx.eps_like is not None else None
+        gs = acc[1].to(ctx.sig_like) if ctx.sig_like is not None else None
+        return out.t(), ge, gs, None, None, None
+
+
+class TrajectoryMeanPE(torch.autograd.Function):
+    """O = TrajectoryMeanPE.apply(q0, v0, eps, sigma, box, steps=200, ckpt=20,
+    dt=0.005, rc=2.5, rs=2.8).
+
+    Reverse sweep of one velocity-Verlet step (h = dt/2, unit mass, F = -grad U)
+        v' = v + h F(q);  q' = q + dt v';  v'' = v' + h F(q')
+    with adjoints (a_q, a_v) carried backwards:
+        a_q  += -h H(q') a_v          (second kick)
+        a_v  +=  dt a_q               (drift)
+        a_q  += -h H(q) a_v           (first kick)
+    and the observable adds (1/K) grad U(q') = -(1/K) F(q') to a_q at every
+    step; the parameter adjoint gathers h a_v . dF/dtheta at both kicks and
+    (1/K) dU/dtheta at every sampled state.
+    """
+
+    @staticmethod
+    def forward(ctx, q0, v0, eps, sigma, box, steps=200, ckpt=20, dt=0.005, rc=2.5, rs=2.8):
+        e_, s_ = _scalar(eps), _scalar(sigma)
+        dev = q0.device
+        q = q0.detach().to(torch.float64)
+        v = v0.detach().to(torch.float64)
+        ckpts = []
+        total = 0.0
+        k = 0
+        eng = Engine(q.cpu().numpy(), v.cpu().numpy(), box, eps=e_, sigma=s_, rc=rc, rs=rs, dt=dt,
+                     precision="fp64", resort_every=0, device=dev)
+        while k < steps:
+            ckpts.append((eng.pos[:, :3].clone(), eng.vel.t().clone()))
+            m = min(ckpt, steps - k)
+            log = eng.step(m, sample_every=1)
+            total += float(np.sum(log[:, 1]))
+            k += m
+        ctx.ckpts = ckpts
+        ctx.cfg = dict(box=box, steps=steps, ckpt=ckpt, dt=dt, rc=rc, rs=rs, eps=e_, sigma=s_)
+        ctx.eps_like = eps if torch.is_tensor(eps) else None
+        ctx.sig_like = sigma if torch.is_tensor(sigma) else None
+        return torch.tensor(total / steps, dtype=torch.float64, device=dev)
+
+    @staticmethod
+    def backward(ctx, gO):
+        cfg = ctx.cfg
+        K, dt = cfg["steps"], cfg["dt"]
+        h = 0.5 * dt
+        q0, _ = ctx.ckpts[0]
+        dev = q0.device
+        n = q0.shape[0]
+        f = Field(n, cfg["box"], cfg["eps"], cfg["sigma"], cfg["rc"], cfg["rs"], dev)
+        f.params.dt = dt
+        w = float(gO.detach().cpu()) / K
+        aq = torch.zeros((3, n), dtype=torch.float64, device=dev)
+        av = torch.zeros_like(aq)
+        av_next = torch.empty_like(aq)
+        acc = torch.zeros(2, dtype=torch.float64, device=dev)
+        k_end = K
+        for si in range(len(ctx.ckpts) - 1, -1, -1):
+            qc, vc = ctx.ckpts[si]
+            k0 = si * cfg["ckpt"]
+            m = k_end - k0
+            # recompute the segment's states q_k0 .. q_k0+m from its checkpoint
+            eng = Engine(qc.cpu().numpy(), vc.cpu().numpy(), cfg["box"], eps=cfg["eps"], sigma=cfg["sigma"],
+                         rc=cfg["rc"], rs=cfg["rs"], dt=dt, precision="fp64", resort_every=0, device=dev)
+            states = [qc]
+            for _ in range(m):
+                eng.step(1)
+                states.append(eng.pos[:, :3].clone())
+            del eng
+            for j in range(m - 1, -1, -1):
+                # step q_j -> q_{j+1}: observable term and second kick at q_{j+1},
+                # with the drift of the velocity adjoint fused in
+                f.set_positions(states[j + 1])
+                f.adjoint_kick(av, aq, av_next, (1.0, -h, -w, h, w), acc)
+                av, av_next = av_next, av
+                # first kick at q_j (the list built at q_{j+1} is still valid)
+                f.set_positions(states[j], rebuild=False)
+                f.adjoint_kick(av, aq, None, (1.0, -h, 0.0, h, 0.0), acc)
+            k_end = k0
+        ge = acc[0].to(ctx.eps_like) if ctx.eps_like is not None else None
+        gs = acc[1].to(ctx.sig_like) if ctx.sig_like is not None else None
+        return aq.t(), None, ge, gs, None, None, None, None, None, None

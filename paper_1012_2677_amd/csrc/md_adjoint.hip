@@ -25,8 +25,10 @@ struct AdjArgs {
     const int32_t* counts;
     const uint32_t* nbr;
     const double* u;
-    double* Hu;
+    double* out;
+    double* u_out;
     double* part;
+    double alpha, beta, gamma, cu, cU, dt;
     int64_t n;
     double L[3], invL[3];
     int32_t nc[3];
@@ -67,8 +69,15 @@ __device__ __forceinline__ void block_partial2_a(double a, double b, double* par
     }
 }
 
-// mode 0: Hessian-vector product (+ parameter VJP partials); mode 1: dU/dtheta partials
-template <int G, int MODE>
+// One pass over the list for the key's partners with r < rc, accumulating
+//   Hu_i  = sum_j [2 g'(s) (d . du) d + g du]        (if HAS_U; du = u_j - u_i)
+//   F_i   = -sum_j g d
+//   t_e   = sum (dg/deps) d . du,   t_s = sum (dg/dsigma) d . du   (if HAS_U)
+//   v_e   = sum V / eps,            v_s = sum dV/dsigma
+// then out_i = alpha out_i + beta Hu_i + gamma F_i (when out != nullptr),
+// u_out_i = u_i + dt out_i (when u_out != nullptr), and the block partials
+// (cu t_e + cU v_e, cu t_s + cU v_s) / 2 (each pair is visited twice).
+template <int G, bool HAS_U>
 __global__ __launch_bounds__(kForceBlock) void k_adjoint(AdjArgs a)
 {
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -87,7 +96,7 @@ __global__ __launch_bounds__(kForceBlock) void k_adjoint(AdjArgs a)
         xi = p.x;
         yi = p.y;
         zi = p.z;
-        if (MODE == 0) {
+        if (HAS_U) {
             uxi = a.u[key];
             uyi = a.u[n + key];
             uzi = a.u[2 * n + key];
@@ -95,7 +104,8 @@ __global__ __launch_bounds__(kForceBlock) void k_adjoint(AdjArgs a)
         minimg = a.exact_all || boundary_cell_a(a.cell_xyz[key], a.nc);
     }
     const LJ& lj = a.lj;
-    double hx = 0.0, hy = 0.0, hz = 0.0, t0 = 0.0, t1 = 0.0;
+    double hx = 0.0, hy = 0.0, hz = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    double te = 0.0, ts = 0.0, ve = 0.0, vs = 0.0;
     for (int t = sub; t < cnt; t += G) {
         const uint32_t e = a.nbr[off + t];
         const int64_t j = e & kSlotMask;
@@ -110,8 +120,11 @@ __global__ __launch_bounds__(kForceBlock) void k_adjoint(AdjArgs a)
         if (!(r2 < lj.rc2)) continue;
         const double r2i = 1.0 / r2;
         const double r6i = r2i * r2i * r2i;
-        if (MODE == 0) {
-            const double g = r2i * r6i * (lj.A * r6i - lj.B) - lj.C8;
+        const double g = r2i * r6i * (lj.A * r6i - lj.B) - lj.C8;
+        fx -= g * dx;
+        fy -= g * dy;
+        fz -= g * dz;
+        if (HAS_U) {
             const double gp = r2i * r2i * r6i * (-7.0 * lj.A * r6i + 4.0 * lj.B);
             const double dux = a.u[j] - uxi, duy = a.u[n + j] - uyi, duz = a.u[2 * n + j] - uzi;
             const double ddu = dx * dux + dy * duy + dz * duz;
@@ -120,30 +133,46 @@ __global__ __launch_bounds__(kForceBlock) void k_adjoint(AdjArgs a)
             hy += c * dy + g * duy;
             hz += c * dz + g * duz;
             // dg/deps = g/eps;  dg/dsigma = (12 A s^-7 - 6 B s^-4 - Cs) / sigma
-            t0 += (g / lj.eps) * ddu;
-            t1 += ((12.0 * lj.A * r6i - 6.0 * lj.B) * r6i * r2i - lj.Cs) / lj.sigma * ddu;
-        } else {
-            const double V = r6i * (lj.A4 * r6i - lj.B4) + lj.C2 * r2 + lj.C0;
-            const double sa = r6i * r6i + 6.0 * r2 * lj.rc14i - 7.0 * lj.rc12i;
-            const double sb = r6i + 3.0 * r2 * lj.rc8i - 4.0 * lj.rc6i;
-            t0 += V / lj.eps;
-            t1 += (12.0 * lj.A4 * sa - 6.0 * lj.B4 * sb) / lj.sigma;
+            te += (g / lj.eps) * ddu;
+            ts += ((12.0 * lj.A * r6i - 6.0 * lj.B) * r6i * r2i - lj.Cs) / lj.sigma * ddu;
         }
+        const double V = r6i * (lj.A4 * r6i - lj.B4) + lj.C2 * r2 + lj.C0;
+        const double sa = r6i * r6i + 6.0 * r2 * lj.rc14i - 7.0 * lj.rc12i;
+        const double sb = r6i + 3.0 * r2 * lj.rc8i - 4.0 * lj.rc6i;
+        ve += V / lj.eps;
+        vs += (12.0 * lj.A4 * sa - 6.0 * lj.B4 * sb) / lj.sigma;
     }
-    if (MODE == 0) {
 #pragma unroll
-        for (int o = G / 2; o > 0; o >>= 1) {
+    for (int o = G / 2; o > 0; o >>= 1) {
+        fx += __shfl_xor(fx, o, G);
+        fy += __shfl_xor(fy, o, G);
+        fz += __shfl_xor(fz, o, G);
+        if (HAS_U) {
             hx += __shfl_xor(hx, o, G);
             hy += __shfl_xor(hy, o, G);
             hz += __shfl_xor(hz, o, G);
         }
-        if (valid && sub == 0) {
-            a.Hu[key] = hx;
-            a.Hu[n + key] = hy;
-            a.Hu[2 * n + key] = hz;
+    }
+    if (valid && sub == 0 && a.out) {
+        double ox = a.beta * hx + a.gamma * fx;
+        double oy = a.beta * hy + a.gamma * fy;
+        double oz = a.beta * hz + a.gamma * fz;
+        if (a.alpha != 0.0) {
+            ox += a.alpha * a.out[key];
+            oy += a.alpha * a.out[n + key];
+            oz += a.alpha * a.out[2 * n + key];
+        }
+        a.out[key] = ox;
+        a.out[n + key] = oy;
+        a.out[2 * n + key] = oz;
+        if (a.u_out) {
+            a.u_out[key] = uxi + a.dt * ox;
+            a.u_out[n + key] = uyi + a.dt * oy;
+            a.u_out[2 * n + key] = uzi + a.dt * oz;
         }
     }
-    if (a.part) block_partial2_a<kForceBlock>(0.5 * t0, 0.5 * t1, a.part, blk);
+    if (a.part)
+        block_partial2_a<kForceBlock>(0.5 * (a.cu * te + a.cU * ve), 0.5 * (a.cu * ts + a.cU * vs), a.part, blk);
 }
 
 static AdjArgs make_args(const Geo& g, const LJ& lj, const double* pos, const int32_t* cell_xyz,
@@ -156,8 +185,10 @@ static AdjArgs make_args(const Geo& g, const LJ& lj, const double* pos, const in
     a.counts = list.counts;
     a.nbr = list.nbr;
     a.u = nullptr;
-    a.Hu = nullptr;
+    a.out = nullptr;
+    a.u_out = nullptr;
     a.part = nullptr;
+    a.alpha = a.beta = a.gamma = a.cu = a.cU = a.dt = 0.0;
     a.n = g.n;
     for (int k = 0; k < 3; ++k) {
         a.L[k] = g.L[k];
@@ -169,15 +200,25 @@ static AdjArgs make_args(const Geo& g, const LJ& lj, const double* pos, const in
     return a;
 }
 
+static void launch_adj(const Geo& g, const AdjArgs& a, hipStream_t s)
+{
+    const dim3 grid((unsigned)ceil_div(g.n, kKeysPerBlock)), block(kForceBlock);
+    if (a.u)
+        hipLaunchKernelGGL((k_adjoint<kLanesPerKey, true>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_adjoint<kLanesPerKey, false>), grid, block, 0, s, a);
+}
+
 hipError_t launch_hvp(const Geo& g, const LJ& lj, const double* pos, const int32_t* cell_xyz,
                       const md_pairlist& list, const double* u, double* Hu, double* part, hipStream_t s)
 {
     AdjArgs a = make_args(g, lj, pos, cell_xyz, list);
     a.u = u;
-    a.Hu = Hu;
+    a.out = Hu;
+    a.beta = 1.0;
     a.part = part;
-    hipLaunchKernelGGL((k_adjoint<kLanesPerKey, 0>), dim3((unsigned)ceil_div(g.n, kKeysPerBlock)),
-                       dim3(kForceBlock), 0, s, a);
+    a.cu = 1.0;
+    launch_adj(g, a, s);
     return hipGetLastError();
 }
 
@@ -186,8 +227,27 @@ hipError_t launch_param_grad(const Geo& g, const LJ& lj, const double* pos, cons
 {
     AdjArgs a = make_args(g, lj, pos, cell_xyz, list);
     a.part = part;
-    hipLaunchKernelGGL((k_adjoint<kLanesPerKey, 1>), dim3((unsigned)ceil_div(g.n, kKeysPerBlock)),
-                       dim3(kForceBlock), 0, s, a);
+    a.cU = 1.0;
+    launch_adj(g, a, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_kick(const Geo& g, const LJ& lj, const double* pos, const int32_t* cell_xyz,
+                               const md_pairlist& list, const double* u, double* out, double* u_out,
+                               const AdjCoef& k, double* part, hipStream_t s)
+{
+    AdjArgs a = make_args(g, lj, pos, cell_xyz, list);
+    a.u = u;
+    a.out = out;
+    a.u_out = u_out;
+    a.alpha = k.alpha;
+    a.beta = k.beta;
+    a.gamma = k.gamma;
+    a.cu = k.cu;
+    a.cU = k.cU;
+    a.dt = k.dt;
+    a.part = part;
+    launch_adj(g, a, s);
     return hipGetLastError();
 }
 

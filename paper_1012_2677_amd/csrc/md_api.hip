@@ -243,6 +243,17 @@ size_t md_workspace_bytes(const md_params* p)
     return ws_layout(p->n, (int64_t)nc[0] * nc[1] * nc[2]).total;
 }
 
+int md_pack_positions(const md_params* p, const double* q, double* pos, hipStream_t stream)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if (!q || !pos) return fail(MD_ERR_ARG, "q or pos is NULL");
+    if ((const void*)q == (const void*)pos) return fail(MD_ERR_ARG, "q and pos must not alias");
+    MD_HIP(launch_pack(c.g, q, pos, stream), "md_pack_positions");
+    return MD_OK;
+}
+
 int md_bin_cells(const md_params* p, const double* pos, md_cells* cells, void* ws, size_t ws_bytes,
                  hipStream_t stream)
 {
@@ -329,6 +340,33 @@ int md_param_grad(const md_params* p, const double* pos, const md_cells* cells, 
     double* part = (double*)((char*)ws + c.W.part_a);
     MD_HIP(launch_param_grad(c.g, c.lj, pos, cells->cell_xyz, *list, part, stream), "md_param_grad");
     MD_HIP(launch_reduce_pair(part, c.W.nbf, 1.0, 1.0, dU, stream), "md_param_grad/reduce");
+    return MD_OK;
+}
+
+int md_adjoint_kick(const md_params* p, const double* pos, const md_cells* cells, const md_pairlist* list,
+                    const double* u, double* out, double* u_out, const double coef[5], double* acc, void* ws,
+                    size_t ws_bytes, hipStream_t stream)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if (!pos || !u || !out || !coef || !acc) return fail(MD_ERR_ARG, "pos, u, out, coef or acc is NULL");
+    if (u_out && (u_out == u || u_out == out)) return fail(MD_ERR_ARG, "u_out must not alias u or out");
+    if (out == u) return fail(MD_ERR_ARG, "out must not alias u");
+    if ((rc = check_cells(c, cells)) != MD_OK) return rc;
+    if ((rc = check_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
+    AdjCoef k;
+    k.alpha = coef[0];
+    k.beta = coef[1];
+    k.gamma = coef[2];
+    k.cu = coef[3];
+    k.cU = coef[4];
+    k.dt = p->dt;
+    double* part = (double*)((char*)ws + c.W.part_a);
+    MD_HIP(launch_adjoint_kick(c.g, c.lj, pos, cells->cell_xyz, *list, u, out, u_out, k, part, stream),
+           "md_adjoint_kick");
+    MD_HIP(launch_reduce_pair(part, c.W.nbf, 1.0, 1.0, acc, stream, true), "md_adjoint_kick/reduce");
     return MD_OK;
 }
 

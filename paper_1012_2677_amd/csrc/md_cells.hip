@@ -256,6 +256,31 @@ hipError_t launch_resort(const Geo& g, const int32_t* order, const double* pos, 
     return hipGetLastError();
 }
 
+// ---- user [n][3] coordinates -> [n][4] slots, folded into the box ------------
+__device__ __forceinline__ double fold(double x, double L, double invL)
+{
+    double y = x - L * floor(x * invL);
+    if (y >= L) y -= L;
+    if (y < 0.0) y += L;
+    return y;
+}
+
+__global__ __launch_bounds__(kStreamBlock) void k_pack(Geo g, const double* __restrict__ q,
+                                                       double4* __restrict__ pos)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.n) return;
+    pos[i] = make_double4(fold(q[3 * i], g.L[0], g.invL[0]), fold(q[3 * i + 1], g.L[1], g.invL[1]),
+                          fold(q[3 * i + 2], g.L[2], g.invL[2]), 0.0);
+}
+
+hipError_t launch_pack(const Geo& g, const double* q, double* pos, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)ceil_div(g.n, kStreamBlock)), dim3(kStreamBlock), 0, s, g, q,
+                       (double4*)pos);
+    return hipGetLastError();
+}
+
 // ---- reference positions (and local coordinates) without a re-sort ----------
 __global__ __launch_bounds__(kStreamBlock) void k_ref_copy(Geo g, const double4* __restrict__ pos,
                                                            const int32_t* __restrict__ cell_xyz,

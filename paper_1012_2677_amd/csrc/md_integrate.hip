@@ -196,9 +196,10 @@ hipError_t launch_reduce_energy(const double* part_pw, int64_t nbf, const double
     return hipGetLastError();
 }
 
-// out2[k] = scale_k * sum_b part[2b + k]
+// out2[k] = scale_k * sum_b part[2b + k]   (or += when accumulating)
 __global__ __launch_bounds__(kReduceBlock) void k_reduce_pair(const double* __restrict__ part, int64_t nb,
-                                                              double s0, double s1, double* __restrict__ out2)
+                                                              double s0, double s1, double* __restrict__ out2,
+                                                              int accumulate)
 {
     double a = 0.0, b = 0.0;
     for (int64_t k = threadIdx.x; k < nb; k += kReduceBlock) {
@@ -208,15 +209,16 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce_pair(const double* __re
     a = block_sum_1024(a);
     b = block_sum_1024(b);
     if (threadIdx.x == 0) {
-        out2[0] = s0 * a;
-        out2[1] = s1 * b;
+        out2[0] = (accumulate ? out2[0] : 0.0) + s0 * a;
+        out2[1] = (accumulate ? out2[1] : 0.0) + s1 * b;
     }
 }
 
 hipError_t launch_reduce_pair(const double* part, int64_t nb, double scale0, double scale1, double* out2,
-                              hipStream_t s)
+                              hipStream_t s, bool accumulate)
 {
-    hipLaunchKernelGGL(k_reduce_pair, dim3(1), dim3(kReduceBlock), 0, s, part, nb, scale0, scale1, out2);
+    hipLaunchKernelGGL(k_reduce_pair, dim3(1), dim3(kReduceBlock), 0, s, part, nb, scale0, scale1, out2,
+                       accumulate ? 1 : 0);
     return hipGetLastError();
 }
 

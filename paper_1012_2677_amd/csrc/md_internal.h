@@ -132,6 +132,7 @@ hipError_t launch_resort(const Geo& g, const int32_t* order, const double* pos, 
                          const int32_t* id, double* pos_alt, double* vel_alt, int32_t* id_alt,
                          double* pos_ref, float* pos32, int32_t* cell_of, int32_t* cell_xyz,
                          hipStream_t s);
+hipError_t launch_pack(const Geo& g, const double* q, double* pos, hipStream_t s);
 hipError_t launch_ref_copy(const Geo& g, const double* pos, const int32_t* cell_xyz, double* pos_ref,
                            float* pos32, hipStream_t s);
 
@@ -167,7 +168,7 @@ hipError_t launch_integrate(const Geo& g, IntMode mode, const IntArgs& a, hipStr
 hipError_t launch_reduce_energy(const double* part_pw, int64_t nbf, const double* part_ke,
                                 int64_t nbi, double* energy, double* log_row, hipStream_t s);
 hipError_t launch_reduce_pair(const double* part, int64_t nb, double scale0, double scale1,
-                              double* out2, hipStream_t s);
+                              double* out2, hipStream_t s, bool accumulate = false);
 hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags,
                                const double* energy, int64_t* out, hipStream_t s);
 hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t* status, long long* part,
@@ -177,6 +178,12 @@ hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t* s
 hipError_t launch_hvp(const Geo& g, const LJ& lj, const double* pos, const int32_t* cell_xyz,
                       const md_pairlist& list, const double* u, double* Hu, double* part,
                       hipStream_t s);
+struct AdjCoef {
+    double alpha, beta, gamma, cu, cU, dt;
+};
+hipError_t launch_adjoint_kick(const Geo& g, const LJ& lj, const double* pos, const int32_t* cell_xyz,
+                               const md_pairlist& list, const double* u, double* out, double* u_out,
+                               const AdjCoef& k, double* part, hipStream_t s);
 hipError_t launch_param_grad(const Geo& g, const LJ& lj, const double* pos,
                              const int32_t* cell_xyz, const md_pairlist& list, double* part,
                              hipStream_t s);

@@ -116,3 +116,16 @@ def force_error(F, Fref, S):
     """max_i |F_i - Fref_i| / S_i with S_i the sum of pair-force magnitudes on i."""
     err = np.linalg.norm(F - Fref, axis=1)
     return float(np.max(err / np.maximum(S, 1e-300)))
+
+
+def rows_for_slots(plist, slots):
+    """Host copies of the list rows of the given key slots (a device gather of
+    just those rows): returns (key index into `slots`, partner slot, code)."""
+    s = torch.as_tensor(slots, dtype=torch.long, device=plist.offsets.device)
+    off = plist.offsets[s]
+    cnt = plist.counts[s].long()
+    rep = torch.repeat_interleave(torch.arange(s.numel(), device=s.device), cnt)
+    first = torch.cumsum(cnt, 0) - cnt
+    within = torch.arange(rep.numel(), device=s.device) - first[rep]
+    ent = plist.nbr[off[rep] + within].long() & 0xFFFFFFFF
+    return rep.cpu().numpy(), (ent & SLOT_MASK).cpu().numpy(), (ent >> 27).cpu().numpy()

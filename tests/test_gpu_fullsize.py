@@ -1,0 +1,99 @@
+"""Parity at full workload sizes, in the launch configuration the benchmark
+times (re-sort at every rebuild; mixed precision at 32M and 131M, FP64 at 4M),
+on sampled particles the oracle can check one by one:
+
+  * the pair-list rows of the sampled particles equal the oracle's neighbour
+    sets within rs (exact set equality, ids);
+  * the forces on the sampled particles equal the oracle's to the precision
+    bar (1e-5 mixed, 1e-12 FP64, relative to the pair-force scale S_i);
+  * the list's total entry count equals twice the number of pairs implied by
+    the per-particle neighbour counts of the sample (statistical check only).
+
+The state is first advanced some steps (a disordered fluid with several
+rebuilds and re-sorts behind it), then md_prepare rebuilds the list at the
+current positions.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import lj_inputs as li
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _cuda():
+    assert torch.cuda.is_available()
+    import paper_1012_2677_amd  # noqa: F401
+
+
+def _sample_ids(n, k, seed):
+    rng = np.random.default_rng(seed)
+    ids = rng.choice(n, size=k, replace=False)
+    return np.unique(np.concatenate([ids, [0, 1, n - 2, n - 1]])).astype(np.int64)
+
+
+def _check_state(ref, e, L, ids, tol):
+    q = e.positions()
+    nc, _ = ref.cell_dims(L, e.params.rs)
+    _, count, start, order = ref.bin_cells(q, L, nc)
+    grid = (nc, count, start, order)
+    # rows
+    ids_dev = e.id.long()
+    slot_of_id = torch.empty_like(ids_dev)
+    slot_of_id[ids_dev] = torch.arange(e.n, device=ids_dev.device)
+    slots = slot_of_id[torch.as_tensor(ids, device=ids_dev.device)]
+    kidx, pslot, _ = G.rows_for_slots(e.plist, slots)
+    pid = e.id.cpu().numpy()[pslot]
+    ref_rows = ref.neighbors_sample(q, L, ids, rs=e.params.rs, grid=grid)
+    for k in range(len(ids)):
+        got = np.sort(pid[kidx == k])
+        assert np.array_equal(got, ref_rows[k]), (ids[k], len(got), len(ref_rows[k]))
+    # forces
+    F = e.forces()[ids]
+    Fr, S, _, _, nb = ref.forces_sample(q, L, ids, rc=e.params.rc, rs=e.params.rs, grid=grid)
+    err = G.force_error(F, Fr, S)
+    assert err <= tol, err
+    mean_nb = nb.mean()
+    total = int(e.plist.status[0].item())
+    assert abs(total / e.n - mean_nb) < 0.05 * mean_nb
+    return err
+
+
+@pytest.mark.parametrize("config,precision,tol,steps", [
+    ("lj32m", "mixed", 1e-5, 40),
+    ("lj4m", "fp64", 1e-12, 40),
+])
+def test_full_size_sampled_parity(ref, config, precision, tol, steps):
+    from paper_1012_2677_amd import Engine
+
+    cfg = li.CONFIGS[config]
+    q, L = li.fcc_lattice(cfg["n_fcc"])
+    v = li.maxwell_boltzmann(q.shape[0], cfg["T"], seed=0)
+    n = q.shape[0]
+    e = Engine(q, v, L, rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], dt=cfg["dt"], precision=precision,
+               resort_every=1, device="cuda:0")
+    del q, v
+    e.step(steps)
+    assert e.rebuilds > 3
+    e.prepare()
+    _check_state(ref, e, L, _sample_ids(n, 2048, 1), tol)
+
+
+def test_largest_workload_sampled_parity(ref):
+    """131,072,000 particles (the largest single-GPU workload), mixed."""
+    from paper_1012_2677_amd import Engine
+
+    cfg = li.CONFIGS["lj131m"]
+    q, L = li.fcc_lattice(cfg["n_fcc"])
+    v = li.maxwell_boltzmann(q.shape[0], cfg["T"], seed=0)
+    n = q.shape[0]
+    e = Engine(q, v, L, rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], dt=cfg["dt"], precision="mixed",
+               resort_every=1, device="cuda:0")
+    del q, v
+    e.step(12)
+    e.prepare()
+    _check_state(ref, e, L, _sample_ids(n, 1024, 2), 1e-5)
