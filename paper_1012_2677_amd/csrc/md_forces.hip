@@ -76,9 +76,21 @@ __device__ __forceinline__ void block_partial2(double a, double b, double* part,
     }
 }
 
-// Row walk shared by both precisions: lane `sub` of the group handles entries
-// sub, sub + G, ...; U entries per lane are fetched before any is used, so each
-// lane keeps U index loads and then U position gathers in flight at once.
+// Row walk shared by both precisions.  Lane `sub` of a key's group handles
+// entries sub, sub + G, ... of the row.  The wave walks the rows of its keys
+// in lockstep up to the longest one (a wave-uniform bound), U entries per lane
+// at a time: the U index loads are issued, then the U position gathers, then
+// the U pair terms are evaluated.  Unroll slots that no lane of the wave needs
+// are skipped by a uniform branch; inside a slot, lanes past the end of their
+// row load nothing and use a stand-in partner placed beyond the cutoff.
+// maximum over the wave, returned as a wave-uniform (scalar) value
+__device__ __forceinline__ int wave_max_i32(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 template <int G, int U, bool ENERGY>
 __global__ __launch_bounds__(kForceBlock) void k_forces_fp64(ForceArgs a)
 {
@@ -102,7 +114,8 @@ __global__ __launch_bounds__(kForceBlock) void k_forces_fp64(ForceArgs a)
     const double rc2 = a.lj.rc2, A = a.lj.A, B = a.lj.B, C8 = a.lj.C8;
     double fx = 0.0, fy = 0.0, fz = 0.0, pe = 0.0, w = 0.0;
     const uint32_t* row = a.nbr + off;
-    for (int t0 = sub; t0 < cnt; t0 += G * U) {
+    const int cmax = wave_max_i32(cnt);
+    for (int t0 = sub; t0 - sub < cmax; t0 += G * U) {
         uint32_t e[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -112,30 +125,37 @@ __global__ __launch_bounds__(kForceBlock) void k_forces_fp64(ForceArgs a)
         double4 pj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (e[u] != 0xFFFFFFFFu) pj[u] = a.pos[e[u] & kSlotMask];
-            else pj[u] = make_double4(xi + 1.0e3, yi, zi, 0.0);
+            if (t0 - sub + u * G < cmax) {
+                // stand-in for masked slots: half a box away along x, which the
+                // minimum image leaves in place (rint(1/2) = 0) and which is
+                // beyond rs because every axis has at least three cells
+                if (e[u] != 0xFFFFFFFFu) pj[u] = a.pos[e[u] & kSlotMask];
+                else pj[u] = make_double4(xi + 0.5 * a.L[0], yi, zi, 0.0);
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            double dx = pj[u].x - xi, dy = pj[u].y - yi, dz = pj[u].z - zi;
-            if (minimg) {
-                dx -= a.L[0] * rint(dx * a.invL[0]);
-                dy -= a.L[1] * rint(dy * a.invL[1]);
-                dz -= a.L[2] * rint(dz * a.invL[2]);
-            }
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double r2i = rcp64(r2);
-            const double r6i = r2i * r2i * r2i;
-            double g = r2i * r6i * (A * r6i - B) - C8;
-            const bool in = r2 < rc2 && e[u] != 0xFFFFFFFFu;
-            g = in ? g : 0.0;
-            fx -= g * dx;
-            fy -= g * dy;
-            fz -= g * dz;
-            if (ENERGY) {
-                const double V = r6i * (a.lj.A4 * r6i - a.lj.B4) + a.lj.C2 * r2 + a.lj.C0;
-                pe += in ? V : 0.0;
-                w += g * r2;
+            if (t0 - sub + u * G < cmax) {
+                double dx = pj[u].x - xi, dy = pj[u].y - yi, dz = pj[u].z - zi;
+                if (minimg) {
+                    dx -= a.L[0] * rint(dx * a.invL[0]);
+                    dy -= a.L[1] * rint(dy * a.invL[1]);
+                    dz -= a.L[2] * rint(dz * a.invL[2]);
+                }
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double r2i = rcp64(r2);
+                const double r6i = r2i * r2i * r2i;
+                double g = r2i * r6i * (A * r6i - B) - C8;
+                const bool in = r2 < rc2;
+                g = in ? g : 0.0;
+                fx -= g * dx;
+                fy -= g * dy;
+                fz -= g * dz;
+                if (ENERGY) {
+                    const double V = r6i * (a.lj.A4 * r6i - a.lj.B4) + a.lj.C2 * r2 + a.lj.C0;
+                    pe += in ? V : 0.0;
+                    w += g * r2;
+                }
             }
         }
     }
@@ -158,14 +178,13 @@ __global__ __launch_bounds__(kForceBlock) void k_forces_fp64(ForceArgs a)
 template <int G, int U, bool ENERGY>
 __global__ __launch_bounds__(kForceBlock) void k_forces_mixed(ForceArgs a)
 {
-    __shared__ float4 s_shift[28];
-    if (threadIdx.x < 28) {
-        // code 27 never occurs in an entry: it is the far-away dummy used for
-        // the unused unrolled slots of a row
-        s_shift[threadIdx.x] = threadIdx.x < 27
-                                   ? make_float4(a.shift[threadIdx.x][0], a.shift[threadIdx.x][1],
-                                                 a.shift[threadIdx.x][2], 0.0f)
-                                   : make_float4(1.0e3f, 0.0f, 0.0f, 0.0f);
+    __shared__ float4 s_shift[32];
+    if (threadIdx.x < 32) {
+        // code 27 never occurs in an entry: it is the stand-in used for
+        // masked slots, displaced far beyond the cutoff
+        s_shift[threadIdx.x] = threadIdx.x < 27 ? make_float4(a.shift[threadIdx.x][0], a.shift[threadIdx.x][1],
+                                                              a.shift[threadIdx.x][2], 0.0f)
+                                                : make_float4(1.0e3f, 0.0f, 0.0f, 0.0f);
     }
     __syncthreads();
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -184,9 +203,9 @@ __global__ __launch_bounds__(kForceBlock) void k_forces_mixed(ForceArgs a)
     float fx = 0.f, fy = 0.f, fz = 0.f;
     double pe = 0.0, w = 0.0;
     const uint32_t* row = a.nbr + off;
-    // the dummy entry points at the key itself with code 27 (displacement 1e3)
     const uint32_t dummy = (uint32_t)(valid ? key : 0) | (27u << kCodeShift);
-    for (int t0 = sub; t0 < cnt; t0 += G * U) {
+    const int cmax = wave_max_i32(cnt);
+    for (int t0 = sub; t0 - sub < cmax; t0 += G * U) {
         uint32_t e[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -195,27 +214,30 @@ __global__ __launch_bounds__(kForceBlock) void k_forces_mixed(ForceArgs a)
         }
         float4 pj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) pj[u] = a.pos32[e[u] & kSlotMask];
+        for (int u = 0; u < U; ++u)
+            if (t0 - sub + u * G < cmax) pj[u] = a.pos32[e[u] & kSlotMask];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const float4 sh = s_shift[e[u] >> kCodeShift];
-            const float dx = (pj[u].x - li.x) + sh.x;
-            const float dy = (pj[u].y - li.y) + sh.y;
-            const float dz = (pj[u].z - li.z) + sh.z;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float r2i = __builtin_amdgcn_rcpf(r2);
-            const float r6i = r2i * r2i * r2i;
-            float g = r2i * r6i * (A * r6i - B) - C8;
-            const bool in = r2 < rc2;
-            g = in ? g : 0.0f;
-            fx -= g * dx;
-            fy -= g * dy;
-            fz -= g * dz;
-            if (ENERGY) {
-                const float V = r6i * ((float)a.lj.A4 * r6i - (float)a.lj.B4) + (float)a.lj.C2 * r2 +
-                                (float)a.lj.C0;
-                pe += in ? (double)V : 0.0;
-                w += (double)(g * r2);
+            if (t0 - sub + u * G < cmax) {
+                const float4 sh = s_shift[e[u] >> kCodeShift];
+                const float dx = (pj[u].x - li.x) + sh.x;
+                const float dy = (pj[u].y - li.y) + sh.y;
+                const float dz = (pj[u].z - li.z) + sh.z;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float r2i = __builtin_amdgcn_rcpf(r2);
+                const float r6i = r2i * r2i * r2i;
+                float g = r2i * r6i * (A * r6i - B) - C8;
+                const bool in = r2 < rc2;
+                g = in ? g : 0.0f;
+                fx -= g * dx;
+                fy -= g * dy;
+                fz -= g * dz;
+                if (ENERGY) {
+                    const float V = r6i * ((float)a.lj.A4 * r6i - (float)a.lj.B4) + (float)a.lj.C2 * r2 +
+                                    (float)a.lj.C0;
+                    pe += in ? (double)V : 0.0;
+                    w += (double)(g * r2);
+                }
             }
         }
     }
@@ -267,7 +289,7 @@ hipError_t launch_forces(const Geo& g, const LJ& lj, int precision, const double
     a.flags = out.flags;
     const dim3 grid((unsigned)a.nblocks), block(kForceBlock);
     const bool energy = out.part != nullptr;
-    constexpr int G = kLanesPerKey, U = kForceUnroll;
+    constexpr int G = kLanesPerKey, U = kForceUnroll, U64 = kForceUnroll64;
     if (precision == MD_MIXED) {
         if (energy)
             hipLaunchKernelGGL((k_forces_mixed<G, U, true>), grid, block, 0, s, a);
@@ -275,9 +297,9 @@ hipError_t launch_forces(const Geo& g, const LJ& lj, int precision, const double
             hipLaunchKernelGGL((k_forces_mixed<G, U, false>), grid, block, 0, s, a);
     } else {
         if (energy)
-            hipLaunchKernelGGL((k_forces_fp64<G, U, true>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_forces_fp64<G, U64, true>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL((k_forces_fp64<G, U, false>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_forces_fp64<G, U64, false>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }

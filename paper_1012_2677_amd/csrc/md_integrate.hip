@@ -36,22 +36,40 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
     const int64_t n = g.n;
     const bool valid = i < n;
     const double h = 0.5 * a.dt;
+    constexpr bool DRIFT = MODE == INT_KD || MODE == INT_KKD;
+    double* __restrict__ vel = a.vel;
+    double4* __restrict__ P = (double4*)a.pos;
+    const double* __restrict__ ref = a.pos_ref;
     double ke = 0.0, d2 = 0.0;
     if (valid) {
-        double vx = a.vel[i], vy = a.vel[n + i], vz = a.vel[2 * n + i];
+        // every input is loaded before anything is stored, so all loads of a
+        // thread are in flight together
+        double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
         double fx = 0.0, fy = 0.0, fz = 0.0;
         if (MODE != INT_KE) {
             if (MIXED) {
-                const float* F = (const float*)a.force;
+                const float* __restrict__ F = (const float*)a.force;
                 fx = F[i];
                 fy = F[n + i];
                 fz = F[2 * n + i];
             } else {
-                const double* F = (const double*)a.force;
+                const double* __restrict__ F = (const double*)a.force;
                 fx = F[i];
                 fy = F[n + i];
                 fz = F[2 * n + i];
             }
+        }
+        double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
+        double rx = 0.0, ry = 0.0, rz = 0.0;
+        int32_t c = 0;
+        if (DRIFT) {
+            p = P[i];
+            rx = ref[i];
+            ry = ref[n + i];
+            rz = ref[2 * n + i];
+            if (MIXED) c = a.cell_xyz[i];
+        }
+        if (MODE != INT_KE) {
             vx = vx + h * fx;
             vy = vy + h * fy;
             vz = vz + h * fz;
@@ -62,20 +80,17 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
             vy = vy + h * fy;
             vz = vz + h * fz;
         }
-        if (MODE == INT_KD || MODE == INT_KKD) {
-            double4* P = (double4*)a.pos;
-            double4 p = P[i];
+        if (DRIFT) {
             p.x = wrap_coord(p.x + a.dt * vx, g.L[0], g.invL[0]);
             p.y = wrap_coord(p.y + a.dt * vy, g.L[1], g.invL[1]);
             p.z = wrap_coord(p.z + a.dt * vz, g.L[2], g.invL[2]);
-            P[i] = p;
-            double ex = p.x - a.pos_ref[i], ey = p.y - a.pos_ref[n + i], ez = p.z - a.pos_ref[2 * n + i];
+            double ex = p.x - rx, ey = p.y - ry, ez = p.z - rz;
             ex -= g.L[0] * rint(ex * g.invL[0]);
             ey -= g.L[1] * rint(ey * g.invL[1]);
             ez -= g.L[2] * rint(ez * g.invL[2]);
             d2 = ex * ex + ey * ey + ez * ez;
+            P[i] = p;
             if (MIXED) {
-                const int32_t c = a.cell_xyz[i];
                 ((float4*)a.pos32)[i] =
                     make_float4(local_coord_i(p.x, c & 1023, g.cs[0], g.L[0], g.invL[0]),
                                 local_coord_i(p.y, (c >> 10) & 1023, g.cs[1], g.L[1], g.invL[1]),
@@ -83,13 +98,13 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
             }
         }
         if (MODE != INT_KE) {
-            a.vel[i] = vx;
-            a.vel[n + i] = vy;
-            a.vel[2 * n + i] = vz;
+            vel[i] = vx;
+            vel[n + i] = vy;
+            vel[2 * n + i] = vz;
         }
     }
     __shared__ double s_v[kStreamBlock / 64];
-    if (MODE == INT_KD || MODE == INT_KKD) {
+    if (DRIFT) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) d2 = fmax(d2, __shfl_xor(d2, o, 64));
         if ((threadIdx.x & 63) == 0) s_v[threadIdx.x >> 6] = d2;

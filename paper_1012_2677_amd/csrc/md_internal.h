@@ -21,10 +21,14 @@ constexpr int kForceBlock = 256;         // force / adjoint kernels
 #define MD_LANES_PER_KEY 8
 #endif
 #ifndef MD_FORCE_UNROLL
-#define MD_FORCE_UNROLL 4
+#define MD_FORCE_UNROLL 8
+#endif
+#ifndef MD_FORCE_UNROLL_FP64
+#define MD_FORCE_UNROLL_FP64 4
 #endif
 constexpr int kLanesPerKey = MD_LANES_PER_KEY;   // lanes cooperating on one key's row
-constexpr int kForceUnroll = MD_FORCE_UNROLL;    // row entries in flight per lane
+constexpr int kForceUnroll = MD_FORCE_UNROLL;    // row entries in flight per lane (FP32 pair terms)
+constexpr int kForceUnroll64 = MD_FORCE_UNROLL_FP64;  // same for FP64 pair terms (register bound)
 constexpr int kKeysPerBlock = kForceBlock / kLanesPerKey;
 constexpr int kBuildChunks = 8;          // candidates held in registers: 8 x 64
 constexpr int kReduceBlock = 1024;
