@@ -15,8 +15,10 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -24,6 +26,9 @@ import numpy as np
 
 METRIC = "particle-steps/s, 32M-atom LJ NVE: FP64 vs FP32/FP64 mixed at stated drift"
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+# sources that define the force kernels; a counter record is used only while they are unchanged
+FORCE_SOURCES = ("paper_1012_2677_amd/csrc/md_forces.hip", "paper_1012_2677_amd/csrc/md_internal.h")
 
 
 def log(*a):
@@ -31,12 +36,67 @@ def log(*a):
 
 
 def force_bytes_per_key(mean_entries: float, mixed: bool) -> float:
-    """Algorithmic HBM bytes of one force-kernel key: row offset (8) + row length
-    (4) + 4 bytes per list entry + the key's own position (16 B FP32 local
-    coordinates in mixed mode, 32 B FP64 in FP64 mode) + the force written
-    (12 B FP32 / 24 B FP64).  Partner positions are re-reads of positions that
-    are counted once as keys."""
-    return 8 + 4 + 4 * mean_entries + (16 if mixed else 32) + (12 if mixed else 24)
+    """Algorithmic HBM bytes of one key in the timed force pass, which inside a
+    run is fused with the integrator (second half kick, next first half kick,
+    drift): row offset (8) + row length (4) + 4 bytes per list entry + the
+    key's own coordinates (FP32 local 16 B in mixed mode; FP64 32 B plus its
+    4 B packed cell in FP64 mode) + the integrator's streams: velocity read and
+    write (48), reference position (24), position written (32; mixed mode also
+    reads the FP64 position, 32, its packed cell, 4, and writes new local
+    coordinates, 16).  Partner coordinates are re-reads of coordinates counted
+    once as keys."""
+    idx = 8 + 4 + 4 * mean_entries
+    if mixed:
+        return idx + 16 + 32 + 4 + 48 + 24 + 32 + 16
+    return idx + 32 + 4 + 48 + 24 + 32
+
+
+def force_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for rel in FORCE_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed rocprofv3
+    counter record (profiles/<kernel>_<workload>_hbm_traffic.md): FETCH_SIZE and
+    WRITE_SIZE in KiB per dispatch, each scaled by what the counter reads for a
+    plain copy of known size.  None when there is no record or the force-kernel
+    sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None, "no counter record"
+    with open(path) as f:
+        m = re.search(r"^traffic: (.*)$", f.read(), re.M)
+    if not m:
+        return None, "counter record has no traffic line"
+    kv = dict(item.split("=", 1) for item in m.group(1).split())
+    if kv.get("source_sha256") != force_sources_sha256():
+        return None, "force kernel changed since the counters were taken"
+    b = (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) + float(kv["write_kib"]) * float(kv["write_scale"])) * 1024
+    return b, path
+
+
+def copy_bandwidth(nbytes: int = 4 << 30, reps: int = 10):
+    """Achievable HBM bandwidth: a plain device-to-device copy of nbytes (reads
+    nbytes, writes nbytes), timed with events on the current stream."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * nbytes, "ms": ms, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
 def drift_per_1000(steps_axis, e_per_particle):
@@ -71,11 +131,20 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed):
         e.timers.ms[k] = 0.0
         e.timers.launches[k] = 0
     reb0 = e.rebuilds
+    # the paper's own protocol also reports the rate after its first 150 steps
+    split = 150 if steps >= 300 and steps % sample_every == 0 and 150 % sample_every == 0 else 0
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    elog = e.step(steps, sample_every=sample_every)
+    if split:
+        elog0 = e.step(split, sample_every=sample_every)
+        torch.cuda.synchronize()
+        t_split = time.perf_counter()
+        elog = np.concatenate([elog0, e.step(steps - split, sample_every=sample_every)])
+    else:
+        elog = e.step(steps, sample_every=sample_every)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    dt = t2 - t1
     entries = int(e.plist.status[0].item())
     tim = e.timer_dict()
     rebuilds = e.rebuilds - reb0
@@ -97,6 +166,8 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed):
         "drift_per_1000_steps": drift_per_1000(axis, e_pp),
         "max_abs_energy_change": float(np.abs(e_pp - e0[3] / n).max()) if len(e_pp) else None,
         "temperature_end": float(2.0 * elog[-1, 0] / (3.0 * (n - 1))) if len(elog) else None,
+        "value_after_step_150": n * (steps - split) / (t2 - t_split) if split else None,
+        "hbm_footprint_bytes": int(torch.cuda.max_memory_allocated()),
     }
     fm, fl = tim.get("force", (0.0, 0))
     if fl > 0:
@@ -107,6 +178,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed):
                                "achieved_GBs": gbs}
     del e
     torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
     return out
 
 
@@ -123,7 +195,7 @@ def cpu_baseline(cfg, seconds_target=15.0):
     t0 = time.perf_counter()
     oracle.run(q, v, L, 2, dt=cfg["dt"], rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], sample_every=0)
     per_step = (time.perf_counter() - t0) / 2.0
-    k = max(2, min(60, int(seconds_target / max(per_step, 1e-3))))
+    k = max(2, min(200, int(seconds_target / max(per_step, 1e-3))))
     t0 = time.perf_counter()
     oracle.run(q, v, L, k, dt=cfg["dt"], rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], sample_every=0)
     dt = time.perf_counter() - t0
@@ -138,11 +210,13 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="lj32m")
-    ap.add_argument("--sample-every", type=int, default=100)
+    ap.add_argument("--sample-every", type=int, default=50)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--modes", default=None, help="comma list of precisions to run (default mixed,fp64)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (the reference kernel for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how the "
@@ -153,6 +227,9 @@ def main():
 
     import lj_inputs as li
 
+    if args.calibrate_copy:
+        print(json.dumps({"calibrate_copy": copy_bandwidth(1 << 30, 3)}), flush=True)
+        return
     cfg = dict(li.CONFIGS[args.config])
     headline = cfg["precision"]
     modes = args.modes.split(",") if args.modes else ([headline] + ([] if args.no_fp64 else
@@ -164,13 +241,22 @@ def main():
     head = results[modes[0]]
     n = head["n"]
     fk = head.get("force_kernel")
+    copy = copy_bandwidth()
+    log(f"[bench] plain copy: {copy['GBs']:.0f} GB/s")
     roofline = None
     if fk:
+        kname = "k_pairs_mixed" if modes[0] == "mixed" else "k_pairs_fp64"
+        traffic, tsrc = counter_traffic(kname, args.config)
         roofline = {"bound": "hbm", "achieved": round(fk["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(fk["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": "k_forces_mixed" if modes[0] == "mixed" else "k_forces_fp64",
+                    "unit": "GB/s", "frac": round(fk["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                    "traffic": None if traffic is None else round(traffic / (fk["avg_ms"] * 1e-3) / 1e9, 1),
+                    "traffic_bytes_per_launch": None if traffic is None else int(traffic),
+                    "traffic_source": tsrc,
+                    "kernel": kname,
                     "avg_launch_ms": round(fk["avg_ms"], 4),
-                    "algorithmic_bytes_per_launch": int(fk["algorithmic_bytes_per_launch"])}
+                    "algorithmic_bytes_per_launch": int(fk["algorithmic_bytes_per_launch"]),
+                    "achievable_copy_GBs": round(copy["GBs"], 1),
+                    "frac_of_achievable": round(fk["achieved_GBs"] / copy["GBs"], 4)}
     cpu = None if args.no_cpu else cpu_baseline(cfg)
     line = {
         "metric": METRIC,

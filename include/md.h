@@ -131,11 +131,19 @@ typedef struct md_timers {
 } md_timers;
 
 /* Whole simulation state for md_prepare / md_step / md_energy.
- *   pos, vel, id: current arrays; pos_alt, vel_alt, id_alt: targets of the
- *   re-sort, swapped with the current ones by the library (read the pointers
- *   back after a call).  pos_ref: device double[3][n], positions at the last
- *   build.  pos32: device float[n][4], MD_MIXED only: coordinates relative to
- *   each slot's cell corner at the last build (NULL in MD_FP64).
+ *   pos, vel, id: current arrays; pos_alt, vel_alt, id_alt: second buffers,
+ *   swapped with the current ones by the library (read the pointers back
+ *   after a call).  The re-sort writes all three; in MD_FP64 md_step also
+ *   writes each step's drifted positions to pos_alt (the force pass still
+ *   reads the old ones), so pos_alt is required in MD_FP64 and vel_alt /
+ *   id_alt only when resort_every > 0.  pos_ref: device double[3][n],
+ *   positions at the last build.  pos32, pos32_alt: device float[n][4],
+ *   MD_MIXED only (NULL in MD_FP64): coordinates relative to each slot's cell
+ *   corner at the last build, and the second buffer md_step writes the
+ *   drifted coordinates to (swapped like pos / pos_alt).
+ *   force: after md_prepare, md_energy and at the end of md_step, the forces
+ *   at the current positions; inside a run they are consumed by the fused
+ *   kicks and not stored.
  *   energy: device double[8]: KE, PE, W, E at the last sampled step, then
  *   max squared displacement, reserved.
  *   flags: device int64[8]: [0] non-finite force seen, others reserved.
@@ -150,6 +158,7 @@ typedef struct md_state {
     void*     force;
     double*   pos_ref;
     float*    pos32;
+    float*    pos32_alt;
     int32_t*  id;
     double*   pos_alt;
     double*   vel_alt;
@@ -228,6 +237,8 @@ int md_prepare(const md_params* p, md_state* st, hipStream_t stream);
 /* nsteps of velocity Verlet (kick-drift-kick, unit mass; Sec. 4.5):
  *   v += (dt/2) F;  q = wrap(q + dt v);  [rebuild if max displacement since
  *   the last build exceeds (rs - rc)/2];  F = F(q);  v += (dt/2) F.
+ * Inside a run the second half kick, the next step's first half kick and its
+ * drift run in the force pass (two separate roundings for the two kicks).
  * Every sample_every steps (counted from st->step) the row
  * energy_log[k][0..3] = (KE, PE, W, KE + PE) is written (device double
  * array; NULL to skip; sample_every <= 0 samples nothing).  Synchronises once

@@ -63,7 +63,7 @@ class MdTimers(C.Structure):
 
 class MdState(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("vel", C.c_void_p), ("force", C.c_void_p), ("pos_ref", C.c_void_p),
-                ("pos32", C.c_void_p), ("id", C.c_void_p), ("pos_alt", C.c_void_p), ("vel_alt", C.c_void_p),
+                ("pos32", C.c_void_p), ("pos32_alt", C.c_void_p), ("id", C.c_void_p), ("pos_alt", C.c_void_p), ("vel_alt", C.c_void_p),
                 ("id_alt", C.c_void_p), ("cells", MdCells), ("list", MdPairlist), ("energy", C.c_void_p),
                 ("flags", C.c_void_p), ("host_scratch", C.c_void_p), ("ws", C.c_void_p),
                 ("ws_bytes", C.c_size_t), ("timers", C.POINTER(MdTimers)), ("step", C.c_int64),

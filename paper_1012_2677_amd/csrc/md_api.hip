@@ -307,7 +307,7 @@ int md_forces(const md_params* p, const double* pos, const md_cells* cells, cons
     out.flags = (int64_t*)(w + c.W.scal) + 2;
     MD_HIP(launch_forces(c.g, c.lj, p->precision, pos, pos32, cells->cell_xyz, *list, out, stream),
            "md_forces");
-    if (pe_w) MD_HIP(launch_reduce_pair(out.part, c.W.nbf, 1.0, 1.0, pe_w, stream), "md_forces/reduce");
+    if (pe_w) MD_HIP(launch_reduce_pair(out.part, pair_blocks(c.g), 1.0, 1.0, pe_w, stream), "md_forces/reduce");
     return MD_OK;
 }
 
@@ -378,7 +378,9 @@ static int check_state(const Ctx& c, const md_params* p, md_state* st)
     if (!st) return fail(MD_ERR_ARG, "state is NULL");
     if (!st->pos || !st->vel || !st->force || !st->pos_ref || !st->id || !st->energy || !st->flags)
         return fail(MD_ERR_ARG, "state has a NULL array");
-    if (p->precision == MD_MIXED && !st->pos32) return fail(MD_ERR_ARG, "mixed precision needs pos32");
+    if (p->precision == MD_MIXED && (!st->pos32 || !st->pos32_alt))
+        return fail(MD_ERR_ARG, "mixed precision needs pos32 and pos32_alt");
+    if (p->precision == MD_FP64 && !st->pos_alt) return fail(MD_ERR_ARG, "FP64 needs pos_alt");
     if (p->resort_every > 0 && (!st->pos_alt || !st->vel_alt || !st->id_alt))
         return fail(MD_ERR_ARG, "re-sorting needs pos_alt, vel_alt and id_alt");
     int rc = check_cells(c, &st->cells);
@@ -518,7 +520,7 @@ int md_prepare(const md_params* p, md_state* st, hipStream_t s)
     if ((rc = force_eval(c, p, st, true, T, s)) != MD_OK) return rc;
     IntArgs a = int_args(c, p, st, true);
     MD_HIP(launch_integrate(c.g, INT_KE, a, s), "prepare/ke");
-    MD_HIP(launch_reduce_energy((double*)((char*)st->ws + c.W.part_a), c.W.nbf,
+    MD_HIP(launch_reduce_energy((double*)((char*)st->ws + c.W.part_a), pair_blocks(c.g),
                                 (double*)((char*)st->ws + c.W.part_b), c.W.nbi, st->energy, nullptr, s),
            "prepare/reduce");
     if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
@@ -540,7 +542,7 @@ int md_energy(const md_params* p, md_state* st, double* out, hipStream_t s)
     if ((rc = force_eval(c, p, st, true, T, s)) != MD_OK) return rc;
     IntArgs a = int_args(c, p, st, true);
     MD_HIP(launch_integrate(c.g, INT_KE, a, s), "energy/ke");
-    MD_HIP(launch_reduce_energy((double*)((char*)st->ws + c.W.part_a), c.W.nbf,
+    MD_HIP(launch_reduce_energy((double*)((char*)st->ws + c.W.part_a), pair_blocks(c.g),
                                 (double*)((char*)st->ws + c.W.part_b), c.W.nbi, st->energy, out, s),
            "energy/reduce");
     return MD_OK;
@@ -597,18 +599,38 @@ int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_eve
             }
             st->list_valid = 1;
         }
-        if ((rc = force_eval(c, p, st, sample, T, s)) != MD_OK) return rc;
-        // second half kick of this step, fused with the next step's first half
-        // kick and drift unless this is the last step of the call
+        // force pass with the second half kick of this step, fused with the
+        // next step's first half kick and drift unless this is the last step
+        // of the call (then the force is stored for the next call)
         const bool last = done + 1 == nsteps;
-        IntArgs a = int_args(c, p, st, sample);
-        MD_HIP(launch_fill_i32((int32_t*)(st->energy + 4), 0, 2, s), "step/maxd2");
-        tick(T, MD_T_INTEGRATE, 0, s);
-        MD_HIP(launch_integrate(c.g, last ? INT_K : INT_KKD, a, s), "step/kick");
-        tick(T, MD_T_INTEGRATE, 1, s);
+        const bool mixed = p->precision == MD_MIXED;
+        StepIo io;
+        io.pos = st->pos;
+        io.pos32 = mixed ? st->pos32 : nullptr;
+        io.cell_xyz = st->cells.cell_xyz;
+        io.list = st->list;
+        io.force = st->force;
+        io.part_pw = sample ? part_pw : nullptr;
+        io.part_ke = sample ? part_ke : nullptr;
+        io.flags = st->flags;
+        io.vel = st->vel;
+        io.pos_ref = st->pos_ref;
+        io.pos_out = mixed ? st->pos : st->pos_alt;
+        io.pos32_out = mixed ? st->pos32_alt : nullptr;
+        io.max_d2 = (unsigned long long*)(st->energy + 4);
+        io.dt = p->dt;
+        io.drift = !last;
+        if (!last) MD_HIP(launch_fill_i32((int32_t*)(st->energy + 4), 0, 2, s), "step/maxd2");
+        tick(T, MD_T_FORCE, 0, s);
+        MD_HIP(launch_force_step(c.g, c.lj, p->precision, io, s), "step/force");
+        tick(T, MD_T_FORCE, 1, s);
+        if (!last) {
+            if (mixed) std::swap(st->pos32, st->pos32_alt);
+            else std::swap(st->pos, st->pos_alt);
+        }
         if (sample) {
             tick(T, MD_T_REDUCE, 0, s);
-            MD_HIP(launch_reduce_energy(part_pw, c.W.nbf, part_ke, c.W.nbi, st->energy,
+            MD_HIP(launch_reduce_energy(part_pw, pair_blocks(c.g), part_ke, pair_blocks(c.g), st->energy,
                                         energy_log ? energy_log + 4 * k_log : nullptr, s),
                    "step/reduce");
             tick(T, MD_T_REDUCE, 1, s);

@@ -1,13 +1,23 @@
-// Force / energy / virial kernel (Sec. 3.1-3.2 force loop over a key-sorted
-// list; Sec. 2.4: the key particle's position and force stay in registers).
+// Pair-force kernels: force / energy / virial over the key-sorted list
+// (Sec. 3.1-3.2 force loop; Sec. 2.4: the key's position and force stay in
+// registers while its row is walked), optionally fused with the velocity-Verlet
+// kicks and drift that consume the force (Sec. 4.5 integrator).
 //
-// kLanesPerKey lanes share one key's row: lane t of the group takes entries
-// t, t + G, t + 2G, ... of the row, so the group reads the row as one
-// contiguous run and the rows of consecutive keys (consecutive slots, hence
-// neighbouring cells after the re-sort) follow each other in memory.  Every
-// listed pair is evaluated; pairs with r >= rc are zeroed by a select rather
-// than a branch (Sec. 3.1).  Per-lane partial sums are combined with
-// cross-lane shuffles inside the group, and one lane writes the force.
+// Work layout.  A wave owns 64 consecutive keys: lane L owns key base + L for
+// everything that is per key (row bounds, own coordinates, the force it ends
+// with and the integrator epilogue, all coalesced).  The pair work runs in
+// 8 rounds: in round r the 8 lanes of group q (lanes 8q .. 8q+7) walk the row of
+// key base + 8r + q together, lane j of the group taking entries j, j+8, ...
+// so each group reads its row as one contiguous run and a round covers 8
+// consecutive keys (consecutive rows; partners in the same few cells).  The wave walks the 8 rows
+// of a round in lockstep up to the longest (a wave-uniform bound), U entries
+// per lane at a time: U index loads, then U position gathers, then U pair terms.
+// Unroll slots no lane needs are skipped by a uniform branch; lanes past the
+// end of their row use a stand-in partner beyond the cutoff.  Every listed pair
+// is evaluated and pairs with r >= rc are zeroed by a select, not a branch
+// (Sec. 3.1).  A group's partial sums are combined with DPP lane moves, leaving
+// the key's force in every lane of the group; lane 8r + q fetches it with one
+// cross-lane permute, so after the rounds lane L holds the force of key base + L.
 //
 // FP64 mode: displacements from absolute FP64 positions, with the minimum
 // image taken only for keys in boundary cells (elsewhere no partner can wrap).
@@ -16,30 +26,41 @@
 // the FP32 displacement never suffers the cancellation of absolute FP32
 // coordinates.  Forces are accumulated per key in FP32; PE and W in FP64.
 //
-// The kernel is bound by HBM bandwidth (list indices dominate the traffic)
-// with the FP64 arithmetic close behind.
+// Integrator epilogue (MODE_KICK: second half kick; MODE_KKD: second half kick,
+// next step's first half kick and drift, as two separate roundings): positions
+// move only after every wave has read them, so the drifted coordinates the
+// other waves still gather go to a second buffer (FP64 positions in FP64 mode,
+// local coordinates in mixed mode) that the caller swaps in afterwards.
 
 #include "md_internal.h"
 
 namespace md {
 
-struct ForceArgs {
-    const double4* pos;
-    const float4* pos32;
+enum PairMode { MODE_FORCE = 0, MODE_KICK = 1, MODE_KKD = 2 };
+
+struct PairArgs {
+    const double4* pos;        // positions (partners and keys)
+    const float4* pos32;       // mixed: local coordinates (partners and keys)
     const int32_t* cell_xyz;
     const int64_t* offsets;
     const int32_t* counts;
     const uint32_t* nbr;
     int64_t n;
-    int64_t nblocks;
-    double L[3], invL[3];
+    double L[3], invL[3], cs[3];
     int32_t nc[3];
     int32_t exact_all;
     LJ lj;
-    float shift[27][4];   // s * cs per stencil code (mixed mode)
-    void* force;
-    double* part;
-    int64_t* flags;
+    float shift[27][4];        // s * cs per stencil code (mixed mode)
+    void* force;               // [3][n]; written unless MODE_KKD
+    double* part_pw;           // per-block (PE, W) partials (ENERGY)
+    double* part_ke;           // per-block KE partials (ENERGY, MODE_KICK / MODE_KKD)
+    int64_t* flags;            // [0] |= 1 on a non-finite force
+    double* vel;               // [3][n], updated in place (MODE_KICK / MODE_KKD)
+    const double* pos_ref;     // [3][n], positions at the last build (MODE_KKD)
+    double4* pos_out;          // positions after the drift (MODE_KKD; FP64: other buffer)
+    float4* pos32_out;         // mixed: local coordinates after the drift (other buffer)
+    unsigned long long* max_d2;  // atomic max of squared displacement bits (MODE_KKD)
+    double dt;
 };
 
 __device__ __forceinline__ bool boundary_cell(int32_t c, const int32_t* nc)
@@ -48,137 +69,265 @@ __device__ __forceinline__ bool boundary_cell(int32_t c, const int32_t* nc)
     return x == 0 || x == nc[0] - 1 || y == 0 || y == nc[1] - 1 || z == 0 || z == nc[2] - 1;
 }
 
-// block-wide sum of (a, b) into part[2*block]
-template <int BLOCK>
-__device__ __forceinline__ void block_partial2(double a, double b, double* part, int64_t blk)
+// DPP lane moves inside each group of 8 lanes: mirror (lane j <-> 7 - j), then
+// swap pairs of pairs, then neighbours.  Summing over the three moves gives
+// every lane of the group the same, bitwise identical total (each step adds
+// two values that the partner lane adds in the other order).
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppXor2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+constexpr int kDppXor1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v)
 {
-    __shared__ double s_a[BLOCK / 64], s_b[BLOCK / 64];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o, 64);
-        b += __shfl_xor(b, o, 64);
-    }
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ float group8_sum(float v)
+{
+    v += dpp_f32<kDppHalfMirror>(v);
+    v += dpp_f32<kDppXor2>(v);
+    return v + dpp_f32<kDppXor1>(v);
+}
+
+__device__ __forceinline__ double group8_sum(double v)
+{
+    v += dpp_f64<kDppHalfMirror>(v);
+    v += dpp_f64<kDppXor2>(v);
+    return v + dpp_f64<kDppXor1>(v);
+}
+
+__device__ __forceinline__ int group8_max(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppHalfMirror, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppXor2, 0xF, 0xF, false));
+    return max(v, __builtin_amdgcn_update_dpp(0, v, kDppXor1, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double wrap_coord(double x, double L, double invL)
+{
+    double y = x - L * floor(x * invL);
+    if (y >= L) y -= L;
+    if (y < 0.0) y += L;
+    return y;
+}
+
+__device__ __forceinline__ float local_coord(double x, int c, double cs, double L, double invL)
+{
+    double l = x - (double)c * cs;
+    l -= L * rint((l - 0.5 * cs) * invL);
+    return (float)l;
+}
+
+// Block-level epilogue: (PE, W) and KE partials, displacement maximum.
+template <bool ENERGY, int MODE>
+__device__ __forceinline__ void block_epilogue(const PairArgs& a, int64_t blk, double pe, double w, double ke,
+                                               double d2)
+{
+    constexpr int NW = kForceBlock / 64;
+    __shared__ double s_r[4][NW];
     const int wave = threadIdx.x >> 6;
+    if (ENERGY) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            pe += __shfl_xor(pe, o, 64);
+            w += __shfl_xor(w, o, 64);
+            if (MODE != MODE_FORCE) ke += __shfl_xor(ke, o, 64);
+        }
+    }
+    if (MODE == MODE_KKD) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) d2 = fmax(d2, __shfl_xor(d2, o, 64));
+    }
     if ((threadIdx.x & 63) == 0) {
-        s_a[wave] = a;
-        s_b[wave] = b;
+        s_r[0][wave] = pe;
+        s_r[1][wave] = w;
+        s_r[2][wave] = ke;
+        s_r[3][wave] = d2;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double sa = 0.0, sb = 0.0;
+        double spe = 0.0, sw = 0.0, ske = 0.0, m = 0.0;
 #pragma unroll
-        for (int w = 0; w < BLOCK / 64; ++w) {
-            sa += s_a[w];
-            sb += s_b[w];
+        for (int k = 0; k < NW; ++k) {
+            spe += s_r[0][k];
+            sw += s_r[1][k];
+            ske += s_r[2][k];
+            m = fmax(m, s_r[3][k]);
         }
-        part[2 * blk] = sa;
-        part[2 * blk + 1] = sb;
+        if (ENERGY) {
+            a.part_pw[2 * blk] = 0.5 * spe;
+            a.part_pw[2 * blk + 1] = 0.5 * sw;
+            if (MODE != MODE_FORCE) a.part_ke[blk] = 0.5 * ske;
+        }
+        if (MODE == MODE_KKD) atomicMax(a.max_d2, (unsigned long long)__double_as_longlong(m));
     }
 }
 
-// Row walk shared by both precisions.  Lane `sub` of a key's group handles
-// entries sub, sub + G, ... of the row.  The wave walks the rows of its keys
-// in lockstep up to the longest one (a wave-uniform bound), U entries per lane
-// at a time: the U index loads are issued, then the U position gathers, then
-// the U pair terms are evaluated.  Unroll slots that no lane of the wave needs
-// are skipped by a uniform branch; inside a slot, lanes past the end of their
-// row load nothing and use a stand-in partner placed beyond the cutoff.
-// maximum over the wave, returned as a wave-uniform (scalar) value
-__device__ __forceinline__ int wave_max_i32(int v)
+// Integrator epilogue of one key (lane): kicks, drift, wrap, displacement since
+// the last build.  Same arithmetic as the stand-alone integrator.
+template <int MODE, bool MIXED>
+__device__ __forceinline__ void integrate_key(const PairArgs& a, int64_t k, double fx, double fy, double fz,
+                                              double& ke, double& d2)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return __builtin_amdgcn_readfirstlane(v);
+    const int64_t n = a.n;
+    const double h = 0.5 * a.dt;
+    double* __restrict__ vel = a.vel;
+    double vx = vel[k], vy = vel[n + k], vz = vel[2 * n + k];
+    double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    int32_t c = 0;
+    if (MODE == MODE_KKD) {
+        p = a.pos[k];
+        rx = a.pos_ref[k];
+        ry = a.pos_ref[n + k];
+        rz = a.pos_ref[2 * n + k];
+        if (MIXED) c = a.cell_xyz[k];
+    }
+    vx = vx + h * fx;
+    vy = vy + h * fy;
+    vz = vz + h * fz;
+    ke = vx * vx + vy * vy + vz * vz;
+    if (MODE == MODE_KKD) {
+        vx = vx + h * fx;
+        vy = vy + h * fy;
+        vz = vz + h * fz;
+        p.x = wrap_coord(p.x + a.dt * vx, a.L[0], a.invL[0]);
+        p.y = wrap_coord(p.y + a.dt * vy, a.L[1], a.invL[1]);
+        p.z = wrap_coord(p.z + a.dt * vz, a.L[2], a.invL[2]);
+        double ex = p.x - rx, ey = p.y - ry, ez = p.z - rz;
+        ex -= a.L[0] * rint(ex * a.invL[0]);
+        ey -= a.L[1] * rint(ey * a.invL[1]);
+        ez -= a.L[2] * rint(ez * a.invL[2]);
+        d2 = ex * ex + ey * ey + ez * ez;
+        a.pos_out[k] = p;
+        if (MIXED)
+            a.pos32_out[k] = make_float4(local_coord(p.x, c & 1023, a.cs[0], a.L[0], a.invL[0]),
+                                         local_coord(p.y, (c >> 10) & 1023, a.cs[1], a.L[1], a.invL[1]),
+                                         local_coord(p.z, (c >> 20) & 1023, a.cs[2], a.L[2], a.invL[2]), 0.0f);
+    }
+    vel[k] = vx;
+    vel[n + k] = vy;
+    vel[2 * n + k] = vz;
 }
 
-template <int G, int U, bool ENERGY>
-__global__ __launch_bounds__(kForceBlock) void k_forces_fp64(ForceArgs a)
+template <int U, bool ENERGY, int MODE>
+__global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_fp64(PairArgs a)
 {
+    constexpr int NW = kForceBlock / 64;
+    __shared__ double4 s_p[NW][64];     // own position, .w = 1 if the key needs minimum images
+    __shared__ int64_t s_off[NW][64];
+    __shared__ int32_t s_cnt[NW][64];
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t key = blk * (kForceBlock / G) + threadIdx.x / G;
-    const int sub = threadIdx.x % G;
-    const bool valid = key < a.n;
-    int64_t off = 0;
-    int cnt = 0;
-    double xi = 0.0, yi = 0.0, zi = 0.0;
-    bool minimg = false;
-    if (valid) {
-        off = a.offsets[key];
-        cnt = a.counts[key];
-        const double4 p = a.pos[key];
-        xi = p.x;
-        yi = p.y;
-        zi = p.z;
-        minimg = a.exact_all || boundary_cell(a.cell_xyz[key], a.nc);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, sub = lane & 7, grp = lane >> 3;
+    const int64_t base = (blk * NW + wave) * 64;
+    const int64_t mykey = base + lane;
+    const bool myvalid = mykey < a.n;
+    {
+        // lanes past the end load the last key (no branch) and get an empty row
+        const int64_t k = myvalid ? mykey : a.n - 1;
+        double4 p = a.pos[k];
+        p.w = (a.exact_all || boundary_cell(a.cell_xyz[k], a.nc)) ? 1.0 : 0.0;
+        s_p[wave][lane] = p;
+        s_off[wave][lane] = a.offsets[k];
+        s_cnt[wave][lane] = myvalid ? a.counts[k] : 0;
     }
+    __syncthreads();
     const double rc2 = a.lj.rc2, A = a.lj.A, B = a.lj.B, C8 = a.lj.C8;
-    double fx = 0.0, fy = 0.0, fz = 0.0, pe = 0.0, w = 0.0;
-    const uint32_t* row = a.nbr + off;
-    const int cmax = wave_max_i32(cnt);
-    for (int t0 = sub; t0 - sub < cmax; t0 += G * U) {
-        uint32_t e[U];
+    double kfx = 0.0, kfy = 0.0, kfz = 0.0, pe = 0.0, w = 0.0;
+    for (int r = 0; r < 8; ++r) {
+        const int ks = (r << 3) | grp;           // key base + 8 r + grp
+        const int cmax = __builtin_amdgcn_readfirstlane(group8_max(s_cnt[wave][(r << 3) | sub]));
+        const int cnt = s_cnt[wave][ks];
+        const uint32_t* row = a.nbr + s_off[wave][ks];
+        const double4 pi = s_p[wave][ks];
+        const double xi = pi.x, yi = pi.y, zi = pi.z;
+        const bool minimg = pi.w != 0.0;
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int t0 = sub; t0 - sub < cmax; t0 += 8 * U) {
+            uint32_t e[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = t0 + u * G;
-            e[u] = t < cnt ? row[t] : 0xFFFFFFFFu;
-        }
-        double4 pj[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (t0 - sub + u * G < cmax) {
-                // stand-in for masked slots: half a box away along x, which the
-                // minimum image leaves in place (rint(1/2) = 0) and which is
-                // beyond rs because every axis has at least three cells
-                if (e[u] != 0xFFFFFFFFu) pj[u] = a.pos[e[u] & kSlotMask];
-                else pj[u] = make_double4(xi + 0.5 * a.L[0], yi, zi, 0.0);
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * 8;
+                e[u] = t < cnt ? row[t] : 0xFFFFFFFFu;
             }
-        }
+            double4 pj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (t0 - sub + u * G < cmax) {
-                double dx = pj[u].x - xi, dy = pj[u].y - yi, dz = pj[u].z - zi;
-                if (minimg) {
-                    dx -= a.L[0] * rint(dx * a.invL[0]);
-                    dy -= a.L[1] * rint(dy * a.invL[1]);
-                    dz -= a.L[2] * rint(dz * a.invL[2]);
-                }
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const double r2i = rcp64(r2);
-                const double r6i = r2i * r2i * r2i;
-                double g = r2i * r6i * (A * r6i - B) - C8;
-                const bool in = r2 < rc2;
-                g = in ? g : 0.0;
-                fx -= g * dx;
-                fy -= g * dy;
-                fz -= g * dz;
-                if (ENERGY) {
-                    const double V = r6i * (a.lj.A4 * r6i - a.lj.B4) + a.lj.C2 * r2 + a.lj.C0;
-                    pe += in ? V : 0.0;
-                    w += g * r2;
+            for (int u = 0; u < U; ++u) {
+                if (t0 - sub + u * 8 < cmax) {
+                    // stand-in for masked slots: half a box away along x, which
+                    // the minimum image leaves in place (rint(1/2) = 0) and which
+                    // is beyond rs because every axis has at least three cells
+                    if (e[u] != 0xFFFFFFFFu) pj[u] = a.pos[e[u] & kSlotMask];
+                    else pj[u] = make_double4(xi + 0.5 * a.L[0], yi, zi, 0.0);
                 }
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (t0 - sub + u * 8 < cmax) {
+                    double dx = pj[u].x - xi, dy = pj[u].y - yi, dz = pj[u].z - zi;
+                    if (minimg) {
+                        dx -= a.L[0] * rint(dx * a.invL[0]);
+                        dy -= a.L[1] * rint(dy * a.invL[1]);
+                        dz -= a.L[2] * rint(dz * a.invL[2]);
+                    }
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    const double r2i = rcp64(r2);
+                    const double r6i = r2i * r2i * r2i;
+                    double g = r2i * r6i * (A * r6i - B) - C8;
+                    const bool in = r2 < rc2;
+                    g = in ? g : 0.0;
+                    fx -= g * dx;
+                    fy -= g * dy;
+                    fz -= g * dz;
+                    if (ENERGY) {
+                        const double V = r6i * (a.lj.A4 * r6i - a.lj.B4) + a.lj.C2 * r2 + a.lj.C0;
+                        pe += in ? V : 0.0;
+                        w += g * r2;
+                    }
+                }
+            }
+        }
+        fx = __shfl(group8_sum(fx), sub << 3, 64);
+        fy = __shfl(group8_sum(fy), sub << 3, 64);
+        fz = __shfl(group8_sum(fz), sub << 3, 64);
+        if (grp == r) {
+            kfx = fx;
+            kfy = fy;
+            kfz = fz;
         }
     }
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-        fx += __shfl_xor(fx, o, G);
-        fy += __shfl_xor(fy, o, G);
-        fz += __shfl_xor(fz, o, G);
+    double ke = 0.0, d2 = 0.0;
+    if (myvalid) {
+        if (!isfinite(kfx + kfy + kfz)) atomicOr((unsigned long long*)a.flags, 1ull);
+        if (MODE != MODE_KKD) {
+            double* F = (double*)a.force;
+            F[mykey] = kfx;
+            F[a.n + mykey] = kfy;
+            F[2 * a.n + mykey] = kfz;
+        }
+        if (MODE != MODE_FORCE) integrate_key<MODE, false>(a, mykey, kfx, kfy, kfz, ke, d2);
     }
-    if (valid && sub == 0) {
-        double* F = (double*)a.force;
-        F[key] = fx;
-        F[a.n + key] = fy;
-        F[2 * a.n + key] = fz;
-        if (!isfinite(fx + fy + fz)) atomicOr((unsigned long long*)a.flags, 1ull);
-    }
-    if (ENERGY) block_partial2<kForceBlock>(0.5 * pe, 0.5 * w, a.part, blk);
+    if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE>(a, blk, pe, w, ke, d2);
 }
 
-template <int G, int U, bool ENERGY>
-__global__ __launch_bounds__(kForceBlock) void k_forces_mixed(ForceArgs a)
+template <int U, bool ENERGY, int MODE>
+__global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed(PairArgs a)
 {
+    constexpr int NW = kForceBlock / 64;
     __shared__ float4 s_shift[32];
+    __shared__ float4 s_l[NW][64];
+    __shared__ int64_t s_off[NW][64];
+    __shared__ int32_t s_cnt[NW][64];
     if (threadIdx.x < 32) {
         // code 27 never occurs in an entry: it is the stand-in used for
         // masked slots, displaced far beyond the cutoff
@@ -186,82 +335,97 @@ __global__ __launch_bounds__(kForceBlock) void k_forces_mixed(ForceArgs a)
                                                               a.shift[threadIdx.x][2], 0.0f)
                                                 : make_float4(1.0e3f, 0.0f, 0.0f, 0.0f);
     }
-    __syncthreads();
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t key = blk * (kForceBlock / G) + threadIdx.x / G;
-    const int sub = threadIdx.x % G;
-    const bool valid = key < a.n;
-    int64_t off = 0;
-    int cnt = 0;
-    float4 li = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (valid) {
-        off = a.offsets[key];
-        cnt = a.counts[key];
-        li = a.pos32[key];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, sub = lane & 7, grp = lane >> 3;
+    const int64_t base = (blk * NW + wave) * 64;
+    const int64_t mykey = base + lane;
+    const bool myvalid = mykey < a.n;
+    {
+        // lanes past the end load the last key (no branch) and get an empty row
+        const int64_t k = myvalid ? mykey : a.n - 1;
+        float4 l = a.pos32[k];
+        l.w = __int_as_float((int)k);   // the key's own slot (stand-in partner)
+        s_l[wave][lane] = l;
+        s_off[wave][lane] = a.offsets[k];
+        s_cnt[wave][lane] = myvalid ? a.counts[k] : 0;
     }
+    __syncthreads();
     const float rc2 = (float)a.lj.rc2, A = (float)a.lj.A, B = (float)a.lj.B, C8 = (float)a.lj.C8;
-    float fx = 0.f, fy = 0.f, fz = 0.f;
+    float kfx = 0.f, kfy = 0.f, kfz = 0.f;
     double pe = 0.0, w = 0.0;
-    const uint32_t* row = a.nbr + off;
-    const uint32_t dummy = (uint32_t)(valid ? key : 0) | (27u << kCodeShift);
-    const int cmax = wave_max_i32(cnt);
-    for (int t0 = sub; t0 - sub < cmax; t0 += G * U) {
-        uint32_t e[U];
+    for (int r = 0; r < 8; ++r) {
+        const int ks = (r << 3) | grp;           // key base + 8 r + grp
+        const int cmax = __builtin_amdgcn_readfirstlane(group8_max(s_cnt[wave][(r << 3) | sub]));
+        const int cnt = s_cnt[wave][ks];
+        const uint32_t* row = a.nbr + s_off[wave][ks];
+        const float4 li = s_l[wave][ks];
+        const uint32_t dummy = (uint32_t)__float_as_int(li.w) | (27u << kCodeShift);
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        for (int t0 = sub; t0 - sub < cmax; t0 += 8 * U) {
+            uint32_t e[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = t0 + u * G;
-            e[u] = t < cnt ? row[t] : dummy;
-        }
-        float4 pj[U];
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * 8;
+                e[u] = t < cnt ? row[t] : dummy;
+            }
+            float4 pj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (t0 - sub + u * G < cmax) pj[u] = a.pos32[e[u] & kSlotMask];
+            for (int u = 0; u < U; ++u)
+                if (t0 - sub + u * 8 < cmax) pj[u] = a.pos32[e[u] & kSlotMask];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (t0 - sub + u * G < cmax) {
-                const float4 sh = s_shift[e[u] >> kCodeShift];
-                const float dx = (pj[u].x - li.x) + sh.x;
-                const float dy = (pj[u].y - li.y) + sh.y;
-                const float dz = (pj[u].z - li.z) + sh.z;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const float r2i = __builtin_amdgcn_rcpf(r2);
-                const float r6i = r2i * r2i * r2i;
-                float g = r2i * r6i * (A * r6i - B) - C8;
-                const bool in = r2 < rc2;
-                g = in ? g : 0.0f;
-                fx -= g * dx;
-                fy -= g * dy;
-                fz -= g * dz;
-                if (ENERGY) {
-                    const float V = r6i * ((float)a.lj.A4 * r6i - (float)a.lj.B4) + (float)a.lj.C2 * r2 +
-                                    (float)a.lj.C0;
-                    pe += in ? (double)V : 0.0;
-                    w += (double)(g * r2);
+            for (int u = 0; u < U; ++u) {
+                if (t0 - sub + u * 8 < cmax) {
+                    const float4 sh = s_shift[e[u] >> kCodeShift];
+                    const float dx = (pj[u].x - li.x) + sh.x;
+                    const float dy = (pj[u].y - li.y) + sh.y;
+                    const float dz = (pj[u].z - li.z) + sh.z;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float r2i = __builtin_amdgcn_rcpf(r2);
+                    const float r6i = r2i * r2i * r2i;
+                    float g = r2i * r6i * (A * r6i - B) - C8;
+                    const bool in = r2 < rc2;
+                    g = in ? g : 0.0f;
+                    fx -= g * dx;
+                    fy -= g * dy;
+                    fz -= g * dz;
+                    if (ENERGY) {
+                        const float V = r6i * ((float)a.lj.A4 * r6i - (float)a.lj.B4) + (float)a.lj.C2 * r2 +
+                                        (float)a.lj.C0;
+                        pe += in ? (double)V : 0.0;
+                        w += (double)(g * r2);
+                    }
                 }
             }
         }
+        fx = __shfl(group8_sum(fx), sub << 3, 64);
+        fy = __shfl(group8_sum(fy), sub << 3, 64);
+        fz = __shfl(group8_sum(fz), sub << 3, 64);
+        if (grp == r) {
+            kfx = fx;
+            kfy = fy;
+            kfz = fz;
+        }
     }
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-        fx += __shfl_xor(fx, o, G);
-        fy += __shfl_xor(fy, o, G);
-        fz += __shfl_xor(fz, o, G);
+    double ke = 0.0, d2 = 0.0;
+    if (myvalid) {
+        if (!isfinite(kfx + kfy + kfz)) atomicOr((unsigned long long*)a.flags, 1ull);
+        if (MODE != MODE_KKD) {
+            float* F = (float*)a.force;
+            F[mykey] = kfx;
+            F[a.n + mykey] = kfy;
+            F[2 * a.n + mykey] = kfz;
+        }
+        if (MODE != MODE_FORCE) integrate_key<MODE, true>(a, mykey, kfx, kfy, kfz, ke, d2);
     }
-    if (valid && sub == 0) {
-        float* F = (float*)a.force;
-        F[key] = fx;
-        F[a.n + key] = fy;
-        F[2 * a.n + key] = fz;
-        if (!isfinite(fx + fy + fz)) atomicOr((unsigned long long*)a.flags, 1ull);
-    }
-    if (ENERGY) block_partial2<kForceBlock>(0.5 * pe, 0.5 * w, a.part, blk);
+    if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE>(a, blk, pe, w, ke, d2);
 }
 
-hipError_t launch_forces(const Geo& g, const LJ& lj, int precision, const double* pos,
-                         const float* pos32, const int32_t* cell_xyz, const md_pairlist& list,
-                         const ForceOut& out, hipStream_t s)
+int64_t pair_blocks(const Geo& g) { return ceil_div(g.n, kForceBlock); }
+
+static PairArgs make_pair_args(const Geo& g, const LJ& lj, const double* pos, const float* pos32,
+                               const int32_t* cell_xyz, const md_pairlist& list)
 {
-    ForceArgs a;
+    PairArgs a = {};
     a.pos = (const double4*)pos;
     a.pos32 = (const float4*)pos32;
     a.cell_xyz = cell_xyz;
@@ -269,10 +433,10 @@ hipError_t launch_forces(const Geo& g, const LJ& lj, int precision, const double
     a.counts = list.counts;
     a.nbr = list.nbr;
     a.n = g.n;
-    a.nblocks = ceil_div(g.n, kKeysPerBlock);
     for (int k = 0; k < 3; ++k) {
         a.L[k] = g.L[k];
         a.invL[k] = g.invL[k];
+        a.cs[k] = g.cs[k];
         a.nc[k] = g.nc[k];
     }
     a.exact_all = g.exact_all;
@@ -284,22 +448,54 @@ hipError_t launch_forces(const Geo& g, const LJ& lj, int precision, const double
         a.shift[code][2] = (float)(sz * g.cs[2]);
         a.shift[code][3] = 0.0f;
     }
+    return a;
+}
+
+template <bool ENERGY, int MODE>
+static void launch_pairs_mode(const Geo& g, int precision, const PairArgs& a, hipStream_t s)
+{
+    const dim3 grid((unsigned)pair_blocks(g)), block(kForceBlock);
+    if (precision == MD_MIXED)
+        hipLaunchKernelGGL((k_pairs_mixed<kForceUnroll, ENERGY, MODE>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_pairs_fp64<kForceUnroll64, ENERGY, MODE>), grid, block, 0, s, a);
+}
+
+hipError_t launch_forces(const Geo& g, const LJ& lj, int precision, const double* pos,
+                         const float* pos32, const int32_t* cell_xyz, const md_pairlist& list,
+                         const ForceOut& out, hipStream_t s)
+{
+    PairArgs a = make_pair_args(g, lj, pos, pos32, cell_xyz, list);
     a.force = out.force;
-    a.part = out.part;
+    a.part_pw = out.part;
     a.flags = out.flags;
-    const dim3 grid((unsigned)a.nblocks), block(kForceBlock);
-    const bool energy = out.part != nullptr;
-    constexpr int G = kLanesPerKey, U = kForceUnroll, U64 = kForceUnroll64;
-    if (precision == MD_MIXED) {
-        if (energy)
-            hipLaunchKernelGGL((k_forces_mixed<G, U, true>), grid, block, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_forces_mixed<G, U, false>), grid, block, 0, s, a);
+    if (out.part)
+        launch_pairs_mode<true, MODE_FORCE>(g, precision, a, s);
+    else
+        launch_pairs_mode<false, MODE_FORCE>(g, precision, a, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_step(const Geo& g, const LJ& lj, int precision, const StepIo& io, hipStream_t s)
+{
+    PairArgs a = make_pair_args(g, lj, io.pos, io.pos32, io.cell_xyz, io.list);
+    a.force = io.force;
+    a.part_pw = io.part_pw;
+    a.part_ke = io.part_ke;
+    a.flags = io.flags;
+    a.vel = io.vel;
+    a.pos_ref = io.pos_ref;
+    a.pos_out = (double4*)io.pos_out;
+    a.pos32_out = (float4*)io.pos32_out;
+    a.max_d2 = io.max_d2;
+    a.dt = io.dt;
+    const bool energy = io.part_pw != nullptr;
+    if (io.drift) {
+        if (energy) launch_pairs_mode<true, MODE_KKD>(g, precision, a, s);
+        else launch_pairs_mode<false, MODE_KKD>(g, precision, a, s);
     } else {
-        if (energy)
-            hipLaunchKernelGGL((k_forces_fp64<G, U64, true>), grid, block, 0, s, a);
-        else
-            hipLaunchKernelGGL((k_forces_fp64<G, U64, false>), grid, block, 0, s, a);
+        if (energy) launch_pairs_mode<true, MODE_KICK>(g, precision, a, s);
+        else launch_pairs_mode<false, MODE_KICK>(g, precision, a, s);
     }
     return hipGetLastError();
 }

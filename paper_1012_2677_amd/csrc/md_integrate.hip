@@ -3,12 +3,12 @@
 // and the fixed-order FP64 reductions of energy and list statistics.
 //
 // One thread per slot streams pos, vel, force and pos_ref (SoA, coalesced);
-// the kernel is bound by HBM bandwidth.  Between two force evaluations the
-// two half kicks of consecutive steps are applied in one pass (kick, kick,
-// drift), keeping them as two separate roundings so the result is the same as
-// two separate passes.  Block maxima of the squared displacement since the last
-// build go to one atomic max (exact, order independent); kinetic-energy block
-// sums go to a partials array reduced later in a fixed order (deterministic).
+// the kernel is bound by HBM bandwidth.  It runs the first half kick and drift
+// at the start of a run and the kinetic energy of a state; inside a run the
+// kicks and drift after each force evaluation are fused into the pair kernel.
+// Block maxima of the squared displacement since the last build go to one
+// atomic max (exact, order independent); kinetic-energy block sums go to a
+// partials array reduced later in a fixed order (deterministic).
 
 #include "md_internal.h"
 
@@ -29,14 +29,19 @@ __device__ __forceinline__ float local_coord_i(double x, int c, double cs, doubl
     return (float)l;
 }
 
-template <int MODE, bool KE, bool MIXED>
+// MODE INT_KD: first half kick and drift of a step (the start of a run, when
+// no force evaluation precedes it in the same pass).  MODE INT_KE: kinetic
+// energy only.  The kicks that follow a force evaluation run inside the pair
+// kernel (launch_force_step).
+template <int MODE, bool MIXED>
 __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = g.n;
     const bool valid = i < n;
     const double h = 0.5 * a.dt;
-    constexpr bool DRIFT = MODE == INT_KD || MODE == INT_KKD;
+    constexpr bool DRIFT = MODE == INT_KD;
+    constexpr bool KE = MODE == INT_KE;
     double* __restrict__ vel = a.vel;
     double4* __restrict__ P = (double4*)a.pos;
     const double* __restrict__ ref = a.pos_ref;
@@ -46,7 +51,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
         // thread are in flight together
         double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
         double fx = 0.0, fy = 0.0, fz = 0.0;
-        if (MODE != INT_KE) {
+        if (DRIFT) {
             if (MIXED) {
                 const float* __restrict__ F = (const float*)a.force;
                 fx = F[i];
@@ -69,18 +74,11 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
             rz = ref[2 * n + i];
             if (MIXED) c = a.cell_xyz[i];
         }
-        if (MODE != INT_KE) {
-            vx = vx + h * fx;
-            vy = vy + h * fy;
-            vz = vz + h * fz;
-        }
         if (KE) ke = vx * vx + vy * vy + vz * vz;
-        if (MODE == INT_KKD) {
+        if (DRIFT) {
             vx = vx + h * fx;
             vy = vy + h * fy;
             vz = vz + h * fz;
-        }
-        if (DRIFT) {
             p.x = wrap_coord(p.x + a.dt * vx, g.L[0], g.invL[0]);
             p.y = wrap_coord(p.y + a.dt * vy, g.L[1], g.invL[1]);
             p.z = wrap_coord(p.z + a.dt * vz, g.L[2], g.invL[2]);
@@ -96,8 +94,6 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
                                 local_coord_i(p.y, (c >> 10) & 1023, g.cs[1], g.L[1], g.invL[1]),
                                 local_coord_i(p.z, (c >> 20) & 1023, g.cs[2], g.L[2], g.invL[2]), 0.0f);
             }
-        }
-        if (MODE != INT_KE) {
             vel[i] = vx;
             vel[n + i] = vy;
             vel[2 * n + i] = vz;
@@ -115,7 +111,6 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
             for (int w = 0; w < kStreamBlock / 64; ++w) m = fmax(m, s_v[w]);
             atomicMax(a.max_d2, (unsigned long long)__double_as_longlong(m));
         }
-        __syncthreads();
     }
     if (KE) {
 #pragma unroll
@@ -131,30 +126,16 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
     }
 }
 
-template <int MODE, bool KE>
-static void launch_int_mode(const Geo& g, const IntArgs& a, hipStream_t s)
-{
-    const dim3 grid((unsigned)ceil_div(g.n, kStreamBlock)), block(kStreamBlock);
-    if (a.precision == MD_MIXED)
-        hipLaunchKernelGGL((k_integrate<MODE, KE, true>), grid, block, 0, s, g, a);
-    else
-        hipLaunchKernelGGL((k_integrate<MODE, KE, false>), grid, block, 0, s, g, a);
-}
-
 hipError_t launch_integrate(const Geo& g, IntMode mode, const IntArgs& a, hipStream_t s)
 {
-    const bool ke = a.part_ke != nullptr;
-    switch (mode) {
-    case INT_KD: launch_int_mode<INT_KD, false>(g, a, s); break;
-    case INT_KKD:
-        if (ke) launch_int_mode<INT_KKD, true>(g, a, s);
-        else launch_int_mode<INT_KKD, false>(g, a, s);
-        break;
-    case INT_K:
-        if (ke) launch_int_mode<INT_K, true>(g, a, s);
-        else launch_int_mode<INT_K, false>(g, a, s);
-        break;
-    case INT_KE: launch_int_mode<INT_KE, true>(g, a, s); break;
+    const dim3 grid((unsigned)ceil_div(g.n, kStreamBlock)), block(kStreamBlock);
+    const bool mixed = a.precision == MD_MIXED;
+    if (mode == INT_KD) {
+        if (mixed) hipLaunchKernelGGL((k_integrate<INT_KD, true>), grid, block, 0, s, g, a);
+        else hipLaunchKernelGGL((k_integrate<INT_KD, false>), grid, block, 0, s, g, a);
+    } else {
+        if (mixed) hipLaunchKernelGGL((k_integrate<INT_KE, true>), grid, block, 0, s, g, a);
+        else hipLaunchKernelGGL((k_integrate<INT_KE, false>), grid, block, 0, s, g, a);
     }
     return hipGetLastError();
 }

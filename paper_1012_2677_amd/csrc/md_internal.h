@@ -26,7 +26,10 @@ constexpr int kForceBlock = 256;         // force / adjoint kernels
 #ifndef MD_FORCE_UNROLL_FP64
 #define MD_FORCE_UNROLL_FP64 4
 #endif
-constexpr int kLanesPerKey = MD_LANES_PER_KEY;   // lanes cooperating on one key's row
+#ifndef MD_PAIR_MIN_BLOCKS
+#define MD_PAIR_MIN_BLOCKS 1
+#endif
+constexpr int kLanesPerKey = MD_LANES_PER_KEY;   // lanes cooperating on one key's row (adjoint kernels)
 constexpr int kForceUnroll = MD_FORCE_UNROLL;    // row entries in flight per lane (FP32 pair terms)
 constexpr int kForceUnroll64 = MD_FORCE_UNROLL_FP64;  // same for FP64 pair terms (register bound)
 constexpr int kKeysPerBlock = kForceBlock / kLanesPerKey;
@@ -153,9 +156,32 @@ struct ForceOut {
 hipError_t launch_forces(const Geo& g, const LJ& lj, int precision, const double* pos,
                          const float* pos32, const int32_t* cell_xyz, const md_pairlist& list,
                          const ForceOut& out, hipStream_t s);
+// Force evaluation fused with the integrator: the second half kick (drift =
+// false: also writes the force) or second kick + next first kick + drift
+// (drift = true: writes positions to pos_out and, in mixed mode, local
+// coordinates to pos32_out; the force is not stored).
+struct StepIo {
+    const double* pos;
+    const float* pos32;
+    const int32_t* cell_xyz;
+    md_pairlist list;
+    void* force;
+    double* part_pw;              // per-block (PE, W) partials, or nullptr
+    double* part_ke;              // per-block KE partials (with part_pw)
+    int64_t* flags;
+    double* vel;
+    const double* pos_ref;
+    double* pos_out;
+    float* pos32_out;
+    unsigned long long* max_d2;
+    double dt;
+    bool drift;
+};
+hipError_t launch_force_step(const Geo& g, const LJ& lj, int precision, const StepIo& io, hipStream_t s);
+int64_t pair_blocks(const Geo& g);   // blocks (and energy partials) of one pair-kernel launch
 
 // md_integrate.hip
-enum IntMode { INT_KD = 0, INT_KKD = 1, INT_K = 2, INT_KE = 3 };
+enum IntMode { INT_KD = 0, INT_KE = 1 };
 struct IntArgs {
     double* pos;
     double* vel;

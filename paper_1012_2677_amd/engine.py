@@ -149,19 +149,23 @@ class Engine:
         self.vel = torch.from_numpy(np.ascontiguousarray(vel.T)).to(dev)
         self.id = torch.arange(n, dtype=torch.int32, device=dev)
         resort = resort_every > 0
-        self.pos_alt = torch.empty_like(self.pos) if resort else None
+        # second buffers: the re-sort writes all three; in FP64 every step also
+        # writes its drifted positions to pos_alt (mixed: local coordinates to
+        # pos32_alt) while the force pass still reads the current ones
+        self.pos_alt = torch.empty_like(self.pos) if (resort or not self.mixed) else None
         self.vel_alt = torch.empty_like(self.vel) if resort else None
         self.id_alt = torch.empty_like(self.id) if resort else None
         self.force = torch.zeros((3, n), dtype=torch.float32 if self.mixed else torch.float64, device=dev)
         self.pos_ref = torch.empty((3, n), **f64)
         self.pos32 = torch.empty((n, 4), dtype=torch.float32, device=dev) if self.mixed else None
+        self.pos32_alt = torch.empty_like(self.pos32) if self.mixed else None
         self.energy = torch.zeros(8, **f64)
         self.flags = torch.zeros(8, dtype=torch.int64, device=dev)
         self.host_scratch = torch.zeros(16, dtype=torch.int64, pin_memory=True)
         self.timers = A.MdTimers() if timers else None
         s = A.MdState()
         s.pos, s.vel, s.force = _ptr(self.pos), _ptr(self.vel), _ptr(self.force)
-        s.pos_ref, s.pos32, s.id = _ptr(self.pos_ref), _ptr(self.pos32), _ptr(self.id)
+        s.pos_ref, s.pos32, s.pos32_alt, s.id = _ptr(self.pos_ref), _ptr(self.pos32), _ptr(self.pos32_alt), _ptr(self.id)
         s.pos_alt, s.vel_alt, s.id_alt = _ptr(self.pos_alt), _ptr(self.vel_alt), _ptr(self.id_alt)
         self.grid.fill(s.cells)
         self.plist.fill(s.list)
@@ -172,13 +176,14 @@ class Engine:
         self.state = s
         self.prepared = False
 
-    # -- pointer bookkeeping after the library swapped re-sort buffers ---------
+    # -- pointer bookkeeping after the library swapped buffers ------------------
     def _sync_pointers(self):
         s = self.state
-        if self.pos_alt is not None and s.pos == self.pos_alt.data_ptr():
-            self.pos, self.pos_alt = self.pos_alt, self.pos
-            self.vel, self.vel_alt = self.vel_alt, self.vel
-            self.id, self.id_alt = self.id_alt, self.id
+        for cur, alt in (("pos", "pos_alt"), ("vel", "vel_alt"), ("id", "id_alt"), ("pos32", "pos32_alt")):
+            t_cur, t_alt = getattr(self, cur), getattr(self, alt)
+            if t_alt is not None and getattr(s, cur) == t_alt.data_ptr():
+                setattr(self, cur, t_alt)
+                setattr(self, alt, t_cur)
 
     def stream(self) -> int:
         return stream_handle(self.device)
