@@ -109,7 +109,8 @@ typedef struct md_cells {
  * the block nbr[c*cell_stride .. (c+1)*cell_stride).
  *   offsets   device int64[n]
  *   counts    device int32[n]
- *   nbr       device uint32[capacity], capacity >= nc * cell_stride
+ *   nbr       device uint32[capacity], capacity >= nc * cell_stride,
+ *             1 <= cell_stride <= 2^29
  *   status    device int64[4]: [0] total entries, [1] largest per-cell block,
  *             [2] 1 if some cell block overflowed cell_stride (list invalid),
  *             [3] reserved.                                               */

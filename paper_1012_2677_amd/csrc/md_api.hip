@@ -101,18 +101,20 @@ LJ make_lj(const md_params& p)
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-WsLayout ws_layout(int64_t n, int64_t ncell)
+WsLayout ws_layout(const Geo& g)
 {
+    const int64_t n = g.n, ncell = g.ncell;
     WsLayout L;
     L.nbs = ceil_div(ncell, kScanItems);
     L.nbf = ceil_div(n, kKeysPerBlock);
+    const int64_t np = pair_blocks(g);
     L.nbi = ceil_div(n, kStreamBlock);
     size_t off = 0;
     L.rank = off;      off = align256(off + sizeof(int32_t) * (size_t)n);
     L.bsum = off;      off = align256(off + sizeof(int32_t) * (size_t)(L.nbs + 1));
     L.cell_rows = off; off = align256(off + sizeof(int32_t) * (size_t)ncell);
     L.part_a = off;    off = align256(off + sizeof(double) * 2 * (size_t)L.nbf);
-    L.part_b = off;    off = align256(off + sizeof(double) * (size_t)L.nbi);
+    L.part_b = off;    off = align256(off + sizeof(double) * (size_t)(np > L.nbi ? np : L.nbi));
     L.pos32 = off;     off = align256(off + 16 * (size_t)n);
     L.red = off;       off = align256(off + sizeof(int64_t) * 2 * 1024);
     L.scal = off;      off = align256(off + sizeof(double) * 16);
@@ -133,7 +135,7 @@ static int setup(const md_params* p, Ctx& c)
     if (rc != MD_OK) return rc;
     c.g = make_geo(*p, c.nc);
     c.lj = make_lj(*p);
-    c.W = ws_layout(p->n, c.g.ncell);
+    c.W = ws_layout(c.g);
     return MD_OK;
 }
 
@@ -156,7 +158,8 @@ static int check_list(const Ctx& c, const md_pairlist* list)
 {
     if (!list || !list->offsets || !list->counts || !list->nbr || !list->status)
         return fail(MD_ERR_ARG, "pair list has a NULL array");
-    if (list->cell_stride <= 0) return fail(MD_ERR_ARG, "cell_stride must be > 0");
+    if (list->cell_stride <= 0 || list->cell_stride > ((int64_t)1 << 29))
+        return fail(MD_ERR_ARG, "cell_stride must be in [1, 2^29]");
     if (list->capacity < c.g.ncell * list->cell_stride)
         return fail(MD_ERR_ARG, "capacity %lld < ncell * cell_stride = %lld", (long long)list->capacity,
                     (long long)(c.g.ncell * list->cell_stride));
@@ -240,7 +243,7 @@ size_t md_workspace_bytes(const md_params* p)
 {
     int32_t nc[3];
     if (check_params(p, nc) != MD_OK) return 0;
-    return ws_layout(p->n, (int64_t)nc[0] * nc[1] * nc[2]).total;
+    return ws_layout(make_geo(*p, nc)).total;
 }
 
 int md_pack_positions(const md_params* p, const double* q, double* pos, hipStream_t stream)
@@ -307,7 +310,8 @@ int md_forces(const md_params* p, const double* pos, const md_cells* cells, cons
     out.flags = (int64_t*)(w + c.W.scal) + 2;
     MD_HIP(launch_forces(c.g, c.lj, p->precision, pos, pos32, cells->cell_xyz, *list, out, stream),
            "md_forces");
-    if (pe_w) MD_HIP(launch_reduce_pair(out.part, pair_blocks(c.g), 1.0, 1.0, pe_w, stream), "md_forces/reduce");
+    if (pe_w)
+        MD_HIP(launch_reduce_pair(out.part, pair_blocks(c.g), 1.0, 1.0, pe_w, stream), "md_forces/reduce");
     return MD_OK;
 }
 

@@ -63,6 +63,13 @@ struct PairArgs {
     double dt;
 };
 
+// Keys [kb, ke) of logical block b: a chunk of kForceBlock consecutive slots.
+__device__ __forceinline__ void block_keys(const PairArgs& a, int64_t b, int64_t& kb, int64_t& ke)
+{
+    kb = b * kForceBlock;
+    ke = kb + kForceBlock < a.n ? kb + kForceBlock : a.n;
+}
+
 __device__ __forceinline__ bool boundary_cell(int32_t c, const int32_t* nc)
 {
     const int x = c & 1023, y = (c >> 10) & 1023, z = (c >> 20) & 1023;
@@ -229,21 +236,27 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_fp64(
     __shared__ int32_t s_cnt[NW][64];
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, sub = lane & 7, grp = lane >> 3;
-    const int64_t base = (blk * NW + wave) * 64;
+    int64_t kb, kend;
+    block_keys(a, blk, kb, kend);
+    const double rc2 = a.lj.rc2, A = a.lj.A, B = a.lj.B, C8 = a.lj.C8;
+    double pe = 0.0, w = 0.0, ke = 0.0, d2 = 0.0;
+    // each wave takes 64-key chunks of the block's range (a wave-uniform loop;
+    // the LDS rows below are private to the wave, so no block barrier inside;
+    // written as a loop, which also schedules better than a straight pass)
+    for (int64_t base = kb + wave * 64; base < kend; base += NW * 64) {
     const int64_t mykey = base + lane;
-    const bool myvalid = mykey < a.n;
+    const bool myvalid = mykey < kend;
     {
         // lanes past the end load the last key (no branch) and get an empty row
-        const int64_t k = myvalid ? mykey : a.n - 1;
+        const int64_t k = myvalid ? mykey : kend - 1;
         double4 p = a.pos[k];
         p.w = (a.exact_all || boundary_cell(a.cell_xyz[k], a.nc)) ? 1.0 : 0.0;
         s_p[wave][lane] = p;
         s_off[wave][lane] = a.offsets[k];
         s_cnt[wave][lane] = myvalid ? a.counts[k] : 0;
     }
-    __syncthreads();
-    const double rc2 = a.lj.rc2, A = a.lj.A, B = a.lj.B, C8 = a.lj.C8;
-    double kfx = 0.0, kfy = 0.0, kfz = 0.0, pe = 0.0, w = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    double kfx = 0.0, kfy = 0.0, kfz = 0.0;
     for (int r = 0; r < 8; ++r) {
         const int ks = (r << 3) | grp;           // key base + 8 r + grp
         const int cmax = __builtin_amdgcn_readfirstlane(group8_max(s_cnt[wave][(r << 3) | sub]));
@@ -306,7 +319,6 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_fp64(
             kfz = fz;
         }
     }
-    double ke = 0.0, d2 = 0.0;
     if (myvalid) {
         if (!isfinite(kfx + kfy + kfz)) atomicOr((unsigned long long*)a.flags, 1ull);
         if (MODE != MODE_KKD) {
@@ -315,7 +327,14 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_fp64(
             F[a.n + mykey] = kfy;
             F[2 * a.n + mykey] = kfz;
         }
-        if (MODE != MODE_FORCE) integrate_key<MODE, false>(a, mykey, kfx, kfy, kfz, ke, d2);
+        if (MODE != MODE_FORCE) {
+            double kk = 0.0, dd = 0.0;
+            integrate_key<MODE, false>(a, mykey, kfx, kfy, kfz, kk, dd);
+            ke += kk;
+            d2 = fmax(d2, dd);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
     }
     if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE>(a, blk, pe, w, ke, d2);
 }
@@ -335,24 +354,30 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed
                                                               a.shift[threadIdx.x][2], 0.0f)
                                                 : make_float4(1.0e3f, 0.0f, 0.0f, 0.0f);
     }
+    __syncthreads();
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, sub = lane & 7, grp = lane >> 3;
-    const int64_t base = (blk * NW + wave) * 64;
+    int64_t kb, kend;
+    block_keys(a, blk, kb, kend);
+    const float rc2 = (float)a.lj.rc2, A = (float)a.lj.A, B = (float)a.lj.B, C8 = (float)a.lj.C8;
+    double pe = 0.0, w = 0.0, ke = 0.0, d2 = 0.0;
+    // each wave takes 64-key chunks of the block's range (a wave-uniform loop;
+    // the LDS rows below are private to the wave, so no block barrier inside;
+    // written as a loop, which also schedules better than a straight pass)
+    for (int64_t base = kb + wave * 64; base < kend; base += NW * 64) {
     const int64_t mykey = base + lane;
-    const bool myvalid = mykey < a.n;
+    const bool myvalid = mykey < kend;
     {
         // lanes past the end load the last key (no branch) and get an empty row
-        const int64_t k = myvalid ? mykey : a.n - 1;
+        const int64_t k = myvalid ? mykey : kend - 1;
         float4 l = a.pos32[k];
         l.w = __int_as_float((int)k);   // the key's own slot (stand-in partner)
         s_l[wave][lane] = l;
         s_off[wave][lane] = a.offsets[k];
         s_cnt[wave][lane] = myvalid ? a.counts[k] : 0;
     }
-    __syncthreads();
-    const float rc2 = (float)a.lj.rc2, A = (float)a.lj.A, B = (float)a.lj.B, C8 = (float)a.lj.C8;
+    __builtin_amdgcn_wave_barrier();
     float kfx = 0.f, kfy = 0.f, kfz = 0.f;
-    double pe = 0.0, w = 0.0;
     for (int r = 0; r < 8; ++r) {
         const int ks = (r << 3) | grp;           // key base + 8 r + grp
         const int cmax = __builtin_amdgcn_readfirstlane(group8_max(s_cnt[wave][(r << 3) | sub]));
@@ -406,7 +431,6 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed
             kfz = fz;
         }
     }
-    double ke = 0.0, d2 = 0.0;
     if (myvalid) {
         if (!isfinite(kfx + kfy + kfz)) atomicOr((unsigned long long*)a.flags, 1ull);
         if (MODE != MODE_KKD) {
@@ -415,7 +439,14 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed
             F[a.n + mykey] = kfy;
             F[2 * a.n + mykey] = kfz;
         }
-        if (MODE != MODE_FORCE) integrate_key<MODE, true>(a, mykey, kfx, kfy, kfz, ke, d2);
+        if (MODE != MODE_FORCE) {
+            double kk = 0.0, dd = 0.0;
+            integrate_key<MODE, true>(a, mykey, kfx, kfy, kfz, kk, dd);
+            ke += kk;
+            d2 = fmax(d2, dd);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
     }
     if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE>(a, blk, pe, w, ke, d2);
 }

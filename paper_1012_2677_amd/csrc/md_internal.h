@@ -90,7 +90,7 @@ struct WsLayout {
     int64_t nbf;       // force-kernel blocks
     int64_t nbi;       // streaming-kernel blocks
 };
-WsLayout ws_layout(int64_t n, int64_t ncell);
+WsLayout ws_layout(const Geo& g);
 
 // ---------------------------------------------------------------------------
 // Small device helpers
