@@ -62,33 +62,92 @@ __device__ __forceinline__ void write_row(const BuildArgs& a, int32_t kslot, int
     a.counts[kslot] = (int32_t)(wpos < room ? wpos : room);
 }
 
+constexpr int kMaxOwn = 64;     // own-cell particles kept in LDS for the key loop
+constexpr int kRowBuf = 1024;   // entries of one cell's rows staged in LDS before the block is written
+
 // Keys of one cell against candidates held in registers (at most NCH*64).
 // Empty candidate slots carry NaN coordinates, so r2 < rs2 fails for them in
-// both the plain and the minimum-image form of the test.
+// both the plain and the minimum-image form of the test.  The key itself is
+// candidate number self_t.  Output positions come from mbcnt of the row mask,
+// counted on from the row's start.
+//
+// Fast form (the key's row surely fits in the LDS row buffer): the row mask is
+// the ballot of the distance test minus the key's own lane; every lane stores,
+// those outside the mask into a spare LDS word, so there is no branch and no
+// exec-mask change per chunk.
+template <bool MINIMG, int NCH>
+__device__ __forceinline__ uint32_t row_chunks_lds(const BuildArgs& a, int T, const double4& kp, int self_t,
+                                                   uint32_t w0, const double* cx, const double* cy,
+                                                   const double* cz, const uint32_t* meta, uint32_t* s_rows)
+{
+    const int lane = (int)lane_id();
+    uint32_t wpos = w0;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        if (ch * 64 < T) {
+            const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
+            const bool in = r2 < a.rs2, self = lane == self_t - ch * 64;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(in) & ~__builtin_amdgcn_ballot_w64(self);
+            const uint32_t wb = (mbcnt64(m) + wpos) << 2;   // byte offset in the row buffer
+            *(uint32_t*)((char*)s_rows + (__builtin_amdgcn_inverse_ballot_w64(m) ? wb : 4u * kRowBuf)) = meta[ch];
+            wpos += (uint32_t)__popcll(m);
+        }
+    }
+    return wpos;
+}
+
+// General form: entries go to the LDS row buffer while they fit in it, past
+// that straight to the cell block with a capacity test.
+template <bool MINIMG, int NCH>
+__device__ __forceinline__ uint32_t row_chunks(const BuildArgs& a, uint32_t* blk, uint32_t stride, int T,
+                                               const double4& kp, int self_t, uint32_t w0, const double* cx,
+                                               const double* cy, const double* cz, const uint32_t* meta,
+                                               uint32_t* s_rows)
+{
+    const int lane = (int)lane_id();
+    uint32_t wpos = w0;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        if (ch * 64 < T) {
+            const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
+            const bool in = r2 < a.rs2;
+            uint64_t m = __builtin_amdgcn_ballot_w64(in);
+            const int sl = self_t - ch * 64;          // the key's own lane in this chunk, if any
+            if (sl >= 0 && sl < 64) m &= ~(1ull << sl);
+            const uint32_t w = mbcnt64(m) + wpos;
+            if (in && lane != sl) {
+                if (w < (uint32_t)kRowBuf) s_rows[w] = meta[ch];
+                else if (w < stride) blk[w] = meta[ch];
+            }
+            wpos += (uint32_t)__popcll(m);
+        }
+    }
+    return wpos;
+}
+
 template <bool MINIMG, int NCH>
 __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, uint32_t* blk, uint32_t stride,
-                                                       int T, int own_cnt, const double4* s_key,
+                                                       int T, int own_pref, int own_cnt, const double4* s_key,
                                                        const double* cx, const double* cy, const double* cz,
-                                                       const uint32_t* meta)
+                                                       const uint32_t* meta, uint32_t* s_rows, uint32_t* s_rowend)
 {
     uint32_t used = 0;
     for (int kk = 0; kk < own_cnt; ++kk) {
-        const double4 kp = s_key[kk];
-        const int32_t kslot = (int32_t)__double_as_longlong(kp.w);
-        uint32_t wpos = 0;
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            if (ch * 64 < T) {
-                const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
-                const bool pass = r2 < a.rs2 && (int32_t)(meta[ch] & kSlotMask) != kslot;
-                const uint64_t m = __ballot(pass);
-                const uint32_t w = used + wpos + mbcnt64(m);
-                if (pass && w < stride) blk[w] = meta[ch];
-                wpos += (uint32_t)__popcll(m);
-            }
-        }
-        if (lane_id() == 0) write_row(a, kslot, (int64_t)(blk - a.nbr), used, wpos);
-        used += wpos;
+        if (used + (uint32_t)T <= (uint32_t)kRowBuf)
+            used = row_chunks_lds<MINIMG, NCH>(a, T, s_key[kk], own_pref + kk, used, cx, cy, cz, meta, s_rows);
+        else
+            used = row_chunks<MINIMG, NCH>(a, blk, stride, T, s_key[kk], own_pref + kk, used, cx, cy, cz, meta,
+                                           s_rows);
+        if (lane_id() == 0) s_rowend[kk] = used;
+    }
+    __syncthreads();
+    // the staged part of the block, then the row headers, with full-wave stores
+    const uint32_t staged = min(min(used, (uint32_t)kRowBuf), stride);
+    for (uint32_t t = lane_id(); t < staged; t += 64) blk[t] = s_rows[t];
+    const int kk = (int)lane_id();
+    if (kk < own_cnt) {
+        const uint32_t end = s_rowend[kk], beg = kk > 0 ? s_rowend[kk - 1] : 0u;
+        write_row(a, (int32_t)__double_as_longlong(s_key[kk].w), (int64_t)(blk - a.nbr), beg, end - beg);
     }
     return used;
 }
@@ -131,8 +190,6 @@ __device__ uint32_t rows_from_memory(const BuildArgs& a, uint32_t* blk, uint32_t
     return used;
 }
 
-constexpr int kMaxOwn = 64;   // own-cell particles kept in LDS for the key loop
-
 template <int NCH>
 __global__ __launch_bounds__(64) void k_build(BuildArgs a)
 {
@@ -147,6 +204,8 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     __shared__ int s_nstart[27];
     __shared__ int s_pref[28];
     __shared__ double4 s_key[kMaxOwn];
+    __shared__ uint32_t s_rows[kRowBuf + 1];   // + a spare word for lanes that store nothing
+    __shared__ uint32_t s_rowend[kMaxOwn];
     int cnt = 0, st = 0;
     if (lane < 27) {
         int ax = cx + lane / 9 - 1, ay = cy + (lane / 3) % 3 - 1, az = cz + lane % 3 - 1;
@@ -180,7 +239,8 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     const bool minimg = a.exact_all || cx == 0 || cx == nx - 1 || cy == 0 || cy == ny - 1 || cz == 0 ||
                         cz == nz - 1;
     uint32_t* blk = a.nbr + c * a.stride;
-    const uint32_t stride = (uint32_t)(a.stride < 0x7FFFFFFF ? a.stride : 0x7FFFFFFF);
+    // capped so that byte offsets (entries << 2) fit in 32 bits
+    const uint32_t stride = (uint32_t)(a.stride < (1 << 29) ? a.stride : (1 << 29));
     uint32_t used = 0;
 
     if (own_cnt > 0 && T <= NCH * 64 && own_cnt <= kMaxOwn) {
@@ -189,6 +249,9 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
         const double qnan = __longlong_as_double(0x7FF8000000000000LL);
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
+            px[ch] = py[ch] = pz[ch] = qnan;
+            meta[ch] = 0;
+            if (ch * 64 >= T) continue;          // uniform: chunk beyond the neighbourhood
             const int t = ch * 64 + lane;
             const int tt = t < T ? t : T - 1;   // in-range index; the result is discarded if t >= T
             // neighbour cell holding candidate tt: binary search in the prefix
@@ -212,8 +275,10 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
             if (ok && k >= 0 && k < own_cnt) s_key[k] = make_double4(p.x, p.y, p.z, __longlong_as_double((long long)slot));
         }
         __syncthreads();
-        used = minimg ? rows_from_registers<true, NCH>(a, blk, stride, T, own_cnt, s_key, px, py, pz, meta)
-                      : rows_from_registers<false, NCH>(a, blk, stride, T, own_cnt, s_key, px, py, pz, meta);
+        used = minimg ? rows_from_registers<true, NCH>(a, blk, stride, T, own_pref, own_cnt, s_key, px, py, pz,
+                                                       meta, s_rows, s_rowend)
+                      : rows_from_registers<false, NCH>(a, blk, stride, T, own_pref, own_cnt, s_key, px, py, pz,
+                                                        meta, s_rows, s_rowend);
     } else if (own_cnt > 0) {
         used = minimg ? rows_from_memory<true>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart)
                       : rows_from_memory<false>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart);
