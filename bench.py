@@ -1,5 +1,10 @@
 """Throughput benchmark of the LJ hot path on one MI355X.
 
+Other workloads: --config lj4k / lj4m / lj256k / lj131m (sizes of the same
+fluid), paper500k / paper32m (the paper's own benchmark conditions: |v| = 0.9
+in random directions, dt = 0.001, 150 untimed + 1000 timed steps, FP64);
+--ablation adds a run without re-sorting on shuffled labels.
+
 Workload (default "lj32m"): N = 32,000,000 particles on a 200^3-cell fcc
 lattice at rho = 0.5 (L = 400), truncated LJ with rc = 2.5 and skin 0.3
 (rs = 2.8), Maxwell-Boltzmann velocities at T = 1 (seed 0), dt = 0.005, NVE.
@@ -26,6 +31,7 @@ import numpy as np
 
 METRIC = "particle-steps/s, 32M-atom LJ NVE: FP64 vs FP32/FP64 mixed at stated drift"
 HBM_PEAK_GBS = 8000.0
+PAPER_NODE_RATE = 105.7e6   # particle-steps/s of one 64-process POWER6 node on 64 x 500k particles (Sec. 4.5)
 ROOT = os.path.dirname(os.path.abspath(__file__))
 # sources that define the force kernels; a counter record is used only while they are unchanged
 FORCE_SOURCES = ("paper_1012_2677_amd/csrc/md_forces.hip", "paper_1012_2677_amd/csrc/md_internal.h")
@@ -107,7 +113,7 @@ def drift_per_1000(steps_axis, e_per_particle):
     return float(slope * 1000.0)
 
 
-def run_mode(cfg, precision, steps, warmup, sample_every, seed):
+def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, shuffle=False):
     import torch
 
     import lj_inputs as li
@@ -115,10 +121,14 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed):
 
     t0 = time.perf_counter()
     q, L = li.fcc_lattice(cfg["n_fcc"], cfg["rho"])
-    v = li.maxwell_boltzmann(q.shape[0], cfg["T"], seed=seed)
+    v = li.initial_velocities(cfg, q.shape[0], seed=seed)
+    if shuffle:
+        # labels exchanged at random, positions and momenta kept (Sec. 3.3's
+        # stand-in for a long run without re-sorting)
+        q, v, _ = li.shuffle_labels(q, v, seed=seed + 1)
     n = q.shape[0]
     e = Engine(q, v, L, rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], dt=cfg["dt"], precision=precision,
-               resort_every=1, device="cuda:0", timers=True)
+               resort_every=resort_every, device="cuda:0", timers=True)
     del q, v
     e.prepare()
     e0 = e.energies()
@@ -149,7 +159,8 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed):
     tim = e.timer_dict()
     rebuilds = e.rebuilds - reb0
     log(f"[bench] {precision}: {steps} steps in {dt:.3f}s, {rebuilds} rebuilds, timers {tim}")
-    first = warmup + sample_every
+    # rows are written at step numbers (counted from the start) divisible by sample_every
+    first = (warmup // sample_every + 1) * sample_every
     axis = np.arange(first, first + sample_every * len(elog), sample_every, dtype=np.float64)[: len(elog)]
     e_pp = elog[:, 3] / n if len(elog) else np.zeros(0)
     out = {
@@ -182,15 +193,15 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed):
     return out
 
 
-def cpu_baseline(cfg, seconds_target=15.0):
+def cpu_baseline(cfg, seconds_target=20.0):
     """The oracle as it is (plain C, one thread) on a bounded sample of the same
-    workload: the same density, temperature, dt and skin on a 256,000-particle
-    box (40^3 fcc cells), timed over enough steps for ~10-30 s."""
+    workload: the same density, initial velocities, dt and skin on a
+    256,000-particle box (40^3 fcc cells), timed over enough steps for ~10-30 s."""
     import oracle
     import lj_inputs as li
 
     q, L = li.fcc_lattice(40, cfg["rho"])
-    v = li.maxwell_boltzmann(q.shape[0], cfg["T"], seed=0)
+    v = li.initial_velocities(cfg, q.shape[0], seed=0)
     n = q.shape[0]
     t0 = time.perf_counter()
     oracle.run(q, v, L, 2, dt=cfg["dt"], rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], sample_every=0)
@@ -199,17 +210,21 @@ def cpu_baseline(cfg, seconds_target=15.0):
     t0 = time.perf_counter()
     oracle.run(q, v, L, k, dt=cfg["dt"], rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], sample_every=0)
     dt = time.perf_counter() - t0
+    vel = f"|v|={cfg['speed']}" if "speed" in cfg else f"T={cfg['T']}"
     return {"value": n * k / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"N={n} (40^3 fcc cells, rho=0.5, T=1, dt=0.005, rc=2.5, skin=0.3, FP64), "
-                      f"{k} velocity-Verlet steps incl. rebuilds, single thread, {dt:.1f} s"}
+            "sample": f"N={n} (40^3 fcc cells, rho={cfg['rho']}, {vel}, dt={cfg['dt']}, rc={cfg['rc']}, "
+                      f"skin={cfg['skin']}, FP64), {k} velocity-Verlet steps incl. rebuilds, single thread, "
+                      f"{dt:.1f} s"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="lj32m")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 10; 150 for paper*)")
+    ap.add_argument("--config", default="lj32m", help="lj4k, lj4m, lj32m, lj256k, lj131m, paper500k, paper32m")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also time the headline precision without re-sorting, labels shuffled first")
     ap.add_argument("--sample-every", type=int, default=50)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
@@ -230,7 +245,9 @@ def main():
     if args.calibrate_copy:
         print(json.dumps({"calibrate_copy": copy_bandwidth(1 << 30, 3)}), flush=True)
         return
-    cfg = dict(li.CONFIGS[args.config])
+    cfg = dict({**li.CONFIGS, **li.PAPER_CONFIGS}[args.config])
+    if args.warmup is None:
+        args.warmup = cfg.get("warmup", 10)
     headline = cfg["precision"]
     modes = args.modes.split(",") if args.modes else ([headline] + ([] if args.no_fp64 else
                                                                     (["fp64"] if headline != "fp64" else [])))
@@ -240,6 +257,13 @@ def main():
         results[m] = run_mode(cfg, m, args.steps, args.warmup, sample_every, args.seed)
     head = results[modes[0]]
     n = head["n"]
+    ablation = None
+    if args.ablation:
+        ab = run_mode(cfg, modes[0], args.steps, args.warmup, sample_every, args.seed, resort_every=0, shuffle=True)
+        ablation = {"no_resort_shuffled": {k: ab[k] for k in ("value", "ms_per_step", "rebuilds", "timers_ms")},
+                    "resort_every_rebuild_over_no_resort": head["value"] / ab["value"]}
+        log(f"[bench] ablation: no re-sort, shuffled labels: {ab['ms_per_step']:.3f} ms/step "
+            f"(re-sort at every rebuild is {ablation['resort_every_rebuild_over_no_resort']:.2f}x faster)")
     fk = head.get("force_kernel")
     copy = copy_bandwidth()
     log(f"[bench] plain copy: {copy['GBs']:.0f} GB/s")
@@ -258,6 +282,12 @@ def main():
                     "achievable_copy_GBs": round(copy["GBs"], 1),
                     "frac_of_achievable": round(fk["achieved_GBs"] / copy["GBs"], 4)}
     cpu = None if args.no_cpu else cpu_baseline(cfg)
+    vel_desc = (f"|v|={cfg['speed']} in random directions" if "speed" in cfg
+                else f"T={cfg['T']} Maxwell-Boltzmann")
+    # The paper's own number exists only for its own workload: 64 cubes of
+    # 500,000 particles, the share of one node of its POWER6 machine
+    # (105.7 M particle-updates/s, FP64, 2010 hardware).
+    vs_baseline = head["value"] / PAPER_NODE_RATE if (args.config == "paper32m" and modes[0] == "fp64") else None
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -268,16 +298,17 @@ def main():
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": None,
+        "vs_baseline": vs_baseline,
         "dtype": "f32+f64" if modes[0] == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: LJ NVE, N={n} on a {cfg['n_fcc']}^3-cell fcc lattice, rho=0.5, "
-                               f"rc=2.5, skin=0.3, T=1 Maxwell-Boltzmann (seed {args.seed}), dt=0.005, "
-                               f"{modes[0]} precision, cell re-sort at every rebuild",
+        "config": {"workload": f"{args.config}: LJ NVE, N={n} on a {cfg['n_fcc']}^3-cell fcc lattice, "
+                               f"rho={cfg['rho']}, rc={cfg['rc']}, skin={cfg['skin']}, {vel_desc} (seed {args.seed}), "
+                               f"dt={cfg['dt']}, {modes[0]} precision, cell re-sort at every rebuild",
                    "n": n, "box": head["L"], "precision": modes[0], "sample_every": sample_every},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "modes": results,
+        "ablation": ablation,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)

@@ -24,9 +24,12 @@ __all__ = [
     "uniform_box",
     "shuffle_labels",
     "CONFIGS",
+    "PAPER_CONFIGS",
+    "initial_velocities",
 ]
 
-# The five workloads the hot path is exercised on (sizes only).
+# The five workloads the hot path is exercised on (sizes only), Maxwell-Boltzmann
+# velocities at temperature T.
 CONFIGS = {
     "lj4k":   dict(n_fcc=10,  rho=0.5, rc=2.5, skin=0.3, T=1.0, dt=0.005, steps=100,  precision="fp64"),
     "lj4m":   dict(n_fcc=100, rho=0.5, rc=2.5, skin=0.3, T=1.0, dt=0.005, steps=1000, precision="fp64"),
@@ -34,6 +37,25 @@ CONFIGS = {
     "lj256k": dict(n_fcc=40,  rho=0.5, rc=2.5, skin=0.3, T=1.0, dt=0.005, steps=200,  precision="fp64"),
     "lj131m": dict(n_fcc=320, rho=0.5, rc=2.5, skin=0.3, T=1.0, dt=0.005, steps=500,  precision="mixed"),
 }
+
+# The paper's own benchmark conditions (Sec. 4.5): 500,000 particles in a
+# 100^3 box per process, |v| = 0.9 in random directions, dt = 0.001, rc = 2.5,
+# rs = 2.8, 150 untimed steps then 1000 timed, FP64.  paper32m is 64 such
+# cubes in one 400^3 box: the share of one node of the paper's first machine.
+PAPER_CONFIGS = {
+    "paper500k": dict(n_fcc=50,  rho=0.5, rc=2.5, skin=0.3, speed=0.9, dt=0.001, warmup=150, steps=1000,
+                      precision="fp64"),
+    "paper32m":  dict(n_fcc=200, rho=0.5, rc=2.5, skin=0.3, speed=0.9, dt=0.001, warmup=150, steps=1000,
+                      precision="fp64"),
+}
+
+
+def initial_velocities(cfg: dict, n: int, seed: int = 0):
+    """Velocities of a workload: fixed speed in random directions when the
+    config names a speed (the paper's conditions), else Maxwell-Boltzmann at T."""
+    if "speed" in cfg:
+        return fixed_speed_velocities(n, cfg["speed"], seed=seed)
+    return maxwell_boltzmann(n, cfg["T"], seed=seed)
 
 
 def lattice_constant(rho: float) -> float:

@@ -6,6 +6,8 @@
   * the list never misses a pair: at every step of a short run the forces on
     the GPU state equal the oracle's forces recomputed from scratch (<= 1e-12);
   * mixed precision tracks the FP64 oracle (energy per particle to 1e-5);
+  * the paper's benchmark conditions (|v| = 0.9, dt = 0.001) in FP64 and mixed,
+    and a never re-sorted run on shuffled labels, match the oracle;
   * runs are bitwise deterministic;
   * the re-sort is an exact permutation;
   * error paths: non-finite force, positions outside the box, list overflow
@@ -80,6 +82,40 @@ def test_mixed_tracks_fp64(ref):
     n = q.shape[0]
     assert np.abs(log[:, 3] - rlog[:, 3]).max() / n < 1e-5
     assert np.abs(log[:, 1] - rlog[:, 1]).max() / n < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_paper_conditions_match_oracle(ref, precision):
+    # the paper's benchmark conditions (Sec. 4.5) on a 4000-particle cube:
+    # |v| = 0.9 in random directions, dt = 0.001, 150 + 100 steps
+    cfg = li.PAPER_CONFIGS["paper500k"]
+    q, L = li.fcc_lattice(10, cfg["rho"])
+    v = li.initial_velocities(cfg, q.shape[0], seed=5)
+    rs = cfg["rc"] + cfg["skin"]
+    e = _engine(q, v, L, precision=precision, rc=cfg["rc"], rs=rs, dt=cfg["dt"], resort_every=1)
+    log = e.step(250, sample_every=25)
+    rq, rv, rlog, rreb = ref.run(q, v, L, 250, dt=cfg["dt"], rc=cfg["rc"], rs=rs, sample_every=25)
+    n = q.shape[0]
+    if precision == "fp64":
+        assert np.abs(log - rlog).max() <= 1e-10 * np.abs(rlog).max()
+        assert np.abs(_min_image(e.positions() - rq, L)).max() < 1e-8
+        assert e.rebuilds - 1 == rreb
+    else:
+        assert np.abs(log[:, 3] - rlog[:, 3]).max() / n < 1e-5
+        assert np.abs(log[:, 1] - rlog[:, 1]).max() / n < 1e-5
+
+
+def test_no_resort_on_shuffled_labels_matches_oracle(ref):
+    # the re-sort ablation's configuration: labels shuffled, never re-sorted
+    q, L = li.fcc_lattice(10)
+    v = li.maxwell_boltzmann(q.shape[0], T=1.0, seed=6)
+    qs, vs, perm = li.shuffle_labels(q, v, seed=7)
+    e = _engine(qs, vs, L, precision="fp64", resort_every=0)
+    log = e.step(60, sample_every=20)
+    rq, rv, rlog, _ = ref.run(qs, vs, L, 60, dt=0.005, sample_every=20)
+    assert np.abs(log - rlog).max() <= 1e-10 * np.abs(rlog).max()
+    assert np.abs(_min_image(e.positions() - rq, L)).max() < 1e-8
+    assert np.array_equal(e.id.cpu().numpy(), np.arange(q.shape[0]))
 
 
 def test_energy_call_matches_log(ref):
