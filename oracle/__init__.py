@@ -15,6 +15,7 @@ sequence.  Functions and the passages they follow:
   forces_sample             per-particle forces by a direct 27-cell scan
   neighbors_sample          per-particle neighbour sets within rs
   run                       Sec. 2.3 + 4.5 (bookkeeping rule; velocity Verlet)
+  ldc_check                 Sec. 2.3, Alg. alg_validity_check (large-displacement check)
   hvp, param_grad           Hessian-vector product / parameter derivatives
   traj_mean_pe_grad         checkpointed reverse sweep of velocity Verlet
 
@@ -68,7 +69,9 @@ def _load():
                                        _i64, _pi64, _pd, _pd, _pd, _pd, _pi32]),
         "mdref_neighbors_sample": (_i64, [_pd, _pd, _d, _pint, _pi32, _pi32, _pi32, _i64, _pi64,
                                           _i64, _pi32, _pi32]),
-        "mdref_run": (C.c_int, [_i64, _pd, _pd, _pd, _d, _d, _d, _d, _d, _i64, _i64, _pd, _pi64]),
+        "mdref_run": (C.c_int, [_i64, _pd, _pd, _pd, _d, _d, _d, _d, _d, _i64, _i64, _pd, _pi64, C.c_int32,
+                                _i64]),
+        "mdref_ldc_check": (C.c_int, [_i64, _pd, _pd, _pd, _d, _d, _i64, _pi64, _pd]),
         "mdref_hvp": (None, [_i64, _pd, _pd, _d, _d, _d, _d, _pd, _pd, _pd]),
         "mdref_param_grad": (None, [_i64, _pd, _pd, _d, _d, _d, _d, _pd]),
         "mdref_traj_mean_pe_grad": (C.c_int, [_i64, _pd, _pd, _pd, _d, _d, _d, _d, _d, _i64, _i64,
@@ -241,19 +244,41 @@ def neighbors_sample(q, L, idx, rs=2.8, grid=None):
     return [out[e - l:e] for e, l in zip(ends, rowlen)]
 
 
-def run(q, v, L, nsteps, dt=0.005, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, sample_every=1):
-    """Velocity-Verlet NVE run with the skin/2 rebuild rule.  Returns
-    (q, v, log[k, 4] = (KE, PE, W, E), rebuilds)."""
+RULES = {"half_skin": 0, "dutc_ldc": 1}
+
+
+def run(q, v, L, nsteps, dt=0.005, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, sample_every=1, rule="half_skin",
+        ldc_max=8192, full_stats=False):
+    """Velocity-Verlet NVE run.  rule "half_skin": rebuild when some particle
+    moved more than (rs - rc)/2 since the last build; "dutc_ldc": the DUTC and
+    large-displacement check of Alg. alg_validity_check with at most ldc_max
+    members.  Returns (q, v, log[k, 4] = (KE, PE, W, E), rebuilds), plus a dict
+    of statistics when full_stats."""
     q = _q(q).copy()
     v = _q(v).copy()
     k = nsteps // sample_every if sample_every > 0 else 0
     log = np.zeros((max(k, 1), 4))
-    stats = np.zeros(2, np.int64)
+    stats = np.zeros(4, np.int64)
     rc_ = _load().mdref_run(q.shape[0], _p(q), _p(v), _p(_box(L)), eps, sigma, rc, rs, dt, nsteps,
-                            sample_every, _p(log), _p(stats, _pi64))
+                            sample_every, _p(log), _p(stats, _pi64), RULES[rule], int(ldc_max))
     if rc_ != 0:
         raise ValueError("oracle run failed (geometry)")
+    if full_stats:
+        return q, v, log[:k], int(stats[0]), dict(rebuilds=int(stats[0]), pairs=int(stats[1]),
+                                                  ldc_checks=int(stats[2]), ldc_kept=int(stats[3]))
     return q, v, log[:k], int(stats[0])
+
+
+def ldc_check(q, qold, L, rc=2.5, rs=2.8, ldc_max=8192):
+    """Large-displacement check of a list built at qold, at positions q
+    (Alg. alg_validity_check).  Returns (valid, members, max squared
+    displacement)."""
+    q, qold = _q(q), _q(qold)
+    nld = np.zeros(1, np.int64)
+    dm2 = np.zeros(1)
+    ok = _load().mdref_ldc_check(q.shape[0], _p(q), _p(qold), _p(_box(L)), rc, rs, int(ldc_max),
+                                 _p(nld, _pi64), _p(dm2))
+    return bool(ok), int(nld[0]), float(dm2[0])
 
 
 def hvp(q, L, u, eps=1.0, sigma=1.0, rc=2.5, rs=2.8):

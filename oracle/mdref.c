@@ -503,6 +503,71 @@ static double max_disp2(const list_t* ls, const double* q)
     return m;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Validity check of a pair list: DUTC and LDC (Sec. 2.3, Alg. alg_validity_check) */
+/* ------------------------------------------------------------------------- */
+
+/* Large-displacement check.  The list built at positions qold lists every pair
+ * whose (pinned) squared distance was below rs^2.  It becomes invalid only if
+ * some pair not listed (old squared distance >= rs^2; the paper writes "> rs",
+ * read here as the complement of the strict list predicate) now interacts
+ * (squared distance < rc^2).  Such a pair needs dr_i + dr_j > rs - rc, where
+ * dr_i = |q_i - qold_i|, so only particles with dr_i > t = (rs - rc) - dr_max
+ * can take part (dr_max the largest displacement).  The test is made on
+ * squares: member iff t < 0 or dr_i^2 > t^2, with t lowered by 1e-12 so that
+ * rounding can only add members.  More than n_l members invalidates the list
+ * outright; otherwise every pair of members is checked.
+ * Returns 1 if the list is still valid, 0 if not; *n_ld = member count,
+ * *dmax2 = dr_max^2. */
+int mdref_ldc_check(int64_t n, const double* q, const double* qold, const double* L, double rc, double rs,
+                    int64_t n_l, int64_t* n_ld, double* dmax2)
+{
+    double invL[3] = {1.0 / L[0], 1.0 / L[1], 1.0 / L[2]};
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double d2 = pair_r2(qold + 3 * i, q + 3 * i, L, invL, NULL);
+        if (d2 > m) m = d2;
+    }
+    *dmax2 = m;
+    double t = (rs - rc) - sqrt(m) - 1e-12;
+    double t2 = t * t;
+    int64_t cnt = 0;
+    int64_t* ld = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_l > 0 ? n_l : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        double d2 = pair_r2(qold + 3 * i, q + 3 * i, L, invL, NULL);
+        if (t < 0.0 || d2 > t2) {
+            if (cnt < n_l) ld[cnt] = i;
+            ++cnt;
+        }
+    }
+    *n_ld = cnt;
+    int valid = cnt <= n_l;
+    double rs2 = rs * rs, rc2 = rc * rc;
+    for (int64_t a = 0; valid && a < cnt; ++a)
+        for (int64_t b = a + 1; b < cnt; ++b) {
+            const int64_t i = ld[a], j = ld[b];
+            if (pair_r2(qold + 3 * i, qold + 3 * j, L, invL, NULL) >= rs2 &&
+                pair_r2(q + 3 * i, q + 3 * j, L, invL, NULL) < rc2) {
+                valid = 0;
+                break;
+            }
+        }
+    free(ld);
+    return valid;
+}
+
+/* Largest squared speed, |v|^2 = fma(vz,vz, fma(vy,vy, vx*vx)) (the DUTC's
+ * v_max, Sec. 2.3), over the velocities v[n][3]. */
+static double max_speed2(int64_t n, const double* v)
+{
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = fma(v[3 * i + 2], v[3 * i + 2], fma(v[3 * i + 1], v[3 * i + 1], v[3 * i] * v[3 * i]));
+        if (s > m) m = s;
+    }
+    return m;
+}
+
 static acc_t kinetic(int64_t n, const double* v)
 {
     acc_t k = 0.0L;
@@ -513,16 +578,22 @@ static acc_t kinetic(int64_t n, const double* v)
 /* NVE run with velocity Verlet (kick-drift-kick, unit mass):
  *   v += (dt/2) F;  q = wrap(q + dt v);  [rebuild?];  F = F(q);  v += (dt/2) F.
  * The paper specifies a second-order symplectic integrator (Sec. 4.5); velocity
- * Verlet is that scheme.  Bookkeeping rule (Sec. 2.3 and the search-length
- * figure): the list of pairs within rs stays valid until some particle has
- * moved more than half the margin rs - rc from its position at the last build,
- * so the list is rebuilt when max_i |q_i - q_i^ref|^2 > ((rs - rc)/2)^2.
+ * Verlet is that scheme.  Rebuild rules:
+ *   rule 0, half skin (Sec. 2.3 and the search-length figure): the list of
+ *     pairs within rs stays valid until some particle has moved more than half
+ *     the margin rs - rc since the last build, so the list is rebuilt when
+ *     max_i |q_i - q_i^ref|^2 > ((rs - rc)/2)^2;
+ *   rule 1, DUTC then LDC (Alg. alg_validity_check): at each build the buffer
+ *     length is rs - rc; each step it shrinks by 2 v_max dt, with v_max the
+ *     largest speed of the drift just made; while it is positive the list is
+ *     valid, afterwards the large-displacement check decides (n_l members at
+ *     most).
  * Every sample_every steps, log[k] = (KE, PE, W, KE + PE) after the step.
- * stats = (rebuild count, pairs at last build).  Returns 0, or -1 on a
- * geometry error. */
+ * stats = (rebuild count, pairs at last build, LDC checks made, LDC checks that
+ * kept the list).  Returns 0, or -1 on a geometry error. */
 int mdref_run(int64_t n, double* q, double* v, const double* L, double eps, double sigma,
               double rc, double rs, double dt, int64_t nsteps, int64_t sample_every,
-              double* log, int64_t* stats)
+              double* log, int64_t* stats, int32_t rule, int64_t n_l)
 {
     list_t ls;
     memset(&ls, 0, sizeof(ls));
@@ -539,7 +610,8 @@ int mdref_run(int64_t n, double* q, double* v, const double* L, double eps, doub
     double thr2 = half_skin * half_skin;
     double h = 0.5 * dt;
     double pe, w;
-    int64_t rebuilds = 0, k = 0;
+    int64_t rebuilds = 0, k = 0, checks = 0, kept = 0;
+    double buffer = rs - rc;
     if (list_build(&ls, q) != 0) { stats[0] = -1; return -1; }
     mdref_forces_pairs(n, q, L, eps, sigma, rc, ls.npairs, ls.pi, ls.pj, F, &pe, &w);
     for (int64_t s = 1; s <= nsteps; ++s) {
@@ -547,9 +619,24 @@ int mdref_run(int64_t n, double* q, double* v, const double* L, double eps, doub
         for (int64_t i = 0; i < n; ++i)
             for (int a = 0; a < 3; ++a)
                 q[3 * i + a] = wrap_coord(q[3 * i + a] + dt * v[3 * i + a], L[a], invL[a]);
-        if (max_disp2(&ls, q) > thr2) {
+        int rebuild;
+        if (rule == 0) {
+            rebuild = max_disp2(&ls, q) > thr2;
+        } else {
+            buffer -= 2.0 * sqrt(max_speed2(n, v)) * dt;
+            rebuild = 0;
+            if (!(buffer > 0.0)) {
+                int64_t nld;
+                double dm2;
+                ++checks;
+                rebuild = !mdref_ldc_check(n, q, ls.qref, L, rc, rs, n_l, &nld, &dm2);
+                kept += !rebuild;
+            }
+        }
+        if (rebuild) {
             list_build(&ls, q);
             ++rebuilds;
+            buffer = rs - rc;
         }
         mdref_forces_pairs(n, q, L, eps, sigma, rc, ls.npairs, ls.pi, ls.pj, F, &pe, &w);
         for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] + h * F[i];
@@ -564,6 +651,8 @@ int mdref_run(int64_t n, double* q, double* v, const double* L, double eps, doub
     }
     stats[0] = rebuilds;
     stats[1] = ls.npairs;
+    stats[2] = checks;
+    stats[3] = kept;
     free(F); free(ls.qref); free(ls.pi); free(ls.pj);
     return 0;
 }
