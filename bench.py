@@ -113,7 +113,8 @@ def drift_per_1000(steps_axis, e_per_particle):
     return float(slope * 1000.0)
 
 
-def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, shuffle=False):
+def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, shuffle=False,
+             rebuild_rule="half_skin", ldc_max=8192):
     import torch
 
     import lj_inputs as li
@@ -128,7 +129,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
         q, v, _ = li.shuffle_labels(q, v, seed=seed + 1)
     n = q.shape[0]
     e = Engine(q, v, L, rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], dt=cfg["dt"], precision=precision,
-               resort_every=resort_every, device="cuda:0", timers=True)
+               resort_every=resort_every, rebuild_rule=rebuild_rule, ldc_max=ldc_max, device="cuda:0", timers=True)
     del q, v
     e.prepare()
     e0 = e.energies()
@@ -141,6 +142,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
         e.timers.ms[k] = 0.0
         e.timers.launches[k] = 0
     reb0 = e.rebuilds
+    ldc0 = e.ldc_stats
     # the paper's own protocol also reports the rate after its first 150 steps
     split = 150 if steps >= 300 and steps % sample_every == 0 and 150 % sample_every == 0 else 0
     torch.cuda.synchronize()
@@ -170,6 +172,8 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
         "value": n * steps / dt,
         "ms_per_step": 1e3 * dt / steps,
         "rebuilds": rebuilds,
+        "rebuild_rule": rebuild_rule,
+        "ldc_checks_kept": [e.ldc_stats[0] - ldc0[0], e.ldc_stats[1] - ldc0[1]],
         "mean_list_entries": entries / n,
         "timers_ms": {k: [round(m, 3), c] for k, (m, c) in tim.items()},
         "energy_per_particle_start": float(e0[3] / n),
@@ -223,6 +227,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 10; 150 for paper*)")
     ap.add_argument("--config", default="lj32m", help="lj4k, lj4m, lj32m, lj256k, lj131m, paper500k, paper32m")
+    ap.add_argument("--rebuild-rule", default="half_skin", choices=["half_skin", "dutc_ldc"],
+                    help="pair-list validity rule (dutc_ldc: Alg. alg_validity_check)")
+    ap.add_argument("--ldc-max", type=int, default=8192, help="most particles in the large-displacement check")
     ap.add_argument("--ablation", action="store_true",
                     help="also time the headline precision without re-sorting, labels shuffled first")
     ap.add_argument("--sample-every", type=int, default=50)
@@ -254,7 +261,8 @@ def main():
     sample_every = min(args.sample_every, max(1, args.steps))
     results = {}
     for m in modes:
-        results[m] = run_mode(cfg, m, args.steps, args.warmup, sample_every, args.seed)
+        results[m] = run_mode(cfg, m, args.steps, args.warmup, sample_every, args.seed,
+                              rebuild_rule=args.rebuild_rule, ldc_max=args.ldc_max)
     head = results[modes[0]]
     n = head["n"]
     ablation = None
@@ -303,7 +311,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: LJ NVE, N={n} on a {cfg['n_fcc']}^3-cell fcc lattice, "
                                f"rho={cfg['rho']}, rc={cfg['rc']}, skin={cfg['skin']}, {vel_desc} (seed {args.seed}), "
-                               f"dt={cfg['dt']}, {modes[0]} precision, cell re-sort at every rebuild",
+                               f"dt={cfg['dt']}, {modes[0]} precision, cell re-sort at every rebuild, "
+                               f"{args.rebuild_rule} rebuild rule",
                    "n": n, "box": head["L"], "precision": modes[0], "sample_every": sample_every},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -59,6 +59,10 @@ extern "C" {
 
 #define MD_MAX_N ((int64_t)1 << 27)   /* slots are stored in 27 bits of a list entry */
 
+/* pair-list rebuild rules (md_params.rebuild_rule) */
+#define MD_REBUILD_HALF_SKIN 0   /* rebuild once some particle moved more than (rs - rc)/2         */
+#define MD_REBUILD_DUTC_LDC  1   /* DUTC, then the large-displacement check (Alg. alg_validity_check) */
+
 /* Model and run parameters.
  *   V(r) = 4 eps [ (sigma/r)^12 - (sigma/r)^6 + c2 (r/sigma)^2 + c0 ] for r < rc,
  *   with c2, c0 fixed by V(rc) = V'(rc) = 0 (Sec. 2.1, eq. lj_cutoff); rc and rs
@@ -67,7 +71,13 @@ extern "C" {
  *   build (the search-length figure of Sec. 2.3).  Cells per axis are
  *   floor(L / rs) (cell side >= rs, Sec. 2.2).
  *   resort_every: re-sort the particle arrays into cell order at every k-th
- *   rebuild (Sec. 3.3; 0 = never, 1 = every rebuild). */
+ *   rebuild (Sec. 3.3; 0 = never, 1 = every rebuild).
+ *   rebuild_rule: MD_REBUILD_HALF_SKIN, or MD_REBUILD_DUTC_LDC (Sec. 2.3,
+ *   Alg. alg_validity_check): a buffer rs - rc shrinks by 2 v_max dt per step
+ *   (v_max the largest speed of the step's drift); while it is positive the
+ *   list is valid, afterwards md_ldc_check decides each step.
+ *   ldc_max: the most particles the large-displacement check takes (N_l of
+ *   the algorithm); more invalidate the list outright.  0 <= ldc_max <= 2^22. */
 typedef struct md_params {
     int64_t n;
     double  box[3];
@@ -76,6 +86,8 @@ typedef struct md_params {
     double  dt;
     int32_t precision;     /* MD_FP64 or MD_MIXED */
     int32_t resort_every;
+    int32_t rebuild_rule;  /* MD_REBUILD_HALF_SKIN or MD_REBUILD_DUTC_LDC */
+    int32_t ldc_max;
 } md_params;
 
 /* Cell grid (Sec. 2.2): GridParticleNumber = count, GridPointer = start,
@@ -125,7 +137,7 @@ typedef struct md_pairlist {
 
 /* Per-kernel-class timers filled by md_step when md_state.timers != NULL:
  * HIP-event time summed over launches, in milliseconds. */
-enum { MD_T_FORCE = 0, MD_T_INTEGRATE, MD_T_BIN, MD_T_RESORT, MD_T_BUILD, MD_T_REDUCE, MD_T_COUNT };
+enum { MD_T_FORCE = 0, MD_T_INTEGRATE, MD_T_BIN, MD_T_RESORT, MD_T_BUILD, MD_T_REDUCE, MD_T_CHECK, MD_T_COUNT };
 typedef struct md_timers {
     double  ms[MD_T_COUNT];
     int64_t launches[MD_T_COUNT];
@@ -146,13 +158,17 @@ typedef struct md_timers {
  *   at the current positions; inside a run they are consumed by the fused
  *   kicks and not stored.
  *   energy: device double[8]: KE, PE, W, E at the last sampled step, then
- *   max squared displacement, reserved.
+ *   the largest squared displacement since the last build and the largest
+ *   squared drift speed of the last step, reserved.
  *   flags: device int64[8]: [0] non-finite force seen, others reserved.
  *   host_scratch: host int64[16] (pinned recommended) for flag read-back.
  *   ws: device workspace of ws_bytes >= md_workspace_bytes().
  *   step, rebuilds, resorts: host counters; phase: 0 = (q, v, F) at a whole
  *   step, 1 = stopped after a drift (resumed by the next md_step), 2 = arrays
- *   re-sorted by md_resort (md_prepare needed). */
+ *   re-sorted by md_resort (md_prepare needed).
+ *   dutc_buffer: remaining DUTC buffer length (MD_REBUILD_DUTC_LDC; reset to
+ *   rs - rc at each build); ldc_checks, ldc_kept: large-displacement checks
+ *   made, and those that kept the list. */
 typedef struct md_state {
     double*   pos;
     double*   vel;
@@ -177,6 +193,9 @@ typedef struct md_state {
     int64_t   resorts;
     int32_t   phase;
     int32_t   list_valid;
+    double    dutc_buffer;
+    int64_t   ldc_checks;
+    int64_t   ldc_kept;
 } md_state;
 
 /* Host-only: cells per axis for these parameters.  MD_ERR_BOX when an axis
@@ -229,6 +248,19 @@ int md_build_pairlist(const md_params* p, const double* pos, const md_cells* cel
 int md_forces(const md_params* p, const double* pos, const md_cells* cells,
               const md_pairlist* list, void* force, double* pe_w,
               void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Large-displacement check (Sec. 2.3, Alg. alg_validity_check) of a list
+ * built at pos_ref, at positions pos: the particles whose displacement
+ * |minimg(q - q_ref)| exceeds t = (rs - rc) - max displacement - 1e-12 are
+ * members (all of them when t < 0; the test is made on squares,
+ * d2 > t^2, with d2 = fma(dz,dz, fma(dy,dy, dx*dx))); more than p->ldc_max
+ * members invalidate the list, otherwise it is invalid iff some pair of
+ * members has old squared distance >= rs^2 and new squared distance < rc^2.
+ * pos: device double[n][4]; pos_ref: device double[3][n].  Results go to host
+ * memory: *valid (1 or 0), *members, *dmax2 (largest squared displacement).
+ * Synchronises the stream. */
+int md_ldc_check(const md_params* p, const double* pos, const double* pos_ref, int32_t* valid,
+                 int64_t* members, double* dmax2, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Bin, (re-sort if resort_every > 0), build the list and evaluate forces and
  * energies at the current positions; leaves st at phase 0.  Synchronises.

@@ -26,12 +26,15 @@ MD_FP64 = 0
 MD_MIXED = 1
 MD_MAX_N = 1 << 27
 
-MD_T_FORCE, MD_T_INTEGRATE, MD_T_BIN, MD_T_RESORT, MD_T_BUILD, MD_T_REDUCE, MD_T_COUNT = range(7)
-TIMER_NAMES = ["force", "integrate", "bin", "resort", "build", "reduce"]
+MD_REBUILD_HALF_SKIN = 0
+MD_REBUILD_DUTC_LDC = 1
+
+MD_T_FORCE, MD_T_INTEGRATE, MD_T_BIN, MD_T_RESORT, MD_T_BUILD, MD_T_REDUCE, MD_T_CHECK, MD_T_COUNT = range(8)
+TIMER_NAMES = ["force", "integrate", "bin", "resort", "build", "reduce", "check"]
 
 EXPORTED = ["md_cell_dims", "md_workspace_bytes", "md_pack_positions", "md_bin_cells", "md_resort", "md_build_pairlist",
             "md_forces", "md_prepare", "md_step", "md_energy", "md_hvp", "md_adjoint_kick", "md_param_grad",
-            "md_last_error"]
+            "md_ldc_check", "md_last_error"]
 
 
 class MdError(RuntimeError):
@@ -43,7 +46,7 @@ class MdError(RuntimeError):
 class MdParams(C.Structure):
     _fields_ = [("n", C.c_int64), ("box", C.c_double * 3), ("eps", C.c_double), ("sigma", C.c_double),
                 ("rc", C.c_double), ("rs", C.c_double), ("dt", C.c_double), ("precision", C.c_int32),
-                ("resort_every", C.c_int32)]
+                ("resort_every", C.c_int32), ("rebuild_rule", C.c_int32), ("ldc_max", C.c_int32)]
 
 
 class MdCells(C.Structure):
@@ -68,7 +71,8 @@ class MdState(C.Structure):
                 ("flags", C.c_void_p), ("host_scratch", C.c_void_p), ("ws", C.c_void_p),
                 ("ws_bytes", C.c_size_t), ("timers", C.POINTER(MdTimers)), ("step", C.c_int64),
                 ("rebuilds", C.c_int64), ("resorts", C.c_int64), ("phase", C.c_int32),
-                ("list_valid", C.c_int32)]
+                ("list_valid", C.c_int32), ("dutc_buffer", C.c_double), ("ldc_checks", C.c_int64),
+                ("ldc_kept", C.c_int64)]
 
 
 _lib = None
@@ -100,6 +104,8 @@ def lib():
         "md_adjoint_kick": (C.c_int, [P(MdParams), vp, P(MdCells), P(MdPairlist), vp, vp, vp,
                                       P(C.c_double), vp, vp, C.c_size_t, vp]),
         "md_param_grad": (C.c_int, [P(MdParams), vp, P(MdCells), P(MdPairlist), vp, vp, C.c_size_t, vp]),
+        "md_ldc_check": (C.c_int, [P(MdParams), vp, vp, P(C.c_int32), P(C.c_int64), P(C.c_double), vp,
+                                   C.c_size_t, vp]),
         "md_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -182,3 +188,11 @@ def md_adjoint_kick(params, pos, cells, plist, u, out, u_out, coef, acc, ws, ws_
 def md_param_grad(params, pos, cells, plist, dU, ws, ws_bytes, stream):
     return _check(lib().md_param_grad(C.byref(params), pos, C.byref(cells), C.byref(plist), dU, ws, ws_bytes,
                                       stream), "md_param_grad")
+
+
+def md_ldc_check(params, pos, pos_ref, ws, ws_bytes, stream):
+    """(valid, members, max squared displacement) of the large-displacement check."""
+    valid, members, dmax2 = C.c_int32(0), C.c_int64(0), C.c_double(0.0)
+    _check(lib().md_ldc_check(C.byref(params), pos, pos_ref, C.byref(valid), C.byref(members), C.byref(dmax2),
+                              ws, ws_bytes, stream), "md_ldc_check")
+    return bool(valid.value), int(members.value), float(dmax2.value)

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmd355.so")
-SOURCES = ["md_api.hip", "md_cells.hip", "md_pairlist.hip", "md_forces.hip", "md_integrate.hip",
+SOURCES = ["md_api.hip", "md_cells.hip", "md_pairlist.hip", "md_forces.hip", "md_integrate.hip", "md_validity.hip",
            "md_adjoint.hip"]
 ARCH = "gfx950"
 

@@ -43,6 +43,9 @@ static int check_params(const md_params* p, int32_t nc[3])
     if (!(p->rc > 0.0) || !(p->rs >= p->rc)) return fail(MD_ERR_ARG, "need 0 < rc <= rs");
     if (p->precision != MD_FP64 && p->precision != MD_MIXED) return fail(MD_ERR_ARG, "precision must be 0 or 1");
     if (p->resort_every < 0) return fail(MD_ERR_ARG, "resort_every must be >= 0");
+    if (p->rebuild_rule != MD_REBUILD_HALF_SKIN && p->rebuild_rule != MD_REBUILD_DUTC_LDC)
+        return fail(MD_ERR_ARG, "rebuild_rule must be 0 or 1");
+    if (p->ldc_max < 0 || p->ldc_max > (1 << 22)) return fail(MD_ERR_ARG, "ldc_max must be in [0, 2^22]");
     for (int k = 0; k < 3; ++k) {
         const double m = std::floor(p->box[k] / p->rs);
         if (m < 3.0) return fail(MD_ERR_BOX, "axis %d has %.0f cells (< 3): box too small for rs", k, m);
@@ -101,7 +104,14 @@ LJ make_lj(const md_params& p)
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-WsLayout ws_layout(const Geo& g)
+// Small device scalars in the workspace (int64 words):
+//   [0], [1]  cell-grid error flags         [2]  md_forces non-finite flag
+//   [4]       large-displacement members    [5]  large-displacement violation
+//   [6]       largest squared displacement (md_ldc_check)
+//   [16..31]  flags gathered for one read-back (layout in k_gather_flags)
+constexpr int kScalOut = 16;
+
+WsLayout ws_layout(const Geo& g, int64_t ldc_max)
 {
     const int64_t n = g.n, ncell = g.ncell;
     WsLayout L;
@@ -117,7 +127,8 @@ WsLayout ws_layout(const Geo& g)
     L.part_b = off;    off = align256(off + sizeof(double) * (size_t)(np > L.nbi ? np : L.nbi));
     L.pos32 = off;     off = align256(off + 16 * (size_t)n);
     L.red = off;       off = align256(off + sizeof(int64_t) * 2 * 1024);
-    L.scal = off;      off = align256(off + sizeof(double) * 16);
+    L.ldc = off;       off = align256(off + sizeof(int32_t) * (size_t)(ldc_max > 0 ? ldc_max : 1));
+    L.scal = off;      off = align256(off + sizeof(int64_t) * 32);
     L.total = off;
     return L;
 }
@@ -135,7 +146,7 @@ static int setup(const md_params* p, Ctx& c)
     if (rc != MD_OK) return rc;
     c.g = make_geo(*p, c.nc);
     c.lj = make_lj(*p);
-    c.W = ws_layout(c.g);
+    c.W = ws_layout(c.g, p->ldc_max);
     return MD_OK;
 }
 
@@ -243,7 +254,7 @@ size_t md_workspace_bytes(const md_params* p)
 {
     int32_t nc[3];
     if (check_params(p, nc) != MD_OK) return 0;
-    return ws_layout(make_geo(*p, nc)).total;
+    return ws_layout(make_geo(*p, nc), p->ldc_max).total;
 }
 
 int md_pack_positions(const md_params* p, const double* q, double* pos, hipStream_t stream)
@@ -429,15 +440,15 @@ static int rebuild(const Ctx& c, const md_params* p, md_state* st, bool allow_re
 
 // wait for the stream and read, in one copy: list status [0..3], cell-grid
 // error flags [4..5], force flags [6], max squared displacement bits [7]
-static int read_flags(const Ctx& c, md_state* st, hipStream_t s, int64_t out[8])
+static int read_flags(const Ctx& c, md_state* st, hipStream_t s, int64_t out[16])
 {
     int64_t* scal = (int64_t*)((char*)st->ws + c.W.scal);
-    MD_HIP(launch_gather_flags(st->list.status, scal, st->flags, st->energy, scal + 8, s), "flags/gather");
+    MD_HIP(launch_gather_flags(st->list.status, scal, st->flags, st->energy, scal + kScalOut, s), "flags/gather");
     int64_t local[16];
     int64_t* dst = st->host_scratch ? st->host_scratch : local;
-    MD_HIP(hipMemcpyAsync(dst, scal + 8, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s), "flags/copy");
+    MD_HIP(hipMemcpyAsync(dst, scal + kScalOut, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, s), "flags/copy");
     MD_HIP(hipStreamSynchronize(s), "flags/sync");
-    for (int k = 0; k < 8; ++k) out[k] = dst[k];
+    for (int k = 0; k < 16; ++k) out[k] = dst[k];
     return MD_OK;
 }
 
@@ -466,18 +477,90 @@ static IntArgs int_args(const Ctx& c, const md_params* p, md_state* st, bool ke)
     a.cell_xyz = st->cells.cell_xyz;
     a.part_ke = ke ? (double*)((char*)st->ws + c.W.part_b) : nullptr;
     a.max_d2 = (unsigned long long*)(st->energy + 4);
+    a.max_v2 = (unsigned long long*)(st->energy + 5);
     a.dt = p->dt;
     a.precision = p->precision;
     return a;
 }
 
-static int check_status(const int64_t f[8], const md_state* st)
+static int check_status(const int64_t f[16], const md_state* st)
 {
     if (f[2] != 0)
         return fail(MD_ERR_CAPACITY, "pair list overflow: a cell needs %lld entries, cell_stride is %lld",
                     (long long)f[1], (long long)st->list.cell_stride);
     if (f[4] & 2) return fail(MD_ERR_ARG, "positions outside [0, L) given to the cell grid");
     if (f[6] & 1) return fail(MD_ERR_NONFINITE, "non-finite force");
+    return MD_OK;
+}
+
+// Threshold of the large-displacement check from the largest squared
+// displacement: members have displacement > t (lowered by 1e-12 so that
+// rounding can only add members).
+static double ldc_threshold(const md_params* p, double dmax2)
+{
+    return (p->rs - p->rc) - std::sqrt(dmax2) - 1e-12;
+}
+
+// One large-displacement check inside md_step (positions after the drift).
+static int ldc_step(const Ctx& c, const md_params* p, md_state* st, double dmax2, Timer& T, hipStream_t s,
+                    bool* keep)
+{
+    st->ldc_checks += 1;
+    // Two outcomes need no kernel and give the same decision: t >= 0 with
+    // max d2 <= t^2, so there are no members (kept); or t < 0, so everyone is a
+    // member, more than ldc_max (expired).
+    const double t = ldc_threshold(p, dmax2);
+    if (t >= 0.0 && dmax2 <= t * t) {
+        *keep = true;
+        st->ldc_kept += 1;
+        return MD_OK;
+    }
+    if (t < 0.0 && c.g.n > (int64_t)p->ldc_max) {
+        *keep = false;
+        return MD_OK;
+    }
+    int64_t* scal = (int64_t*)((char*)st->ws + c.W.scal);
+    tick(T, MD_T_CHECK, 0, s);
+    MD_HIP(launch_fill_i32((int32_t*)(scal + 4), 0, 4, s), "ldc/clear");
+    MD_HIP(launch_ldc_check(c.g, st->pos, st->pos_ref, p->rc, p->rs, t, p->ldc_max,
+                            (int32_t*)((char*)st->ws + c.W.ldc), (unsigned long long*)(scal + 4),
+                            (unsigned long long*)(scal + 5), s),
+           "ldc/check");
+    tick(T, MD_T_CHECK, 1, s);
+    int64_t f[16];
+    int rc = read_flags(c, st, s, f);
+    if (rc != MD_OK) return rc;
+    timer_collect(T);
+    *keep = f[9] <= (int64_t)p->ldc_max && f[10] == 0;
+    st->ldc_kept += *keep ? 1 : 0;
+    return MD_OK;
+}
+
+int md_ldc_check(const md_params* p, const double* pos, const double* pos_ref, int32_t* valid,
+                 int64_t* members, double* dmax2, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if (!pos || !pos_ref || !valid || !members || !dmax2) return fail(MD_ERR_ARG, "NULL argument");
+    if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
+    int64_t* scal = (int64_t*)((char*)ws + c.W.scal);
+    MD_HIP(launch_fill_i32((int32_t*)(scal + 4), 0, 6, stream), "md_ldc_check/clear");
+    MD_HIP(launch_ldc_disp(c.g, pos, pos_ref, (unsigned long long*)(scal + 6), stream), "md_ldc_check/disp");
+    int64_t h[3];
+    MD_HIP(hipMemcpyAsync(h, scal + 4, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, stream), "md_ldc_check/copy");
+    MD_HIP(hipStreamSynchronize(stream), "md_ldc_check/sync");
+    double m2;
+    std::memcpy(&m2, &h[2], sizeof(double));
+    MD_HIP(launch_ldc_check(c.g, pos, pos_ref, p->rc, p->rs, ldc_threshold(p, m2), p->ldc_max,
+                            (int32_t*)((char*)ws + c.W.ldc), (unsigned long long*)(scal + 4),
+                            (unsigned long long*)(scal + 5), stream),
+           "md_ldc_check/check");
+    MD_HIP(hipMemcpyAsync(h, scal + 4, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, stream), "md_ldc_check/copy");
+    MD_HIP(hipStreamSynchronize(stream), "md_ldc_check/sync");
+    *members = h[0];
+    *valid = (h[0] <= (int64_t)p->ldc_max && h[1] == 0) ? 1 : 0;
+    *dmax2 = m2;
     return MD_OK;
 }
 
@@ -514,7 +597,8 @@ int md_prepare(const md_params* p, md_state* st, hipStream_t s)
     MD_HIP(launch_fill_i32((int32_t*)((char*)st->ws + c.W.scal), 0, 4, s), "prepare/err");
     if ((rc = rebuild(c, p, st, true, T, s)) != MD_OK) return rc;
     st->rebuilds += 1;
-    int64_t f[8];
+    st->dutc_buffer = p->rs - p->rc;
+    int64_t f[16];
     if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
     if ((rc = check_status(f, st)) != MD_OK) {
         st->list_valid = 0;
@@ -581,20 +665,36 @@ int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_eve
         if (need_drift) {
             // first half kick and drift of this step (the previous step ended
             // with a completed kick, or this is the first step of the call)
-            MD_HIP(launch_fill_i32((int32_t*)(st->energy + 4), 0, 2, s), "step/maxd2");
+            MD_HIP(launch_fill_i32((int32_t*)(st->energy + 4), 0, 4, s), "step/maxd2");
             tick(T, MD_T_INTEGRATE, 0, s);
             MD_HIP(launch_integrate(c.g, INT_KD, int_args(c, p, st, false), s), "step/kd");
             tick(T, MD_T_INTEGRATE, 1, s);
             st->phase = 1;
         }
-        int64_t f[8];
+        int64_t f[16];
         if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
         timer_collect(T);
-        double maxd2;
+        double maxd2, maxv2;
         std::memcpy(&maxd2, &f[7], sizeof(double));
-        if (!st->list_valid || maxd2 > thr2) {
+        std::memcpy(&maxv2, &f[8], sizeof(double));
+        bool expired = !st->list_valid;
+        if (!expired && p->rebuild_rule == MD_REBUILD_HALF_SKIN) {
+            expired = maxd2 > thr2;
+        } else if (!expired) {
+            // DUTC: the buffer shrinks by twice the distance the fastest
+            // particle drifted; once it is used up, the large-displacement
+            // check decides
+            st->dutc_buffer -= 2.0 * std::sqrt(maxv2) * p->dt;
+            if (!(st->dutc_buffer > 0.0)) {
+                bool keep = false;
+                if ((rc = ldc_step(c, p, st, maxd2, T, s, &keep)) != MD_OK) return rc;
+                expired = !keep;
+            }
+        }
+        if (expired) {
             if ((rc = rebuild(c, p, st, true, T, s)) != MD_OK) return rc;
             st->rebuilds += 1;
+            st->dutc_buffer = p->rs - p->rc;
             if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
             timer_collect(T);
             if (f[2] != 0) {
@@ -622,9 +722,10 @@ int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_eve
         io.pos_out = mixed ? st->pos : st->pos_alt;
         io.pos32_out = mixed ? st->pos32_alt : nullptr;
         io.max_d2 = (unsigned long long*)(st->energy + 4);
+        io.max_v2 = (unsigned long long*)(st->energy + 5);
         io.dt = p->dt;
         io.drift = !last;
-        if (!last) MD_HIP(launch_fill_i32((int32_t*)(st->energy + 4), 0, 2, s), "step/maxd2");
+        if (!last) MD_HIP(launch_fill_i32((int32_t*)(st->energy + 4), 0, 4, s), "step/maxd2");
         tick(T, MD_T_FORCE, 0, s);
         MD_HIP(launch_force_step(c.g, c.lj, p->precision, io, s), "step/force");
         tick(T, MD_T_FORCE, 1, s);

@@ -60,6 +60,7 @@ struct PairArgs {
     double4* pos_out;          // positions after the drift (MODE_KKD; FP64: other buffer)
     float4* pos32_out;         // mixed: local coordinates after the drift (other buffer)
     unsigned long long* max_d2;  // atomic max of squared displacement bits (MODE_KKD)
+    unsigned long long* max_v2;  // atomic max of squared drift speed bits (MODE_KKD)
     double dt;
 };
 
@@ -138,10 +139,10 @@ __device__ __forceinline__ float local_coord(double x, int c, double cs, double 
 // Block-level epilogue: (PE, W) and KE partials, displacement maximum.
 template <bool ENERGY, int MODE>
 __device__ __forceinline__ void block_epilogue(const PairArgs& a, int64_t blk, double pe, double w, double ke,
-                                               double d2)
+                                               double d2, double v2)
 {
     constexpr int NW = kForceBlock / 64;
-    __shared__ double s_r[4][NW];
+    __shared__ double s_r[5][NW];
     const int wave = threadIdx.x >> 6;
     if (ENERGY) {
 #pragma unroll
@@ -153,30 +154,38 @@ __device__ __forceinline__ void block_epilogue(const PairArgs& a, int64_t blk, d
     }
     if (MODE == MODE_KKD) {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) d2 = fmax(d2, __shfl_xor(d2, o, 64));
+        for (int o = 32; o > 0; o >>= 1) {
+            d2 = fmax(d2, __shfl_xor(d2, o, 64));
+            v2 = fmax(v2, __shfl_xor(v2, o, 64));
+        }
     }
     if ((threadIdx.x & 63) == 0) {
         s_r[0][wave] = pe;
         s_r[1][wave] = w;
         s_r[2][wave] = ke;
         s_r[3][wave] = d2;
+        s_r[4][wave] = v2;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double spe = 0.0, sw = 0.0, ske = 0.0, m = 0.0;
+        double spe = 0.0, sw = 0.0, ske = 0.0, m = 0.0, mv = 0.0;
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
             spe += s_r[0][k];
             sw += s_r[1][k];
             ske += s_r[2][k];
             m = fmax(m, s_r[3][k]);
+            mv = fmax(mv, s_r[4][k]);
         }
         if (ENERGY) {
             a.part_pw[2 * blk] = 0.5 * spe;
             a.part_pw[2 * blk + 1] = 0.5 * sw;
             if (MODE != MODE_FORCE) a.part_ke[blk] = 0.5 * ske;
         }
-        if (MODE == MODE_KKD) atomicMax(a.max_d2, (unsigned long long)__double_as_longlong(m));
+        if (MODE == MODE_KKD) {
+            atomicMax(a.max_d2, (unsigned long long)__double_as_longlong(m));
+            atomicMax(a.max_v2, (unsigned long long)__double_as_longlong(mv));
+        }
     }
 }
 
@@ -184,7 +193,7 @@ __device__ __forceinline__ void block_epilogue(const PairArgs& a, int64_t blk, d
 // the last build.  Same arithmetic as the stand-alone integrator.
 template <int MODE, bool MIXED>
 __device__ __forceinline__ void integrate_key(const PairArgs& a, int64_t k, double fx, double fy, double fz,
-                                              double& ke, double& d2)
+                                              double& ke, double& d2, double& v2)
 {
     const int64_t n = a.n;
     const double h = 0.5 * a.dt;
@@ -208,6 +217,7 @@ __device__ __forceinline__ void integrate_key(const PairArgs& a, int64_t k, doub
         vx = vx + h * fx;
         vy = vy + h * fy;
         vz = vz + h * fz;
+        v2 = pinned_len2(vx, vy, vz);
         p.x = wrap_coord(p.x + a.dt * vx, a.L[0], a.invL[0]);
         p.y = wrap_coord(p.y + a.dt * vy, a.L[1], a.invL[1]);
         p.z = wrap_coord(p.z + a.dt * vz, a.L[2], a.invL[2]);
@@ -215,7 +225,7 @@ __device__ __forceinline__ void integrate_key(const PairArgs& a, int64_t k, doub
         ex -= a.L[0] * rint(ex * a.invL[0]);
         ey -= a.L[1] * rint(ey * a.invL[1]);
         ez -= a.L[2] * rint(ez * a.invL[2]);
-        d2 = ex * ex + ey * ey + ez * ez;
+        d2 = pinned_len2(ex, ey, ez);
         a.pos_out[k] = p;
         if (MIXED)
             a.pos32_out[k] = make_float4(local_coord(p.x, c & 1023, a.cs[0], a.L[0], a.invL[0]),
@@ -239,7 +249,7 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_fp64(
     int64_t kb, kend;
     block_keys(a, blk, kb, kend);
     const double rc2 = a.lj.rc2, A = a.lj.A, B = a.lj.B, C8 = a.lj.C8;
-    double pe = 0.0, w = 0.0, ke = 0.0, d2 = 0.0;
+    double pe = 0.0, w = 0.0, ke = 0.0, d2 = 0.0, v2 = 0.0;
     // each wave takes 64-key chunks of the block's range (a wave-uniform loop;
     // the LDS rows below are private to the wave, so no block barrier inside;
     // written as a loop, which also schedules better than a straight pass)
@@ -328,15 +338,16 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_fp64(
             F[2 * a.n + mykey] = kfz;
         }
         if (MODE != MODE_FORCE) {
-            double kk = 0.0, dd = 0.0;
-            integrate_key<MODE, false>(a, mykey, kfx, kfy, kfz, kk, dd);
+            double kk = 0.0, dd = 0.0, vv = 0.0;
+            integrate_key<MODE, false>(a, mykey, kfx, kfy, kfz, kk, dd, vv);
             ke += kk;
             d2 = fmax(d2, dd);
+            v2 = fmax(v2, vv);
         }
     }
     __builtin_amdgcn_wave_barrier();
     }
-    if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE>(a, blk, pe, w, ke, d2);
+    if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE>(a, blk, pe, w, ke, d2, v2);
 }
 
 template <int U, bool ENERGY, int MODE>
@@ -360,7 +371,7 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed
     int64_t kb, kend;
     block_keys(a, blk, kb, kend);
     const float rc2 = (float)a.lj.rc2, A = (float)a.lj.A, B = (float)a.lj.B, C8 = (float)a.lj.C8;
-    double pe = 0.0, w = 0.0, ke = 0.0, d2 = 0.0;
+    double pe = 0.0, w = 0.0, ke = 0.0, d2 = 0.0, v2 = 0.0;
     // each wave takes 64-key chunks of the block's range (a wave-uniform loop;
     // the LDS rows below are private to the wave, so no block barrier inside;
     // written as a loop, which also schedules better than a straight pass)
@@ -440,15 +451,16 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed
             F[2 * a.n + mykey] = kfz;
         }
         if (MODE != MODE_FORCE) {
-            double kk = 0.0, dd = 0.0;
-            integrate_key<MODE, true>(a, mykey, kfx, kfy, kfz, kk, dd);
+            double kk = 0.0, dd = 0.0, vv = 0.0;
+            integrate_key<MODE, true>(a, mykey, kfx, kfy, kfz, kk, dd, vv);
             ke += kk;
             d2 = fmax(d2, dd);
+            v2 = fmax(v2, vv);
         }
     }
     __builtin_amdgcn_wave_barrier();
     }
-    if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE>(a, blk, pe, w, ke, d2);
+    if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE>(a, blk, pe, w, ke, d2, v2);
 }
 
 int64_t pair_blocks(const Geo& g) { return ceil_div(g.n, kForceBlock); }
@@ -519,6 +531,7 @@ hipError_t launch_force_step(const Geo& g, const LJ& lj, int precision, const St
     a.pos_out = (double4*)io.pos_out;
     a.pos32_out = (float4*)io.pos32_out;
     a.max_d2 = io.max_d2;
+    a.max_v2 = io.max_v2;
     a.dt = io.dt;
     const bool energy = io.part_pw != nullptr;
     if (io.drift) {

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
     double* __restrict__ vel = a.vel;
     double4* __restrict__ P = (double4*)a.pos;
     const double* __restrict__ ref = a.pos_ref;
-    double ke = 0.0, d2 = 0.0;
+    double ke = 0.0, d2 = 0.0, v2 = 0.0;
     if (valid) {
         // every input is loaded before anything is stored, so all loads of a
         // thread are in flight together
@@ -79,6 +79,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
             vx = vx + h * fx;
             vy = vy + h * fy;
             vz = vz + h * fz;
+            v2 = pinned_len2(vx, vy, vz);
             p.x = wrap_coord(p.x + a.dt * vx, g.L[0], g.invL[0]);
             p.y = wrap_coord(p.y + a.dt * vy, g.L[1], g.invL[1]);
             p.z = wrap_coord(p.z + a.dt * vz, g.L[2], g.invL[2]);
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
             ex -= g.L[0] * rint(ex * g.invL[0]);
             ey -= g.L[1] * rint(ey * g.invL[1]);
             ez -= g.L[2] * rint(ez * g.invL[2]);
-            d2 = ex * ex + ey * ey + ez * ez;
+            d2 = pinned_len2(ex, ey, ez);
             P[i] = p;
             if (MIXED) {
                 ((float4*)a.pos32)[i] =
@@ -99,17 +100,27 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
             vel[2 * n + i] = vz;
         }
     }
-    __shared__ double s_v[kStreamBlock / 64];
+    __shared__ double s_v[kStreamBlock / 64], s_u[kStreamBlock / 64];
     if (DRIFT) {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) d2 = fmax(d2, __shfl_xor(d2, o, 64));
-        if ((threadIdx.x & 63) == 0) s_v[threadIdx.x >> 6] = d2;
+        for (int o = 32; o > 0; o >>= 1) {
+            d2 = fmax(d2, __shfl_xor(d2, o, 64));
+            v2 = fmax(v2, __shfl_xor(v2, o, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            s_v[threadIdx.x >> 6] = d2;
+            s_u[threadIdx.x >> 6] = v2;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double m = 0.0;
+            double m = 0.0, mv = 0.0;
 #pragma unroll
-            for (int w = 0; w < kStreamBlock / 64; ++w) m = fmax(m, s_v[w]);
+            for (int w = 0; w < kStreamBlock / 64; ++w) {
+                m = fmax(m, s_v[w]);
+                mv = fmax(mv, s_u[w]);
+            }
             atomicMax(a.max_d2, (unsigned long long)__double_as_longlong(m));
+            atomicMax(a.max_v2, (unsigned long long)__double_as_longlong(mv));
         }
     }
     if (KE) {
@@ -309,6 +320,9 @@ __global__ void k_gather_flags(const int64_t* __restrict__ status, const int64_t
     out[5] = err[1];
     out[6] = flags[0];
     out[7] = __double_as_longlong(energy[4]);
+    out[8] = __double_as_longlong(energy[5]);
+    out[9] = err[4];    // large-displacement check: member count
+    out[10] = err[5];   // large-displacement check: violation flag
 }
 
 hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags,

@@ -84,13 +84,14 @@ struct WsLayout {
     size_t part_b;     // double[nbi]    per-block partial sums (streaming kernels)
     size_t pos32;      // float4[n]      mixed-mode local coordinates (md_forces)
     size_t red;        // int64[2*1024]  partials of the list statistics
-    size_t scal;       // double[16]     small device scalars
+    size_t ldc;        // int32[ldc_max] members of the large-displacement check
+    size_t scal;       // int64[32]      small device scalars (layout in md_api.hip)
     size_t total;
     int64_t nbs;       // scan blocks
     int64_t nbf;       // force-kernel blocks
     int64_t nbi;       // streaming-kernel blocks
 };
-WsLayout ws_layout(const Geo& g);
+WsLayout ws_layout(const Geo& g, int64_t ldc_max);
 
 // ---------------------------------------------------------------------------
 // Small device helpers
@@ -174,6 +175,7 @@ struct StepIo {
     double* pos_out;
     float* pos32_out;
     unsigned long long* max_d2;
+    unsigned long long* max_v2;
     double dt;
     bool drift;
 };
@@ -191,9 +193,16 @@ struct IntArgs {
     const int32_t* cell_xyz;
     double* part_ke;                // per-block KE partials (or nullptr)
     unsigned long long* max_d2;     // atomic max of squared displacement bits
+    unsigned long long* max_v2;     // atomic max of squared drift speed bits
     double dt;
     int precision;
 };
+
+// Pinned squared length fma(z, z, fma(y, y, x * x)) (displacements, speeds).
+__device__ __forceinline__ double pinned_len2(double x, double y, double z)
+{
+    return __builtin_fma(z, z, __builtin_fma(y, y, __dmul_rn(x, x)));
+}
 hipError_t launch_integrate(const Geo& g, IntMode mode, const IntArgs& a, hipStream_t s);
 hipError_t launch_reduce_energy(const double* part_pw, int64_t nbf, const double* part_ke,
                                 int64_t nbi, double* energy, double* log_row, hipStream_t s);
@@ -203,6 +212,13 @@ hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const 
                                const double* energy, int64_t* out, hipStream_t s);
 hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t* status, long long* part,
                              hipStream_t s);
+
+// md_validity.hip
+hipError_t launch_ldc_disp(const Geo& g, const double* pos, const double* pos_ref, unsigned long long* max_d2,
+                           hipStream_t s);
+hipError_t launch_ldc_check(const Geo& g, const double* pos, const double* pos_ref, double rc, double rs,
+                            double t, int64_t cap, int32_t* list, unsigned long long* count,
+                            unsigned long long* flag, hipStream_t s);
 
 // md_adjoint.hip
 hipError_t launch_hvp(const Geo& g, const LJ& lj, const double* pos, const int32_t* cell_xyz,

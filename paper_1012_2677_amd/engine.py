@@ -19,8 +19,11 @@ def _ptr(t: torch.Tensor | None) -> int | None:
     return None if t is None else t.data_ptr()
 
 
+REBUILD_RULES = {"half_skin": A.MD_REBUILD_HALF_SKIN, "dutc_ldc": A.MD_REBUILD_DUTC_LDC}
+
+
 def make_params(n, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precision="fp64",
-                resort_every=1) -> A.MdParams:
+                resort_every=1, rebuild_rule="half_skin", ldc_max=8192) -> A.MdParams:
     p = A.MdParams()
     p.n = int(n)
     b = np.broadcast_to(np.asarray(box, dtype=np.float64), (3,))
@@ -29,6 +32,8 @@ def make_params(n, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precisi
     p.eps, p.sigma, p.rc, p.rs, p.dt = float(eps), float(sigma), float(rc), float(rs), float(dt)
     p.precision = A.MD_MIXED if precision in ("mixed", A.MD_MIXED) else A.MD_FP64
     p.resort_every = int(resort_every)
+    p.rebuild_rule = REBUILD_RULES[rebuild_rule] if isinstance(rebuild_rule, str) else int(rebuild_rule)
+    p.ldc_max = int(ldc_max)
     return p
 
 
@@ -123,11 +128,14 @@ class Engine:
 
     pos, vel: (N, 3) arrays (any array type numpy accepts), positions in
     [0, L)^3.  precision: "fp64" or "mixed".  resort_every: re-sort the particle
-    arrays into cell order at every k-th rebuild (0 = never).
+    arrays into cell order at every k-th rebuild (0 = never).  rebuild_rule:
+    "half_skin" or "dutc_ldc" (DUTC, then the large-displacement check with at
+    most ldc_max members).
     """
 
     def __init__(self, pos, vel, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precision="fp64",
-                 resort_every=1, device="cuda", cell_stride=None, timers=False):
+                 resort_every=1, rebuild_rule="half_skin", ldc_max=8192, device="cuda", cell_stride=None,
+                 timers=False):
         pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64))
         vel = np.ascontiguousarray(np.asarray(vel, dtype=np.float64))
         n = pos.shape[0]
@@ -135,7 +143,7 @@ class Engine:
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.params = make_params(n, box, eps=eps, sigma=sigma, rc=rc, rs=rs, dt=dt, precision=precision,
-                                  resort_every=resort_every)
+                                  resort_every=resort_every, rebuild_rule=rebuild_rule, ldc_max=ldc_max)
         self.n = n
         self.mixed = self.params.precision == A.MD_MIXED
         dev = self.device
@@ -263,6 +271,11 @@ class Engine:
     @property
     def rebuilds(self) -> int:
         return int(self.state.rebuilds)
+
+    @property
+    def ldc_stats(self):
+        """(large-displacement checks made, checks that kept the list)."""
+        return int(self.state.ldc_checks), int(self.state.ldc_kept)
 
     def timer_dict(self):
         if self.timers is None:
