@@ -725,6 +725,7 @@ int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_eve
         io.max_v2 = (unsigned long long*)(st->energy + 5);
         io.dt = p->dt;
         io.drift = !last;
+        io.track_speed = p->rebuild_rule == MD_REBUILD_DUTC_LDC;
         if (!last) MD_HIP(launch_fill_i32((int32_t*)(st->energy + 4), 0, 4, s), "step/maxd2");
         tick(T, MD_T_FORCE, 0, s);
         MD_HIP(launch_force_step(c.g, c.lj, p->precision, io, s), "step/force");

@@ -137,7 +137,7 @@ __device__ __forceinline__ float local_coord(double x, int c, double cs, double 
 }
 
 // Block-level epilogue: (PE, W) and KE partials, displacement maximum.
-template <bool ENERGY, int MODE>
+template <bool ENERGY, int MODE, bool VMAX>
 __device__ __forceinline__ void block_epilogue(const PairArgs& a, int64_t blk, double pe, double w, double ke,
                                                double d2, double v2)
 {
@@ -156,7 +156,7 @@ __device__ __forceinline__ void block_epilogue(const PairArgs& a, int64_t blk, d
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             d2 = fmax(d2, __shfl_xor(d2, o, 64));
-            v2 = fmax(v2, __shfl_xor(v2, o, 64));
+            if (VMAX) v2 = fmax(v2, __shfl_xor(v2, o, 64));
         }
     }
     if ((threadIdx.x & 63) == 0) {
@@ -184,14 +184,14 @@ __device__ __forceinline__ void block_epilogue(const PairArgs& a, int64_t blk, d
         }
         if (MODE == MODE_KKD) {
             atomicMax(a.max_d2, (unsigned long long)__double_as_longlong(m));
-            atomicMax(a.max_v2, (unsigned long long)__double_as_longlong(mv));
+            if (VMAX) atomicMax(a.max_v2, (unsigned long long)__double_as_longlong(mv));
         }
     }
 }
 
 // Integrator epilogue of one key (lane): kicks, drift, wrap, displacement since
 // the last build.  Same arithmetic as the stand-alone integrator.
-template <int MODE, bool MIXED>
+template <int MODE, bool MIXED, bool VMAX>
 __device__ __forceinline__ void integrate_key(const PairArgs& a, int64_t k, double fx, double fy, double fz,
                                               double& ke, double& d2, double& v2)
 {
@@ -217,7 +217,7 @@ __device__ __forceinline__ void integrate_key(const PairArgs& a, int64_t k, doub
         vx = vx + h * fx;
         vy = vy + h * fy;
         vz = vz + h * fz;
-        v2 = pinned_len2(vx, vy, vz);
+        if (VMAX) v2 = pinned_len2(vx, vy, vz);
         p.x = wrap_coord(p.x + a.dt * vx, a.L[0], a.invL[0]);
         p.y = wrap_coord(p.y + a.dt * vy, a.L[1], a.invL[1]);
         p.z = wrap_coord(p.z + a.dt * vz, a.L[2], a.invL[2]);
@@ -237,7 +237,7 @@ __device__ __forceinline__ void integrate_key(const PairArgs& a, int64_t k, doub
     vel[2 * n + k] = vz;
 }
 
-template <int U, bool ENERGY, int MODE>
+template <int U, bool ENERGY, int MODE, bool VMAX>
 __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_fp64(PairArgs a)
 {
     constexpr int NW = kForceBlock / 64;
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_fp64(
         }
         if (MODE != MODE_FORCE) {
             double kk = 0.0, dd = 0.0, vv = 0.0;
-            integrate_key<MODE, false>(a, mykey, kfx, kfy, kfz, kk, dd, vv);
+            integrate_key<MODE, false, VMAX>(a, mykey, kfx, kfy, kfz, kk, dd, vv);
             ke += kk;
             d2 = fmax(d2, dd);
             v2 = fmax(v2, vv);
@@ -347,10 +347,10 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_fp64(
     }
     __builtin_amdgcn_wave_barrier();
     }
-    if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE>(a, blk, pe, w, ke, d2, v2);
+    if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE, VMAX>(a, blk, pe, w, ke, d2, v2);
 }
 
-template <int U, bool ENERGY, int MODE>
+template <int U, bool ENERGY, int MODE, bool VMAX>
 __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed(PairArgs a)
 {
     constexpr int NW = kForceBlock / 64;
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed
         }
         if (MODE != MODE_FORCE) {
             double kk = 0.0, dd = 0.0, vv = 0.0;
-            integrate_key<MODE, true>(a, mykey, kfx, kfy, kfz, kk, dd, vv);
+            integrate_key<MODE, true, VMAX>(a, mykey, kfx, kfy, kfz, kk, dd, vv);
             ke += kk;
             d2 = fmax(d2, dd);
             v2 = fmax(v2, vv);
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed
     }
     __builtin_amdgcn_wave_barrier();
     }
-    if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE>(a, blk, pe, w, ke, d2, v2);
+    if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE, VMAX>(a, blk, pe, w, ke, d2, v2);
 }
 
 int64_t pair_blocks(const Geo& g) { return ceil_div(g.n, kForceBlock); }
@@ -494,14 +494,14 @@ static PairArgs make_pair_args(const Geo& g, const LJ& lj, const double* pos, co
     return a;
 }
 
-template <bool ENERGY, int MODE>
+template <bool ENERGY, int MODE, bool VMAX = false>
 static void launch_pairs_mode(const Geo& g, int precision, const PairArgs& a, hipStream_t s)
 {
     const dim3 grid((unsigned)pair_blocks(g)), block(kForceBlock);
     if (precision == MD_MIXED)
-        hipLaunchKernelGGL((k_pairs_mixed<kForceUnroll, ENERGY, MODE>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_pairs_mixed<kForceUnroll, ENERGY, MODE, VMAX>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((k_pairs_fp64<kForceUnroll64, ENERGY, MODE>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_pairs_fp64<kForceUnroll64, ENERGY, MODE, VMAX>), grid, block, 0, s, a);
 }
 
 hipError_t launch_forces(const Geo& g, const LJ& lj, int precision, const double* pos,
@@ -534,7 +534,11 @@ hipError_t launch_force_step(const Geo& g, const LJ& lj, int precision, const St
     a.max_v2 = io.max_v2;
     a.dt = io.dt;
     const bool energy = io.part_pw != nullptr;
-    if (io.drift) {
+    if (io.drift && io.track_speed) {
+        // the largest drift speed is needed by the DUTC rule only
+        if (energy) launch_pairs_mode<true, MODE_KKD, true>(g, precision, a, s);
+        else launch_pairs_mode<false, MODE_KKD, true>(g, precision, a, s);
+    } else if (io.drift) {
         if (energy) launch_pairs_mode<true, MODE_KKD>(g, precision, a, s);
         else launch_pairs_mode<false, MODE_KKD>(g, precision, a, s);
     } else {

@@ -175,9 +175,10 @@ struct StepIo {
     double* pos_out;
     float* pos32_out;
     unsigned long long* max_d2;
-    unsigned long long* max_v2;
+    unsigned long long* max_v2;   // with track_speed
     double dt;
     bool drift;
+    bool track_speed;             // also record the largest squared drift speed
 };
 hipError_t launch_force_step(const Geo& g, const LJ& lj, int precision, const StepIo& io, hipStream_t s);
 int64_t pair_blocks(const Geo& g);   // blocks (and energy partials) of one pair-kernel launch
