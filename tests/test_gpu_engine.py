@@ -5,6 +5,8 @@
     same number of rebuilds;
   * the list never misses a pair: at every step of a short run the forces on
     the GPU state equal the oracle's forces recomputed from scratch (<= 1e-12);
+  * a particle moved from the host by more than half the skin forces a
+    rebuild on the next step, and the forces after it miss no pair;
   * mixed precision tracks the FP64 oracle (energy per particle to 1e-5);
   * the paper's benchmark conditions (|v| = 0.9, dt = 0.001) in FP64 and mixed,
     and a never re-sorted run on shuffled labels, match the oracle;
@@ -71,6 +73,30 @@ def test_no_missed_pair_every_step(ref):
         seen_reuse += e.rebuilds == rebuilds
         rebuilds = e.rebuilds
     assert seen_reuse >= 10  # most steps reuse the list
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_host_move_beyond_half_skin_rebuilds_next_step(ref, precision):
+    # a particle moved from the host by more than half the skin between two
+    # calls is caught by the displacement check of the next step: the list is
+    # rebuilt before that step's force pass, and no pair is missed
+    q, L = li.fcc_lattice(10)
+    v = li.maxwell_boltzmann(q.shape[0], T=0.5, seed=8)
+    e = _engine(q, v, L, precision=precision, resort_every=1)
+    e.prepare()
+    e.step(2)
+    r0 = e.rebuilds
+    e.step(1)
+    assert e.rebuilds == r0  # slow start: the list is still valid
+    skin = 2.8 - 2.5
+    slot = 17
+    x = float(e.pos[slot, 0].item()) + 0.7 * skin
+    e.pos[slot, 0] = x - L * np.floor(x / L)
+    e.step(1)
+    assert e.rebuilds == r0 + 1
+    idx = np.arange(q.shape[0], dtype=np.int64)
+    Fr, S, _, _, _ = ref.forces_sample(e.positions(), L, idx)
+    assert G.force_error(e.forces(), Fr, S) <= (1e-12 if precision == "fp64" else 1e-5)
 
 
 def test_mixed_tracks_fp64(ref):
