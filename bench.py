@@ -41,17 +41,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def force_bytes_per_key(mean_entries: float, mixed: bool) -> float:
+def force_bytes_per_key(mean_entries: float, mixed: bool, entry_bytes: int = 4) -> float:
     """Algorithmic HBM bytes of one key in the timed force pass, which inside a
     run is fused with the integrator (second half kick, next first half kick,
-    drift): row offset (8) + row length (4) + 4 bytes per list entry + the
+    drift): row offset (8) + row length (4) + entry_bytes per list entry (4 for
+    slot entries, 2 for the tiled list) + the
     key's own coordinates (FP32 local 16 B in mixed mode; FP64 32 B plus its
     4 B packed cell in FP64 mode) + the integrator's streams: velocity read and
     write (48), reference position (24), position written (32; mixed mode also
     reads the FP64 position, 32, its packed cell, 4, and writes new local
     coordinates, 16).  Partner coordinates are re-reads of coordinates counted
-    once as keys."""
-    idx = 8 + 4 + 4 * mean_entries
+    once as keys (in the tiled pass: staged into LDS from the same array)."""
+    idx = 8 + 4 + entry_bytes * mean_entries
     if mixed:
         return idx + 16 + 32 + 4 + 48 + 24 + 32 + 16
     return idx + 32 + 4 + 48 + 24 + 32
@@ -114,7 +115,7 @@ def drift_per_1000(steps_axis, e_per_particle):
 
 
 def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, shuffle=False,
-             rebuild_rule="half_skin", ldc_max=8192):
+             rebuild_rule="half_skin", ldc_max=8192, list_layout="auto", tile_cells=0):
     import torch
 
     import lj_inputs as li
@@ -129,12 +130,14 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
         q, v, _ = li.shuffle_labels(q, v, seed=seed + 1)
     n = q.shape[0]
     e = Engine(q, v, L, rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], dt=cfg["dt"], precision=precision,
-               resort_every=resort_every, rebuild_rule=rebuild_rule, ldc_max=ldc_max, device="cuda:0", timers=True)
+               resort_every=resort_every, rebuild_rule=rebuild_rule, ldc_max=ldc_max, list_layout=list_layout,
+               tile_cells=tile_cells, device="cuda:0", timers=True)
     del q, v
     e.prepare()
     e0 = e.energies()
     log(f"[bench] {precision}: N={n} prepared in {time.perf_counter() - t0:.1f}s, "
-        f"list stride {e.plist.cell_stride}, entries {int(e.plist.status[0].item())}")
+        f"list stride {e.plist.cell_stride}, entries {int(e.plist.status[0].item())}, "
+        f"tiled {int(e.state.list_tiled)} (tile cells {int(e.state.tile_cells)}, stage {int(e.state.tile_stage)})")
     if warmup > 0:
         e.step(warmup)
         log(f"[bench] {precision}: {warmup} warmup steps done")
@@ -158,6 +161,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
     t2 = time.perf_counter()
     dt = t2 - t1
     entries = int(e.plist.status[0].item())
+    tiled = int(e.state.list_tiled)
     tim = e.timer_dict()
     rebuilds = e.rebuilds - reb0
     log(f"[bench] {precision}: {steps} steps in {dt:.3f}s, {rebuilds} rebuilds, timers {tim}")
@@ -175,6 +179,8 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
         "rebuild_rule": rebuild_rule,
         "ldc_checks_kept": [e.ldc_stats[0] - ldc0[0], e.ldc_stats[1] - ldc0[1]],
         "mean_list_entries": entries / n,
+        "list_tiled": tiled,
+        "tile_cells": int(e.state.tile_cells),
         "timers_ms": {k: [round(m, 3), c] for k, (m, c) in tim.items()},
         "energy_per_particle_start": float(e0[3] / n),
         "energy_per_particle_samples": [float(x) for x in e_pp],
@@ -187,7 +193,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
     fm, fl = tim.get("force", (0.0, 0))
     if fl > 0:
         avg_ms = fm / fl
-        per_launch = n * force_bytes_per_key(entries / n, precision == "mixed")
+        per_launch = n * force_bytes_per_key(entries / n, precision == "mixed", 2 if tiled else 4)
         gbs = per_launch / (avg_ms * 1e-3) / 1e9
         out["force_kernel"] = {"avg_ms": avg_ms, "launches": fl, "algorithmic_bytes_per_launch": per_launch,
                                "achieved_GBs": gbs}
@@ -233,6 +239,9 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="also time the headline precision without re-sorting, labels shuffled first")
     ap.add_argument("--sample-every", type=int, default=50)
+    ap.add_argument("--list-layout", default="auto", choices=["auto", "slots"],
+                    help="list of the simulation state: tiled when possible (auto) or slot entries")
+    ap.add_argument("--tile-cells", type=int, default=0, help="tile length along z in cells (0 = automatic)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -262,7 +271,8 @@ def main():
     results = {}
     for m in modes:
         results[m] = run_mode(cfg, m, args.steps, args.warmup, sample_every, args.seed,
-                              rebuild_rule=args.rebuild_rule, ldc_max=args.ldc_max)
+                              rebuild_rule=args.rebuild_rule, ldc_max=args.ldc_max, list_layout=args.list_layout,
+                              tile_cells=args.tile_cells)
     head = results[modes[0]]
     n = head["n"]
     ablation = None
@@ -277,7 +287,7 @@ def main():
     log(f"[bench] plain copy: {copy['GBs']:.0f} GB/s")
     roofline = None
     if fk:
-        kname = "k_pairs_mixed" if modes[0] == "mixed" else "k_pairs_fp64"
+        kname = ("k_pairs_tiled" if head.get("list_tiled") else "k_pairs_mixed") if modes[0] == "mixed" else "k_pairs_fp64"
         traffic, tsrc = counter_traffic(kname, args.config)
         roofline = {"bound": "hbm", "achieved": round(fk["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(fk["achieved_GBs"] / HBM_PEAK_GBS, 4),

@@ -59,6 +59,10 @@ extern "C" {
 
 #define MD_MAX_N ((int64_t)1 << 27)   /* slots are stored in 27 bits of a list entry */
 
+/* list layouts of the simulation state (md_params.list_layout) */
+#define MD_LIST_AUTO  0   /* tiled when possible (mixed precision, slots in cell order) */
+#define MD_LIST_SLOTS 1   /* always 32-bit slot entries                                 */
+
 /* pair-list rebuild rules (md_params.rebuild_rule) */
 #define MD_REBUILD_HALF_SKIN 0   /* rebuild once some particle moved more than (rs - rc)/2         */
 #define MD_REBUILD_DUTC_LDC  1   /* DUTC, then the large-displacement check (Alg. alg_validity_check) */
@@ -77,7 +81,19 @@ extern "C" {
  *   (v_max the largest speed of the step's drift); while it is positive the
  *   list is valid, afterwards md_ldc_check decides each step.
  *   ldc_max: the most particles the large-displacement check takes (N_l of
- *   the algorithm); more invalidate the list outright.  0 <= ldc_max <= 2^22. */
+ *   the algorithm); more invalidate the list outright.  0 <= ldc_max <= 2^22.
+ *   list_layout: how md_prepare / md_step / md_energy store the state's list.
+ *   MD_LIST_AUTO: in MD_MIXED, whenever the slots are in cell order (after a
+ *   re-sort), the list's cell_stride is even and every tile's neighbourhood
+ *   fits, the tiled layout: the cells
+ *   are cut into tiles of tile_cells consecutive cells along z, and an entry
+ *   is the 16-bit index of the partner in the tile's neighbourhood (the runs
+ *   of cells around the tile in the 9 columns next to it, which the force
+ *   pass stages in LDS); otherwise, and always with MD_LIST_SLOTS, entries are
+ *   32-bit partner slots as in md_build_pairlist.  Both layouts hold the same
+ *   pairs in the same row order.
+ *   tile_cells: cells per tile along z (0 = about 224 keys per tile at the
+ *   mean density); clipped to [1, nz - 2]. */
 typedef struct md_params {
     int64_t n;
     double  box[3];
@@ -88,6 +104,8 @@ typedef struct md_params {
     int32_t resort_every;
     int32_t rebuild_rule;  /* MD_REBUILD_HALF_SKIN or MD_REBUILD_DUTC_LDC */
     int32_t ldc_max;
+    int32_t list_layout;   /* MD_LIST_AUTO or MD_LIST_SLOTS */
+    int32_t tile_cells;    /* 0 = automatic, else 1 .. 1023 */
 } md_params;
 
 /* Cell grid (Sec. 2.2): GridParticleNumber = count, GridPointer = start,
@@ -152,8 +170,10 @@ typedef struct md_timers {
  *   id_alt only when resort_every > 0.  pos_ref: device double[3][n],
  *   positions at the last build.  pos32, pos32_alt: device float[n][4],
  *   MD_MIXED only (NULL in MD_FP64): coordinates relative to each slot's cell
- *   corner at the last build, and the second buffer md_step writes the
- *   drifted coordinates to (swapped like pos / pos_alt).
+ *   corner at the last build, with the packed cell coordinates
+ *   (cx | cy << 10 | cz << 20) as the bits of the fourth float, and the
+ *   second buffer md_step writes the drifted coordinates to (swapped like
+ *   pos / pos_alt).
  *   force: after md_prepare, md_energy and at the end of md_step, the forces
  *   at the current positions; inside a run they are consumed by the fused
  *   kicks and not stored.
@@ -168,7 +188,14 @@ typedef struct md_timers {
  *   re-sorted by md_resort (md_prepare needed).
  *   dutc_buffer: remaining DUTC buffer length (MD_REBUILD_DUTC_LDC; reset to
  *   rs - rc at each build); ldc_checks, ldc_kept: large-displacement checks
- *   made, and those that kept the list. */
+ *   made, and those that kept the list.
+ *   list_tiled: 1 when st->list holds the tiled layout (set by the library):
+ *   nbr is then read as uint16 entries, offsets count uint16 units, and the
+ *   rows of cell c live in ((uint16_t*)nbr)[c*cell_stride ..), each row
+ *   starting at an even entry (a row of odd length is followed by one unused
+ *   entry, counted in the list status); tile_stage:
+ *   the largest neighbourhood of a tile, in particles; tile_cells: the tile
+ *   length along z in cells. */
 typedef struct md_state {
     double*   pos;
     double*   vel;
@@ -196,6 +223,10 @@ typedef struct md_state {
     double    dutc_buffer;
     int64_t   ldc_checks;
     int64_t   ldc_kept;
+    int32_t   list_tiled;
+    int32_t   tile_stage;
+    int32_t   tile_cells;
+    int32_t   reserved;
 } md_state;
 
 /* Host-only: cells per axis for these parameters.  MD_ERR_BOX when an axis

@@ -26,6 +26,8 @@ MD_FP64 = 0
 MD_MIXED = 1
 MD_MAX_N = 1 << 27
 
+MD_LIST_AUTO = 0
+MD_LIST_SLOTS = 1
 MD_REBUILD_HALF_SKIN = 0
 MD_REBUILD_DUTC_LDC = 1
 
@@ -46,7 +48,8 @@ class MdError(RuntimeError):
 class MdParams(C.Structure):
     _fields_ = [("n", C.c_int64), ("box", C.c_double * 3), ("eps", C.c_double), ("sigma", C.c_double),
                 ("rc", C.c_double), ("rs", C.c_double), ("dt", C.c_double), ("precision", C.c_int32),
-                ("resort_every", C.c_int32), ("rebuild_rule", C.c_int32), ("ldc_max", C.c_int32)]
+                ("resort_every", C.c_int32), ("rebuild_rule", C.c_int32), ("ldc_max", C.c_int32),
+                ("list_layout", C.c_int32), ("tile_cells", C.c_int32)]
 
 
 class MdCells(C.Structure):
@@ -72,7 +75,8 @@ class MdState(C.Structure):
                 ("ws_bytes", C.c_size_t), ("timers", C.POINTER(MdTimers)), ("step", C.c_int64),
                 ("rebuilds", C.c_int64), ("resorts", C.c_int64), ("phase", C.c_int32),
                 ("list_valid", C.c_int32), ("dutc_buffer", C.c_double), ("ldc_checks", C.c_int64),
-                ("ldc_kept", C.c_int64)]
+                ("ldc_kept", C.c_int64), ("list_tiled", C.c_int32), ("tile_stage", C.c_int32),
+                ("tile_cells", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <utility>
 
 #include "md_internal.h"
@@ -46,6 +47,9 @@ static int check_params(const md_params* p, int32_t nc[3])
     if (p->rebuild_rule != MD_REBUILD_HALF_SKIN && p->rebuild_rule != MD_REBUILD_DUTC_LDC)
         return fail(MD_ERR_ARG, "rebuild_rule must be 0 or 1");
     if (p->ldc_max < 0 || p->ldc_max > (1 << 22)) return fail(MD_ERR_ARG, "ldc_max must be in [0, 2^22]");
+    if (p->list_layout != MD_LIST_AUTO && p->list_layout != MD_LIST_SLOTS)
+        return fail(MD_ERR_ARG, "list_layout must be 0 or 1");
+    if (p->tile_cells < 0 || p->tile_cells > 1023) return fail(MD_ERR_ARG, "tile_cells must be in [0, 1023]");
     for (int k = 0; k < 3; ++k) {
         const double m = std::floor(p->box[k] / p->rs);
         if (m < 3.0) return fail(MD_ERR_BOX, "axis %d has %.0f cells (< 3): box too small for rs", k, m);
@@ -70,6 +74,19 @@ Geo make_geo(const md_params& p, const int32_t nc[3])
         g.cs[k] = p.box[k] / (double)nc[k];
         if (nc[k] < 5) g.exact_all = 1;
     }
+    // tiles: about kTileKeys keys each at the mean density, at most nz - 2
+    // cells long so that a tile's runs wrap at most once
+    const int nz = nc[2];
+    int tc = p.tile_cells;
+    if (tc == 0) {
+        const double mean = (double)p.n / (double)g.ncell;
+        tc = (int)std::lround((double)kTileKeys / (mean > 1e-9 ? mean : 1e-9));
+    }
+    tc = std::max(1, std::min(tc, nz - 2));
+    const bool tiles = p.precision == MD_MIXED && p.list_layout == MD_LIST_AUTO;
+    g.tc = tiles ? tc : 0;
+    g.nt = tiles ? (int32_t)ceil_div(nz, tc) : 0;
+    g.ntile = tiles ? (int64_t)nc[0] * nc[1] * g.nt : 0;
     return g;
 }
 
@@ -108,7 +125,9 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 //   [0], [1]  cell-grid error flags         [2]  md_forces non-finite flag
 //   [4]       large-displacement members    [5]  large-displacement violation
 //   [6]       largest squared displacement (md_ldc_check)
+//   [8]       largest staged neighbourhood of a tile (tiled list build)
 //   [16..31]  flags gathered for one read-back (layout in k_gather_flags)
+constexpr int kScalTileMax = 8;
 constexpr int kScalOut = 16;
 
 WsLayout ws_layout(const Geo& g, int64_t ldc_max)
@@ -117,7 +136,8 @@ WsLayout ws_layout(const Geo& g, int64_t ldc_max)
     WsLayout L;
     L.nbs = ceil_div(ncell, kScanItems);
     L.nbf = ceil_div(n, kKeysPerBlock);
-    const int64_t np = pair_blocks(g);
+    const int64_t np = std::max(pair_blocks(g), g.ntile);
+    L.nbf = std::max(L.nbf, g.ntile);
     L.nbi = ceil_div(n, kStreamBlock);
     size_t off = 0;
     L.rank = off;      off = align256(off + sizeof(int32_t) * (size_t)n);
@@ -295,7 +315,7 @@ int md_build_pairlist(const md_params* p, const double* pos, const md_cells* cel
     if ((rc = check_cells(c, cells)) != MD_OK) return rc;
     if ((rc = check_list(c, list)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
-    MD_HIP(launch_build(c.g, p->rs, pos, *cells, *list, ws, c.W, stream), "md_build_pairlist");
+    MD_HIP(launch_build(c.g, p->rs, pos, *cells, *list, ws, c.W, false, nullptr, stream), "md_build_pairlist");
     return MD_OK;
 }
 
@@ -322,7 +342,7 @@ int md_forces(const md_params* p, const double* pos, const md_cells* cells, cons
     MD_HIP(launch_forces(c.g, c.lj, p->precision, pos, pos32, cells->cell_xyz, *list, out, stream),
            "md_forces");
     if (pe_w)
-        MD_HIP(launch_reduce_pair(out.part, pair_blocks(c.g), 1.0, 1.0, pe_w, stream), "md_forces/reduce");
+        MD_HIP(launch_reduce_pair(out.part, force_blocks(c.g, false), 1.0, 1.0, pe_w, stream), "md_forces/reduce");
     return MD_OK;
 }
 
@@ -405,8 +425,31 @@ static int check_state(const Ctx& c, const md_params* p, md_state* st)
 }
 
 // bin + optional re-sort + reference copy + list build (no wait)
+static int read_flags(const Ctx& c, md_state* st, hipStream_t s, int64_t out[16]);
+
+// Pair list of the state: tiled (16-bit entries into each tile's staged
+// neighbourhood) when the geometry has tiles and the slots are in cell order,
+// else slot entries.
+static int build_list(const Ctx& c, const md_params* p, md_state* st, bool tiled, Timer& T, hipStream_t s)
+{
+    int64_t* scal = (int64_t*)((char*)st->ws + c.W.scal);
+    if (tiled) MD_HIP(launch_fill_i32((int32_t*)(scal + kScalTileMax), 0, 2, s), "rebuild/tile-max");
+    tick(T, MD_T_BUILD, 0, s);
+    MD_HIP(launch_build(c.g, p->rs, st->pos, st->cells, st->list, st->ws, c.W, tiled,
+                        (unsigned long long*)(scal + kScalTileMax), s),
+           "rebuild/build");
+    tick(T, MD_T_BUILD, 1, s);
+    st->list_tiled = tiled ? 1 : 0;
+    st->tile_stage = 0;
+    st->tile_cells = tiled ? c.g.tc : 0;
+    return MD_OK;
+}
+
+// Bin, re-sort (every resort_every-th build), build the list, and read the
+// flags back into f.  A tiled list whose largest tile neighbourhood exceeds
+// what the force pass can stage is rebuilt with slot entries.
 static int rebuild(const Ctx& c, const md_params* p, md_state* st, bool allow_resort, Timer& T,
-                   hipStream_t s)
+                   hipStream_t s, int64_t f[16])
 {
     int64_t* err = (int64_t*)((char*)st->ws + c.W.scal);
     tick(T, MD_T_BIN, 0, s);
@@ -432,10 +475,32 @@ static int rebuild(const Ctx& c, const md_params* p, md_state* st, bool allow_re
                                p->precision == MD_MIXED ? st->pos32 : nullptr, s),
                "rebuild/ref");
     }
-    tick(T, MD_T_BUILD, 0, s);
-    MD_HIP(launch_build(c.g, p->rs, st->pos, st->cells, st->list, st->ws, c.W, s), "rebuild/build");
-    tick(T, MD_T_BUILD, 1, s);
+    // tiled rows start at even entries of 4-byte aligned cell blocks
+    const bool tiled = c.g.tc > 0 && st->cells.sorted && (st->list.cell_stride & 1) == 0;
+    int rc = build_list(c, p, st, tiled, T, s);
+    if (rc != MD_OK) return rc;
+    if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
+    if (st->list_tiled) {
+        if (f[11] > kTileMaxStage) {
+            timer_collect(T);
+            if ((rc = build_list(c, p, st, false, T, s)) != MD_OK) return rc;
+            if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
+        } else {
+            st->tile_stage = (int32_t)f[11];
+        }
+    }
     return MD_OK;
+}
+
+static TileIo tile_io(const md_state* st)
+{
+    TileIo t;
+    if (st->list_tiled) {
+        t.start = st->cells.start;
+        t.count = st->cells.count;
+        t.stage = st->tile_stage;
+    }
+    return t;
 }
 
 // wait for the stream and read, in one copy: list status [0..3], cell-grid
@@ -460,7 +525,7 @@ static int force_eval(const Ctx& c, const md_params* p, md_state* st, bool energ
     out.flags = st->flags;
     tick(T, MD_T_FORCE, 0, s);
     MD_HIP(launch_forces(c.g, c.lj, p->precision, st->pos, p->precision == MD_MIXED ? st->pos32 : nullptr,
-                         st->cells.cell_xyz, st->list, out, s),
+                         st->cells.cell_xyz, st->list, out, s, tile_io(st)),
            "forces");
     tick(T, MD_T_FORCE, 1, s);
     return MD_OK;
@@ -595,11 +660,10 @@ int md_prepare(const md_params* p, md_state* st, hipStream_t s)
     timer_begin(T, nullptr);
     MD_HIP(launch_fill_i32((int32_t*)st->flags, 0, 2, s), "prepare/flags");
     MD_HIP(launch_fill_i32((int32_t*)((char*)st->ws + c.W.scal), 0, 4, s), "prepare/err");
-    if ((rc = rebuild(c, p, st, true, T, s)) != MD_OK) return rc;
+    int64_t f[16];
+    if ((rc = rebuild(c, p, st, true, T, s, f)) != MD_OK) return rc;
     st->rebuilds += 1;
     st->dutc_buffer = p->rs - p->rc;
-    int64_t f[16];
-    if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
     if ((rc = check_status(f, st)) != MD_OK) {
         st->list_valid = 0;
         return rc;
@@ -608,7 +672,7 @@ int md_prepare(const md_params* p, md_state* st, hipStream_t s)
     if ((rc = force_eval(c, p, st, true, T, s)) != MD_OK) return rc;
     IntArgs a = int_args(c, p, st, true);
     MD_HIP(launch_integrate(c.g, INT_KE, a, s), "prepare/ke");
-    MD_HIP(launch_reduce_energy((double*)((char*)st->ws + c.W.part_a), pair_blocks(c.g),
+    MD_HIP(launch_reduce_energy((double*)((char*)st->ws + c.W.part_a), force_blocks(c.g, st->list_tiled),
                                 (double*)((char*)st->ws + c.W.part_b), c.W.nbi, st->energy, nullptr, s),
            "prepare/reduce");
     if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
@@ -630,7 +694,7 @@ int md_energy(const md_params* p, md_state* st, double* out, hipStream_t s)
     if ((rc = force_eval(c, p, st, true, T, s)) != MD_OK) return rc;
     IntArgs a = int_args(c, p, st, true);
     MD_HIP(launch_integrate(c.g, INT_KE, a, s), "energy/ke");
-    MD_HIP(launch_reduce_energy((double*)((char*)st->ws + c.W.part_a), pair_blocks(c.g),
+    MD_HIP(launch_reduce_energy((double*)((char*)st->ws + c.W.part_a), force_blocks(c.g, st->list_tiled),
                                 (double*)((char*)st->ws + c.W.part_b), c.W.nbi, st->energy, out, s),
            "energy/reduce");
     return MD_OK;
@@ -692,10 +756,9 @@ int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_eve
             }
         }
         if (expired) {
-            if ((rc = rebuild(c, p, st, true, T, s)) != MD_OK) return rc;
+            if ((rc = rebuild(c, p, st, true, T, s, f)) != MD_OK) return rc;
             st->rebuilds += 1;
             st->dutc_buffer = p->rs - p->rc;
-            if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
             timer_collect(T);
             if (f[2] != 0) {
                 st->list_valid = 0;
@@ -726,6 +789,7 @@ int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_eve
         io.dt = p->dt;
         io.drift = !last;
         io.track_speed = p->rebuild_rule == MD_REBUILD_DUTC_LDC;
+        io.tile = tile_io(st);
         if (!last) MD_HIP(launch_fill_i32((int32_t*)(st->energy + 4), 0, 4, s), "step/maxd2");
         tick(T, MD_T_FORCE, 0, s);
         MD_HIP(launch_force_step(c.g, c.lj, p->precision, io, s), "step/force");
@@ -736,7 +800,8 @@ int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_eve
         }
         if (sample) {
             tick(T, MD_T_REDUCE, 0, s);
-            MD_HIP(launch_reduce_energy(part_pw, pair_blocks(c.g), part_ke, pair_blocks(c.g), st->energy,
+            const int64_t nfb = force_blocks(c.g, st->list_tiled);
+            MD_HIP(launch_reduce_energy(part_pw, nfb, part_ke, nfb, st->energy,
                                         energy_log ? energy_log + 4 * k_log : nullptr, s),
                    "step/reduce");
             tick(T, MD_T_REDUCE, 1, s);

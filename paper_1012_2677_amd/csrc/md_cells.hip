@@ -241,7 +241,8 @@ __global__ __launch_bounds__(kStreamBlock) void k_resort(Geo g, const int32_t* _
     if (pos32) {
         pos32[k] = make_float4(local_coord(p.x, cx, g.cs[0], g.L[0], g.invL[0]),
                                local_coord(p.y, cy, g.cs[1], g.L[1], g.invL[1]),
-                               local_coord(p.z, cz, g.cs[2], g.L[2], g.invL[2]), 0.0f);
+                               local_coord(p.z, cz, g.cs[2], g.L[2], g.invL[2]),
+                               __int_as_float(cx | (cy << 10) | (cz << 20)));
     }
 }
 
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(kStreamBlock) void k_ref_copy(Geo g, const double4*
         const int32_t c = cell_xyz[k];
         pos32[k] = make_float4(local_coord(p.x, c & 1023, g.cs[0], g.L[0], g.invL[0]),
                                local_coord(p.y, (c >> 10) & 1023, g.cs[1], g.L[1], g.invL[1]),
-                               local_coord(p.z, (c >> 20) & 1023, g.cs[2], g.L[2], g.invL[2]), 0.0f);
+                               local_coord(p.z, (c >> 20) & 1023, g.cs[2], g.L[2], g.invL[2]), __int_as_float(c));
     }
 }
 

@@ -62,6 +62,9 @@ struct PairArgs {
     unsigned long long* max_d2;  // atomic max of squared displacement bits (MODE_KKD)
     unsigned long long* max_v2;  // atomic max of squared drift speed bits (MODE_KKD)
     double dt;
+    const int32_t* start;      // tiled: cell starts and counts (slots in cell order)
+    const int32_t* count;
+    int32_t tc, nt;            // tiled: cells per tile along z, tiles per column
 };
 
 // Keys [kb, ke) of logical block b: a chunk of kForceBlock consecutive slots.
@@ -137,11 +140,10 @@ __device__ __forceinline__ float local_coord(double x, int c, double cs, double 
 }
 
 // Block-level epilogue: (PE, W) and KE partials, displacement maximum.
-template <bool ENERGY, int MODE, bool VMAX>
+template <bool ENERGY, int MODE, bool VMAX, int NW = kForceBlock / 64>
 __device__ __forceinline__ void block_epilogue(const PairArgs& a, int64_t blk, double pe, double w, double ke,
                                                double d2, double v2)
 {
-    constexpr int NW = kForceBlock / 64;
     __shared__ double s_r[5][NW];
     const int wave = threadIdx.x >> 6;
     if (ENERGY) {
@@ -230,7 +232,8 @@ __device__ __forceinline__ void integrate_key(const PairArgs& a, int64_t k, doub
         if (MIXED)
             a.pos32_out[k] = make_float4(local_coord(p.x, c & 1023, a.cs[0], a.L[0], a.invL[0]),
                                          local_coord(p.y, (c >> 10) & 1023, a.cs[1], a.L[1], a.invL[1]),
-                                         local_coord(p.z, (c >> 20) & 1023, a.cs[2], a.L[2], a.invL[2]), 0.0f);
+                                         local_coord(p.z, (c >> 20) & 1023, a.cs[2], a.L[2], a.invL[2]),
+                                         __int_as_float(c));
     }
     vel[k] = vx;
     vel[n + k] = vy;
@@ -463,7 +466,220 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed
     if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE, VMAX>(a, blk, pe, w, ke, d2, v2);
 }
 
+// Tiled force pass (mixed): one block per tile of tc cells along z.  The block
+// first copies the tile's neighbourhood (the runs of cells z0-1 .. z1 of the
+// 9 columns around it, in the order of the list build) from the local
+// coordinates into LDS, each particle as (x + sx cs_x, y + sy cs_y, z, j)
+// with (sx, sy) its column offset and j its position in the run; entries are
+// 16-bit indices into that copy.  With the key's (x, y, z) local and its own
+// run position jk, d = (x_j - x_i, y_j - y_i, (z_j - z_i) + (j - jk) cs_z),
+// the last term exact ((j - jk) is -1, 0 or 1).  The row walk, group sums and
+// integrator epilogue are those of k_pairs_mixed; partners come from LDS
+// instead of global gathers.
+#ifndef MD_TILE_PREFETCH
+#define MD_TILE_PREFETCH 64
+#endif
+constexpr int kPrefetch = MD_TILE_PREFETCH;     // row entries per key loaded up front (multiple of 16)
+
+template <int U, bool ENERGY, int MODE, bool VMAX>
+__global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(PairArgs a)
+{
+    constexpr int NW = kTileBlock / 64;
+    extern __shared__ float4 s_nb[];      // staged neighbourhood, then one stand-in
+    __shared__ float4 s_l[NW][64];
+    __shared__ int64_t s_off[NW][64];
+    __shared__ int32_t s_cnt[NW][64];
+    __shared__ int32_t s_run[9][4];
+    __shared__ int32_t s_base[10];
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
+    const int tz = (int)(blk % a.nt);
+    const int64_t cxy = blk / a.nt;
+    const int cy = (int)(cxy % ny), cx = (int)(cxy / ny);
+    const int z0 = tz * a.tc, z1 = min(z0 + a.tc, nz);
+    const int tid = threadIdx.x;
+    if (tid < 9) {
+        const TileRun r = tile_run(a.start, a.count, wrap_cell(cx + tid / 3 - 1, nx), wrap_cell(cy + tid % 3 - 1, ny),
+                                   ny, nz, z0, z1);
+        s_run[tid][0] = r.sA;
+        s_run[tid][1] = r.lenA;
+        s_run[tid][2] = r.sB;
+        s_run[tid][3] = r.lenB;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int b = 0;
+        for (int col = 0; col < 9; ++col) {
+            s_base[col] = b;
+            b += s_run[col][1] + s_run[col][3];
+        }
+        s_base[9] = b;
+        s_nb[b] = make_float4(1.0e3f, 0.0f, 0.0f, 0.0f);   // stand-in partner, far beyond the cutoff
+    }
+    __syncthreads();
+    const float csx = (float)a.cs[0], csy = (float)a.cs[1], csz = (float)a.cs[2];
+    {
+        // every thread takes elements tid and tid + kTileBlock of each column
+        // run (the loads of all 9 columns in flight together), then writes them
+        // shifted by the column offset and tagged with their run position;
+        // longer runs finish in a plain loop
+        float4 p[9][2];
+#pragma unroll
+        for (int col = 0; col < 9; ++col) {
+            const int sA = s_run[col][0], lenA = s_run[col][1], sB = s_run[col][2], len = lenA + s_run[col][3];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                // unconditional loads (slot 0 past the run's end, result unused)
+                const int i = tid + u * kTileBlock;
+                const int src = i < lenA ? sA + i : sB + (i - lenA);
+                p[col][u] = a.pos32[i < len ? src : 0];
+            }
+        }
+        auto put = [&](const float4& q, int col, int i) {
+            int j = ((__float_as_int(q.w) >> 20) & 1023) - z0 + 1;
+            j += j < 0 ? nz : 0;
+            j -= j >= nz ? nz : 0;
+            s_nb[s_base[col] + i] = make_float4(q.x + (float)(col / 3 - 1) * csx, q.y + (float)(col % 3 - 1) * csy,
+                                                q.z, (float)j);
+        };
+#pragma unroll
+        for (int col = 0; col < 9; ++col) {
+            const int len = s_run[col][1] + s_run[col][3];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int i = tid + u * kTileBlock;
+                if (i < len) put(p[col][u], col, i);
+            }
+        }
+        for (int col = 0; col < 9; ++col) {
+            const int sA = s_run[col][0], lenA = s_run[col][1], sB = s_run[col][2], len = lenA + s_run[col][3];
+            for (int i = tid + 2 * kTileBlock; i < len; i += kTileBlock)
+                put(a.pos32[i < lenA ? sA + i : sB + (i - lenA)], col, i);
+        }
+    }
+    __syncthreads();
+    const uint32_t dummy = (uint32_t)s_base[9];
+    const int64_t colc = ((int64_t)cx * ny + cy) * nz;
+    const int64_t kb = a.start[colc + z0];
+    const int64_t kend = (int64_t)a.start[colc + z1 - 1] + a.count[colc + z1 - 1];
+    const int wave = tid >> 6, lane = tid & 63, sub = lane & 7, grp = lane >> 3;
+    const float rc2 = (float)a.lj.rc2, A = (float)a.lj.A, B = (float)a.lj.B, C8 = (float)a.lj.C8;
+    double pe = 0.0, w = 0.0, ke = 0.0, d2 = 0.0, v2 = 0.0;
+    for (int64_t base = kb + wave * 64; base < kend; base += NW * 64) {
+    const int64_t mykey = base + lane;
+    const bool myvalid = mykey < kend;
+    {
+        const int64_t k = myvalid ? mykey : kend - 1;
+        float4 l = a.pos32[k];
+        l.w = (float)(((__float_as_int(l.w) >> 20) & 1023) - z0 + 1);   // own run position
+        s_l[wave][lane] = l;
+        s_off[wave][lane] = a.offsets[k];
+        s_cnt[wave][lane] = myvalid ? a.counts[k] : 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // the first kPrefetch entries of the 8 rows each lane walks, two per
+    // 32-bit load (rows start at even entries): lane j of a group takes
+    // entries 2j + 16u and 2j + 16u + 1; all loads of the chunk go out at once
+    constexpr int UP = kPrefetch / 16;
+    const uint32_t dummy2 = dummy | (dummy << 16);
+    uint32_t E[8][UP];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int ks = (r << 3) | grp;
+        const int cnt = s_cnt[wave][ks];
+        const uint32_t* row2 = (const uint32_t*)((const uint16_t*)a.nbr + s_off[wave][ks]);
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+            const int t = 2 * sub + 16 * u;
+            E[r][u] = t < cnt ? row2[t >> 1] : dummy2;
+        }
+    }
+    float kfx = 0.f, kfy = 0.f, kfz = 0.f;
+    auto pair = [&](const float4& pj, const float4& li, float& fx, float& fy, float& fz) {
+        const float dx = pj.x - li.x;
+        const float dy = pj.y - li.y;
+        const float dz = __builtin_fmaf(pj.w - li.w, csz, pj.z - li.z);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float r2i = __builtin_amdgcn_rcpf(r2);
+        const float r6i = r2i * r2i * r2i;
+        float g = r2i * r6i * (A * r6i - B) - C8;
+        const bool in = r2 < rc2;
+        g = in ? g : 0.0f;
+        fx -= g * dx;
+        fy -= g * dy;
+        fz -= g * dz;
+        if (ENERGY) {
+            const float V = r6i * ((float)a.lj.A4 * r6i - (float)a.lj.B4) + (float)a.lj.C2 * r2 + (float)a.lj.C0;
+            pe += in ? (double)V : 0.0;
+            w += (double)(g * r2);
+        }
+    };
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int ks = (r << 3) | grp;
+        const int cmax = __builtin_amdgcn_readfirstlane(group8_max(s_cnt[wave][(r << 3) | sub]));
+        const int cnt = s_cnt[wave][ks];
+        const float4 li = s_l[wave][ks];
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+            if (16 * u < cmax) {
+                const int t = 2 * sub + 16 * u;
+                const uint32_t e0 = E[r][u] & 0xFFFFu;
+                const uint32_t e1 = t + 1 < cnt ? E[r][u] >> 16 : dummy;
+                const float4 p0 = s_nb[e0], p1 = s_nb[e1];
+                pair(p0, li, fx, fy, fz);
+                pair(p1, li, fx, fy, fz);
+            }
+        }
+        if (cmax > kPrefetch) {
+            // the rest of rows longer than the prefetched part
+            const uint16_t* row = (const uint16_t*)a.nbr + s_off[wave][ks];
+            for (int t0 = kPrefetch + sub; t0 - sub < cmax; t0 += 8 * U) {
+                uint32_t e[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int t = t0 + u * 8;
+                    e[u] = t < cnt ? (uint32_t)row[t] : dummy;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (t0 - sub + u * 8 < cmax) pair(s_nb[e[u]], li, fx, fy, fz);
+            }
+        }
+        fx = __shfl(group8_sum(fx), sub << 3, 64);
+        fy = __shfl(group8_sum(fy), sub << 3, 64);
+        fz = __shfl(group8_sum(fz), sub << 3, 64);
+        if (grp == r) {
+            kfx = fx;
+            kfy = fy;
+            kfz = fz;
+        }
+    }
+    if (myvalid) {
+        if (!isfinite(kfx + kfy + kfz)) atomicOr((unsigned long long*)a.flags, 1ull);
+        if (MODE != MODE_KKD) {
+            float* F = (float*)a.force;
+            F[mykey] = kfx;
+            F[a.n + mykey] = kfy;
+            F[2 * a.n + mykey] = kfz;
+        }
+        if (MODE != MODE_FORCE) {
+            double kk = 0.0, dd = 0.0, vv = 0.0;
+            integrate_key<MODE, true, VMAX>(a, mykey, kfx, kfy, kfz, kk, dd, vv);
+            ke += kk;
+            d2 = fmax(d2, dd);
+            v2 = fmax(v2, vv);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    }
+    if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE, VMAX, NW>(a, blk, pe, w, ke, d2, v2);
+}
+
 int64_t pair_blocks(const Geo& g) { return ceil_div(g.n, kForceBlock); }
+
+int64_t force_blocks(const Geo& g, bool tiled) { return tiled ? g.ntile : pair_blocks(g); }
 
 static PairArgs make_pair_args(const Geo& g, const LJ& lj, const double* pos, const float* pos32,
                                const int32_t* cell_xyz, const md_pairlist& list)
@@ -483,6 +699,8 @@ static PairArgs make_pair_args(const Geo& g, const LJ& lj, const double* pos, co
         a.nc[k] = g.nc[k];
     }
     a.exact_all = g.exact_all;
+    a.tc = g.tc;
+    a.nt = g.nt;
     a.lj = lj;
     for (int code = 0; code < 27; ++code) {
         const int sx = code / 9 - 1, sy = (code / 3) % 3 - 1, sz = code % 3 - 1;
@@ -495,8 +713,14 @@ static PairArgs make_pair_args(const Geo& g, const LJ& lj, const double* pos, co
 }
 
 template <bool ENERGY, int MODE, bool VMAX = false>
-static void launch_pairs_mode(const Geo& g, int precision, const PairArgs& a, hipStream_t s)
+static void launch_pairs_mode(const Geo& g, int precision, const PairArgs& a, hipStream_t s, int stage)
 {
+    if (stage > 0) {
+        const size_t lds = sizeof(float4) * (size_t)(stage + 1);
+        hipLaunchKernelGGL((k_pairs_tiled<kForceUnroll, ENERGY, MODE, VMAX>), dim3((unsigned)g.ntile),
+                           dim3(kTileBlock), lds, s, a);
+        return;
+    }
     const dim3 grid((unsigned)pair_blocks(g)), block(kForceBlock);
     if (precision == MD_MIXED)
         hipLaunchKernelGGL((k_pairs_mixed<kForceUnroll, ENERGY, MODE, VMAX>), grid, block, 0, s, a);
@@ -504,24 +728,38 @@ static void launch_pairs_mode(const Geo& g, int precision, const PairArgs& a, hi
         hipLaunchKernelGGL((k_pairs_fp64<kForceUnroll64, ENERGY, MODE, VMAX>), grid, block, 0, s, a);
 }
 
+static hipError_t check_tiles(const Geo& g, int precision, const TileIo& t)
+{
+    if (t.stage <= 0) return hipSuccess;
+    if (precision != MD_MIXED || g.tc <= 0 || !t.start || !t.count || t.stage > kTileMaxStage)
+        return hipErrorInvalidValue;
+    return hipSuccess;
+}
+
 hipError_t launch_forces(const Geo& g, const LJ& lj, int precision, const double* pos,
                          const float* pos32, const int32_t* cell_xyz, const md_pairlist& list,
-                         const ForceOut& out, hipStream_t s)
+                         const ForceOut& out, hipStream_t s, const TileIo& tio)
 {
+    if (hipError_t e = check_tiles(g, precision, tio)) return e;
     PairArgs a = make_pair_args(g, lj, pos, pos32, cell_xyz, list);
+    a.start = tio.start;
+    a.count = tio.count;
     a.force = out.force;
     a.part_pw = out.part;
     a.flags = out.flags;
     if (out.part)
-        launch_pairs_mode<true, MODE_FORCE>(g, precision, a, s);
+        launch_pairs_mode<true, MODE_FORCE>(g, precision, a, s, tio.stage);
     else
-        launch_pairs_mode<false, MODE_FORCE>(g, precision, a, s);
+        launch_pairs_mode<false, MODE_FORCE>(g, precision, a, s, tio.stage);
     return hipGetLastError();
 }
 
 hipError_t launch_force_step(const Geo& g, const LJ& lj, int precision, const StepIo& io, hipStream_t s)
 {
+    if (hipError_t e = check_tiles(g, precision, io.tile)) return e;
     PairArgs a = make_pair_args(g, lj, io.pos, io.pos32, io.cell_xyz, io.list);
+    a.start = io.tile.start;
+    a.count = io.tile.count;
     a.force = io.force;
     a.part_pw = io.part_pw;
     a.part_ke = io.part_ke;
@@ -536,14 +774,14 @@ hipError_t launch_force_step(const Geo& g, const LJ& lj, int precision, const St
     const bool energy = io.part_pw != nullptr;
     if (io.drift && io.track_speed) {
         // the largest drift speed is needed by the DUTC rule only
-        if (energy) launch_pairs_mode<true, MODE_KKD, true>(g, precision, a, s);
-        else launch_pairs_mode<false, MODE_KKD, true>(g, precision, a, s);
+        if (energy) launch_pairs_mode<true, MODE_KKD, true>(g, precision, a, s, io.tile.stage);
+        else launch_pairs_mode<false, MODE_KKD, true>(g, precision, a, s, io.tile.stage);
     } else if (io.drift) {
-        if (energy) launch_pairs_mode<true, MODE_KKD>(g, precision, a, s);
-        else launch_pairs_mode<false, MODE_KKD>(g, precision, a, s);
+        if (energy) launch_pairs_mode<true, MODE_KKD>(g, precision, a, s, io.tile.stage);
+        else launch_pairs_mode<false, MODE_KKD>(g, precision, a, s, io.tile.stage);
     } else {
-        if (energy) launch_pairs_mode<true, MODE_KICK>(g, precision, a, s);
-        else launch_pairs_mode<false, MODE_KICK>(g, precision, a, s);
+        if (energy) launch_pairs_mode<true, MODE_KICK>(g, precision, a, s, io.tile.stage);
+        else launch_pairs_mode<false, MODE_KICK>(g, precision, a, s, io.tile.stage);
     }
     return hipGetLastError();
 }

@@ -93,7 +93,8 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
                 ((float4*)a.pos32)[i] =
                     make_float4(local_coord_i(p.x, c & 1023, g.cs[0], g.L[0], g.invL[0]),
                                 local_coord_i(p.y, (c >> 10) & 1023, g.cs[1], g.L[1], g.invL[1]),
-                                local_coord_i(p.z, (c >> 20) & 1023, g.cs[2], g.L[2], g.invL[2]), 0.0f);
+                                local_coord_i(p.z, (c >> 20) & 1023, g.cs[2], g.L[2], g.invL[2]),
+                                __int_as_float(c));
             }
             vel[i] = vx;
             vel[n + i] = vy;
@@ -323,6 +324,7 @@ __global__ void k_gather_flags(const int64_t* __restrict__ status, const int64_t
     out[8] = __double_as_longlong(energy[5]);
     out[9] = err[4];    // large-displacement check: member count
     out[10] = err[5];   // large-displacement check: violation flag
+    out[11] = err[8];   // tiled list: largest staged neighbourhood of a tile
 }
 
 hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags,

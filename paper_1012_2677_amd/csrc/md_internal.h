@@ -38,6 +38,15 @@ constexpr int kReduceBlock = 1024;
 
 constexpr uint32_t kSlotMask = (1u << 27) - 1u;
 constexpr int kCodeShift = 27;
+#ifndef MD_TILE_BLOCK
+#define MD_TILE_BLOCK 256
+#endif
+#ifndef MD_TILE_KEYS
+#define MD_TILE_KEYS 180
+#endif
+constexpr int kTileBlock = MD_TILE_BLOCK;     // threads of the tiled force kernel (one block per tile)
+constexpr int kTileKeys = MD_TILE_KEYS;       // target keys per tile (automatic tile length)
+constexpr int kTileMaxStage = 3500;      // staged particles per tile: 16-bit entries, under 64 KB of LDS with the rest
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -53,6 +62,10 @@ struct Geo {
     double inv[3];    // nc / L   (cell label scale)
     double cs[3];     // L / nc   (cell side)
     int32_t exact_all;  // some axis has fewer than 5 cells: always take minimum images
+    // tiles of the LDS-staged force pass: runs of tc cells along z in one
+    // (x, y) column, nt per column, ntile in all (tc = 0: no tiled layout)
+    int32_t tc, nt;
+    int64_t ntile;
 };
 
 // LJ coefficients in the form the kernels evaluate:
@@ -114,6 +127,54 @@ __device__ __forceinline__ int cell_coord(double x, double inv, int n)
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// ---------------------------------------------------------------------------
+// Tiles (list layout MD_LIST_TILED).  Tile t = (cx * ny + cy) * nt + tz holds
+// the cells z0 = tz * tc .. z1 - 1 (z1 = min(z0 + tc, nz)) of column (cx, cy);
+// its keys are those cells' slots, contiguous once the slots are in cell order.
+// Its partners lie in the runs of cells z0 - 1 .. z1 (periodic in z) of the
+// 9 columns (cx + sx, cy + sy), column index col = (sx + 1) * 3 + (sy + 1).
+// Run position j = 0 .. R - 1 (R = z1 - z0 + 2) is cell z0 - 1 + j.  With
+// tc <= nz - 2 a run wraps at most once: at jw = 1 (z0 = 0) or jw = R - 1
+// (z1 = nz), otherwise jw = R; piece A = positions [0, jw) and piece B =
+// [jw, R) are contiguous slot ranges.  The staged copy of a tile lists the
+// runs column after column, each run in position order, so a particle's
+// index in it is base[col] + (its slot - sA) in piece A and
+// base[col] + lenA + (its slot - sB) in piece B; base[col] sums the earlier
+// runs' lengths.  The list build and the force pass both derive this layout
+// from the cell starts and counts.
+// ---------------------------------------------------------------------------
+struct TileRun {
+    int32_t sA, lenA, sB, lenB;
+};
+
+__device__ __forceinline__ int wrap_cell(int z, int n) { return z < 0 ? z + n : (z >= n ? z - n : z); }
+
+__device__ __forceinline__ int tile_jw(int z0, int z1, int nz)
+{
+    const int R = z1 - z0 + 2;
+    return z0 == 0 ? 1 : (z1 == nz ? R - 1 : R);
+}
+
+// Run of column (X, Y) (already wrapped) for the tile cells [z0, z1).
+__device__ __forceinline__ TileRun tile_run(const int32_t* start, const int32_t* count, int X, int Y, int ny,
+                                            int nz, int z0, int z1)
+{
+    const int R = z1 - z0 + 2, jw = tile_jw(z0, z1, nz);
+    const int64_t col = ((int64_t)X * ny + Y) * nz;
+    const int64_t a0 = col + wrap_cell(z0 - 1, nz), a1 = col + wrap_cell(z0 - 2 + jw, nz);
+    TileRun r;
+    r.sA = start[a0];
+    r.lenA = start[a1] + count[a1] - r.sA;
+    r.sB = 0;
+    r.lenB = 0;
+    if (jw < R) {
+        const int64_t b0 = col + wrap_cell(z0 - 1 + jw, nz), b1 = col + wrap_cell(z1, nz);
+        r.sB = start[b0];
+        r.lenB = start[b1] + count[b1] - r.sB;
+    }
+    return r;
+}
+
 __device__ __forceinline__ uint32_t mbcnt64(uint64_t m)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -145,8 +206,12 @@ hipError_t launch_ref_copy(const Geo& g, const double* pos, const int32_t* cell_
                            float* pos32, hipStream_t s);
 
 // md_pairlist.hip
+// tiled: write 16-bit entries that index the staged copy of the key's tile
+// (slots must be in cell order); the largest staged count of any tile goes to
+// tile_max (atomic max).
 hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cells& cells,
-                        const md_pairlist& list, void* ws, const WsLayout& L, hipStream_t s);
+                        const md_pairlist& list, void* ws, const WsLayout& L, bool tiled,
+                        unsigned long long* tile_max, hipStream_t s);
 
 // md_forces.hip
 struct ForceOut {
@@ -154,9 +219,16 @@ struct ForceOut {
     double* part;       // per-block (PE, W) partials, or nullptr
     int64_t* flags;     // [0] |= 1 on a non-finite force
 };
+// Tiled lists (mixed only) need cells (start / count) and the largest staged
+// count (tile_stage); tile_stage = 0 selects the list of slot entries.
+struct TileIo {
+    const int32_t* start = nullptr;
+    const int32_t* count = nullptr;
+    int32_t stage = 0;
+};
 hipError_t launch_forces(const Geo& g, const LJ& lj, int precision, const double* pos,
                          const float* pos32, const int32_t* cell_xyz, const md_pairlist& list,
-                         const ForceOut& out, hipStream_t s);
+                         const ForceOut& out, hipStream_t s, const TileIo& tio = TileIo());
 // Force evaluation fused with the integrator: the second half kick (drift =
 // false: also writes the force) or second kick + next first kick + drift
 // (drift = true: writes positions to pos_out and, in mixed mode, local
@@ -179,9 +251,11 @@ struct StepIo {
     double dt;
     bool drift;
     bool track_speed;             // also record the largest squared drift speed
+    TileIo tile;                  // tiled list (tile.stage > 0)
 };
 hipError_t launch_force_step(const Geo& g, const LJ& lj, int precision, const StepIo& io, hipStream_t s);
 int64_t pair_blocks(const Geo& g);   // blocks (and energy partials) of one pair-kernel launch
+int64_t force_blocks(const Geo& g, bool tiled);   // same for either list layout
 
 // md_integrate.hip
 enum IntMode { INT_KD = 0, INT_KE = 1 };

@@ -13,6 +13,8 @@
 //
 // The work is ALU bound (about 300 FP64 distance tests per particle).
 
+#include <type_traits>
+
 #include "md_internal.h"
 
 namespace md {
@@ -33,6 +35,8 @@ struct BuildArgs {
     int32_t* counts;
     int32_t* cell_rows;
     int64_t* status;
+    int32_t tc;                       // tiled: cells per tile along z
+    unsigned long long* tile_max;     // tiled: atomic max of the staged count per tile
 };
 
 // r^2 of the pinned predicate: d = q_j - q_i, optional minimum image,
@@ -63,6 +67,14 @@ __device__ __forceinline__ void write_row(const BuildArgs& a, int32_t kslot, int
 }
 
 constexpr int kMaxOwn = 64;     // own-cell particles kept in LDS for the key loop
+
+// Tiled (16-bit) rows start at even entries, so the force pass can read two
+// entries with one 32-bit load; slot-entry rows are packed.
+template <typename E>
+__device__ __forceinline__ uint32_t row_start(uint32_t end)
+{
+    return sizeof(E) == 2 ? (end + 1u) & ~1u : end;
+}
 constexpr int kRowBuf = 1024;   // entries of one cell's rows staged in LDS before the block is written
 
 // Keys of one cell against candidates held in registers (at most NCH*64).
@@ -98,8 +110,8 @@ __device__ __forceinline__ uint32_t row_chunks_lds(const BuildArgs& a, int T, co
 
 // General form: entries go to the LDS row buffer while they fit in it, past
 // that straight to the cell block with a capacity test.
-template <bool MINIMG, int NCH>
-__device__ __forceinline__ uint32_t row_chunks(const BuildArgs& a, uint32_t* blk, uint32_t stride, int T,
+template <bool MINIMG, int NCH, typename E>
+__device__ __forceinline__ uint32_t row_chunks(const BuildArgs& a, E* blk, uint32_t stride, int T,
                                                const double4& kp, int self_t, uint32_t w0, const double* cx,
                                                const double* cy, const double* cz, const uint32_t* meta,
                                                uint32_t* s_rows)
@@ -117,7 +129,7 @@ __device__ __forceinline__ uint32_t row_chunks(const BuildArgs& a, uint32_t* blk
             const uint32_t w = mbcnt64(m) + wpos;
             if (in && lane != sl) {
                 if (w < (uint32_t)kRowBuf) s_rows[w] = meta[ch];
-                else if (w < stride) blk[w] = meta[ch];
+                else if (w < stride) blk[w] = (E)meta[ch];
             }
             wpos += (uint32_t)__popcll(m);
         }
@@ -125,8 +137,8 @@ __device__ __forceinline__ uint32_t row_chunks(const BuildArgs& a, uint32_t* blk
     return wpos;
 }
 
-template <bool MINIMG, int NCH>
-__device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, uint32_t* blk, uint32_t stride,
+template <bool MINIMG, int NCH, typename E>
+__device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* blk, uint32_t stride,
                                                        int T, int own_pref, int own_cnt, const double4* s_key,
                                                        const double* cx, const double* cy, const double* cz,
                                                        const uint32_t* meta, uint32_t* s_rows, uint32_t* s_rowend)
@@ -136,18 +148,19 @@ __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, uint
         if (used + (uint32_t)T <= (uint32_t)kRowBuf)
             used = row_chunks_lds<MINIMG, NCH>(a, T, s_key[kk], own_pref + kk, used, cx, cy, cz, meta, s_rows);
         else
-            used = row_chunks<MINIMG, NCH>(a, blk, stride, T, s_key[kk], own_pref + kk, used, cx, cy, cz, meta,
-                                           s_rows);
+            used = row_chunks<MINIMG, NCH, E>(a, blk, stride, T, s_key[kk], own_pref + kk, used, cx, cy, cz,
+                                              meta, s_rows);
         if (lane_id() == 0) s_rowend[kk] = used;
+        used = row_start<E>(used);
     }
     __syncthreads();
     // the staged part of the block, then the row headers, with full-wave stores
     const uint32_t staged = min(min(used, (uint32_t)kRowBuf), stride);
-    for (uint32_t t = lane_id(); t < staged; t += 64) blk[t] = s_rows[t];
+    for (uint32_t t = lane_id(); t < staged; t += 64) blk[t] = (E)s_rows[t];
     const int kk = (int)lane_id();
     if (kk < own_cnt) {
-        const uint32_t end = s_rowend[kk], beg = kk > 0 ? s_rowend[kk - 1] : 0u;
-        write_row(a, (int32_t)__double_as_longlong(s_key[kk].w), (int64_t)(blk - a.nbr), beg, end - beg);
+        const uint32_t end = s_rowend[kk], beg = kk > 0 ? row_start<E>(s_rowend[kk - 1]) : 0u;
+        write_row(a, (int32_t)__double_as_longlong(s_key[kk].w), (int64_t)(blk - (E*)a.nbr), beg, end - beg);
     }
     return used;
 }
@@ -155,9 +168,9 @@ __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, uint
 // Same rows, candidates re-read from memory for every key (neighbourhoods with
 // more than NCH*64 particles or cells with more than 64 particles: never at
 // liquid densities, kept for generality).
-template <bool MINIMG>
-__device__ uint32_t rows_from_memory(const BuildArgs& a, uint32_t* blk, uint32_t stride, int T, int own_start,
-                                     int own_cnt, const int* s_pref, const int* s_nstart)
+template <bool MINIMG, typename E>
+__device__ uint32_t rows_from_memory(const BuildArgs& a, E* blk, uint32_t stride, int T, int own_start,
+                                     int own_cnt, const int* s_pref, const int* s_nstart, const int* s_lbase)
 {
     uint32_t used = 0;
     for (int kk = 0; kk < own_cnt; ++kk) {
@@ -177,22 +190,23 @@ __device__ uint32_t rows_from_memory(const BuildArgs& a, uint32_t* blk, uint32_t
                 const double4 p = a.pos[slot];
                 const double r2 = pair_r2<MINIMG>(a, p.x, p.y, p.z, kp.x, kp.y, kp.z);
                 pass = r2 < a.rs2 && slot != kslot;
-                meta = (uint32_t)slot | ((uint32_t)q << kCodeShift);
+                meta = s_lbase ? (uint32_t)(s_lbase[q] + (t - s_pref[q])) : (uint32_t)slot | ((uint32_t)q << kCodeShift);
             }
             const uint64_t m = __ballot(pass);
             const uint32_t w = used + wpos + mbcnt64(m);
-            if (pass && w < stride) blk[w] = meta;
+            if (pass && w < stride) blk[w] = (E)meta;
             wpos += (uint32_t)__popcll(m);
         }
-        if (lane_id() == 0) write_row(a, kslot, (int64_t)(blk - a.nbr), used, wpos);
-        used += wpos;
+        if (lane_id() == 0) write_row(a, kslot, (int64_t)(blk - (E*)a.nbr), used, wpos);
+        used = row_start<E>(used + wpos);
     }
     return used;
 }
 
-template <int NCH>
+template <int NCH, bool TILED>
 __global__ __launch_bounds__(64) void k_build(BuildArgs a)
 {
+    using E = typename std::conditional<TILED, uint16_t, uint32_t>::type;
     const int64_t c = xcd_remap(blockIdx.x, gridDim.x);
     if (c >= a.ncell) return;
     const int lane = (int)threadIdx.x;
@@ -206,6 +220,7 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     __shared__ double4 s_key[kMaxOwn];
     __shared__ uint32_t s_rows[kRowBuf + 1];   // + a spare word for lanes that store nothing
     __shared__ uint32_t s_rowend[kMaxOwn];
+    __shared__ int s_lbase[27];
     int cnt = 0, st = 0;
     if (lane < 27) {
         int ax = cx + lane / 9 - 1, ay = cy + (lane / 3) % 3 - 1, az = cz + lane % 3 - 1;
@@ -230,6 +245,34 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
         s_pref[lane + 1] = incl;
     }
     if (lane == 0) s_pref[0] = 0;
+    if (TILED) {
+        // the tile's staged layout: the 9 column runs (lanes 0..8), their
+        // bases (exclusive prefix of the run lengths), then the staged index of
+        // the first particle of each neighbour cell q (lanes 0..26; q / 3 is
+        // the column of q)
+        const int z0 = (cz / a.tc) * a.tc, z1 = min(z0 + a.tc, nz);
+        const int jw = tile_jw(z0, z1, nz);
+        TileRun run = {0, 0, 0, 0};
+        if (lane < 9)
+            run = tile_run(a.start, a.count, wrap_cell(cx + lane / 3 - 1, nx), wrap_cell(cy + lane % 3 - 1, ny), ny,
+                           nz, z0, z1);
+        const int len = lane < 9 ? run.lenA + run.lenB : 0;
+        int inc = len;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const int y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        const int total = __shfl(inc, 8, 64);
+        const int col = lane < 27 ? lane / 3 : 0;
+        const int cbase = __shfl(inc - len, col, 64);
+        const int sA = __shfl(run.sA, col, 64), lenA = __shfl(run.lenA, col, 64), sB = __shfl(run.sB, col, 64);
+        if (lane < 27) {
+            const int j = cz + lane % 3 - 1 - z0 + 1;
+            s_lbase[lane] = cbase + (j < jw ? st - sA : lenA + st - sB);
+        }
+        if (lane == 0 && cz == z0) atomicMax(a.tile_max, (unsigned long long)total);
+    }
     __syncthreads();
 
     const int T = s_pref[27];
@@ -238,7 +281,7 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     const int own_cnt = s_pref[14] - own_pref;
     const bool minimg = a.exact_all || cx == 0 || cx == nx - 1 || cy == 0 || cy == ny - 1 || cz == 0 ||
                         cz == nz - 1;
-    uint32_t* blk = a.nbr + c * a.stride;
+    E* blk = (E*)a.nbr + c * a.stride;
     // capped so that byte offsets (entries << 2) fit in 32 bits
     const uint32_t stride = (uint32_t)(a.stride < (1 << 29) ? a.stride : (1 << 29));
     uint32_t used = 0;
@@ -270,18 +313,19 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
             px[ch] = ok ? p.x : qnan;
             py[ch] = ok ? p.y : qnan;
             pz[ch] = ok ? p.z : qnan;
-            meta[ch] = (uint32_t)slot | ((uint32_t)lo << kCodeShift);
+            meta[ch] = TILED ? (uint32_t)(s_lbase[lo] + (tt - s_pref[lo])) : (uint32_t)slot | ((uint32_t)lo << kCodeShift);
             const int k = t - own_pref;
             if (ok && k >= 0 && k < own_cnt) s_key[k] = make_double4(p.x, p.y, p.z, __longlong_as_double((long long)slot));
         }
         __syncthreads();
-        used = minimg ? rows_from_registers<true, NCH>(a, blk, stride, T, own_pref, own_cnt, s_key, px, py, pz,
-                                                       meta, s_rows, s_rowend)
-                      : rows_from_registers<false, NCH>(a, blk, stride, T, own_pref, own_cnt, s_key, px, py, pz,
-                                                        meta, s_rows, s_rowend);
+        used = minimg ? rows_from_registers<true, NCH, E>(a, blk, stride, T, own_pref, own_cnt, s_key, px, py, pz,
+                                                          meta, s_rows, s_rowend)
+                      : rows_from_registers<false, NCH, E>(a, blk, stride, T, own_pref, own_cnt, s_key, px, py,
+                                                           pz, meta, s_rows, s_rowend);
     } else if (own_cnt > 0) {
-        used = minimg ? rows_from_memory<true>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart)
-                      : rows_from_memory<false>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart);
+        const int* lb = TILED ? s_lbase : nullptr;
+        used = minimg ? rows_from_memory<true, E>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart, lb)
+                      : rows_from_memory<false, E>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart, lb);
     }
     if (lane == 0) {
         a.cell_rows[c] = used > 0x7FFFFFFFu ? 0x7FFFFFFF : (int32_t)used;
@@ -290,7 +334,8 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
 }
 
 hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cells& cells,
-                        const md_pairlist& list, void* ws, const WsLayout& L, hipStream_t s)
+                        const md_pairlist& list, void* ws, const WsLayout& L, bool tiled,
+                        unsigned long long* tile_max, hipStream_t s)
 {
     BuildArgs a;
     a.pos = (const double4*)pos;
@@ -311,11 +356,15 @@ hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cel
     a.counts = list.counts;
     a.cell_rows = (int32_t*)((char*)ws + L.cell_rows);
     a.status = list.status;
+    a.tc = g.tc;
+    a.tile_max = tile_max;
+    if (tiled && (!cells.sorted || g.tc <= 0 || !tile_max)) return hipErrorInvalidValue;
     // status[2] (overflow) is cleared by the statistics kernel of the previous
     // build or by the caller; clear it here on the stream before the build.
     hipError_t e = launch_fill_i32((int32_t*)list.status, 0, 8, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_build<kBuildChunks>, dim3((unsigned)g.ncell), dim3(64), 0, s, a);
+    if (tiled) hipLaunchKernelGGL((k_build<kBuildChunks, true>), dim3((unsigned)g.ncell), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((k_build<kBuildChunks, false>), dim3((unsigned)g.ncell), dim3(64), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_list_stats(a.cell_rows, g.ncell, list.status, (long long*)((char*)ws + L.red), s);

@@ -22,8 +22,12 @@ def _ptr(t: torch.Tensor | None) -> int | None:
 REBUILD_RULES = {"half_skin": A.MD_REBUILD_HALF_SKIN, "dutc_ldc": A.MD_REBUILD_DUTC_LDC}
 
 
+LIST_LAYOUTS = {"auto": A.MD_LIST_AUTO, "slots": A.MD_LIST_SLOTS}
+
+
 def make_params(n, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precision="fp64",
-                resort_every=1, rebuild_rule="half_skin", ldc_max=8192) -> A.MdParams:
+                resort_every=1, rebuild_rule="half_skin", ldc_max=8192, list_layout="auto",
+                tile_cells=0) -> A.MdParams:
     p = A.MdParams()
     p.n = int(n)
     b = np.broadcast_to(np.asarray(box, dtype=np.float64), (3,))
@@ -34,6 +38,8 @@ def make_params(n, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precisi
     p.resort_every = int(resort_every)
     p.rebuild_rule = REBUILD_RULES[rebuild_rule] if isinstance(rebuild_rule, str) else int(rebuild_rule)
     p.ldc_max = int(ldc_max)
+    p.list_layout = LIST_LAYOUTS[list_layout] if isinstance(list_layout, str) else int(list_layout)
+    p.tile_cells = int(tile_cells)
     return p
 
 
@@ -130,12 +136,15 @@ class Engine:
     [0, L)^3.  precision: "fp64" or "mixed".  resort_every: re-sort the particle
     arrays into cell order at every k-th rebuild (0 = never).  rebuild_rule:
     "half_skin" or "dutc_ldc" (DUTC, then the large-displacement check with at
-    most ldc_max members).
+    most ldc_max members).  list_layout: "auto" (in mixed precision, the tiled
+    list whose force pass stages each tile's neighbourhood in LDS, whenever the
+    slots are in cell order) or "slots"; tile_cells: tile length along z in
+    cells (0 = automatic).
     """
 
     def __init__(self, pos, vel, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precision="fp64",
-                 resort_every=1, rebuild_rule="half_skin", ldc_max=8192, device="cuda", cell_stride=None,
-                 timers=False):
+                 resort_every=1, rebuild_rule="half_skin", ldc_max=8192, list_layout="auto", tile_cells=0,
+                 device="cuda", cell_stride=None, timers=False):
         pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64))
         vel = np.ascontiguousarray(np.asarray(vel, dtype=np.float64))
         n = pos.shape[0]
@@ -143,7 +152,8 @@ class Engine:
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.params = make_params(n, box, eps=eps, sigma=sigma, rc=rc, rs=rs, dt=dt, precision=precision,
-                                  resort_every=resort_every, rebuild_rule=rebuild_rule, ldc_max=ldc_max)
+                                  resort_every=resort_every, rebuild_rule=rebuild_rule, ldc_max=ldc_max,
+                                  list_layout=list_layout, tile_cells=tile_cells)
         self.n = n
         self.mixed = self.params.precision == A.MD_MIXED
         dev = self.device

@@ -129,3 +129,59 @@ def rows_for_slots(plist, slots):
     within = torch.arange(rep.numel(), device=s.device) - first[rep]
     ent = plist.nbr[off[rep] + within].long() & 0xFFFFFFFF
     return rep.cpu().numpy(), (ent & SLOT_MASK).cpu().numpy(), (ent >> 27).cpu().numpy()
+
+
+def _wrap(z, n):
+    return z + n if z < 0 else (z - n if z >= n else z)
+
+
+def tile_slots(start, count, nc, tc, key_cell_xyz, entries):
+    """Partner slots of tiled entries (16-bit indices into the staged
+    neighbourhood of the key's tile), decoded on the host from the layout the
+    C header states: tiles of tc cells along z; a tile's neighbourhood lists
+    the runs of cells z0-1 .. z1 (periodic) of the 9 columns (cx+sx, cy+sy),
+    column (sx+1)*3 + (sy+1) after column, each run in z order from z0-1.
+    start, count: host int arrays of the cell grid; key_cell_xyz: packed cell
+    of the key of each entry."""
+    nx, ny, nz = nc
+    out = np.empty(len(entries), np.int64)
+    cache = {}
+    for i, (c, e) in enumerate(zip(key_cell_xyz, entries)):
+        cx, cy, cz = c & 1023, (c >> 10) & 1023, (c >> 20) & 1023
+        z0 = (cz // tc) * tc
+        key = (cx, cy, z0)
+        if key not in cache:
+            z1 = min(z0 + tc, nz)
+            pieces = []
+            for col in range(9):
+                X, Y = _wrap(cx + col // 3 - 1, nx), _wrap(cy + col % 3 - 1, ny)
+                slots = []
+                for z in range(z0 - 1, z1 + 1):
+                    cell = (X * ny + Y) * nz + _wrap(z, nz)
+                    slots.extend(range(int(start[cell]), int(start[cell]) + int(count[cell])))
+                pieces.extend(slots)
+            cache[key] = np.asarray(pieces, np.int64)
+        out[i] = cache[key][e]
+    return out
+
+
+def rows_for_slots_state(e, slots):
+    """rows_for_slots for an Engine's state list in either layout: returns
+    (key index into `slots`, partner slot)."""
+    if not int(e.state.list_tiled):
+        k, p, _ = rows_for_slots(e.plist, slots)
+        return k, p
+    pl = e.plist
+    s = torch.as_tensor(slots, dtype=torch.long, device=pl.offsets.device)
+    off = pl.offsets[s]
+    cnt = pl.counts[s].long()
+    rep = torch.repeat_interleave(torch.arange(s.numel(), device=s.device), cnt)
+    first = torch.cumsum(cnt, 0) - cnt
+    within = torch.arange(rep.numel(), device=s.device) - first[rep]
+    nbr16 = pl.nbr.view(torch.int16)
+    ent = (nbr16[off[rep] + within].long() & 0xFFFF).cpu().numpy()
+    kcell = e.grid.cell_xyz[s].cpu().numpy()[rep.cpu().numpy()]
+    start = e.grid.start.cpu().numpy()
+    count = e.grid.count.cpu().numpy()
+    partners = tile_slots(start, count, e.grid.ncell, int(e.state.tile_cells), kcell, ent)
+    return rep.cpu().numpy(), partners

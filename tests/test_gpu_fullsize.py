@@ -3,7 +3,8 @@ times (re-sort at every rebuild; mixed precision at 32M and 131M, FP64 at 4M),
 on sampled particles the oracle can check one by one:
 
   * the pair-list rows of the sampled particles equal the oracle's neighbour
-    sets within rs (exact set equality, ids);
+    sets within rs (exact set equality, ids; mixed runs hold the tiled list,
+    decoded on the host);
   * the forces on the sampled particles equal the oracle's to the precision
     bar (1e-5 mixed, 1e-12 FP64, relative to the pair-force scale S_i);
   * the list's total entry count equals twice the number of pairs implied by
@@ -46,7 +47,7 @@ def _check_state(ref, e, L, ids, tol):
     slot_of_id = torch.empty_like(ids_dev)
     slot_of_id[ids_dev] = torch.arange(e.n, device=ids_dev.device)
     slots = slot_of_id[torch.as_tensor(ids, device=ids_dev.device)]
-    kidx, pslot, _ = G.rows_for_slots(e.plist, slots)
+    kidx, pslot = G.rows_for_slots_state(e, slots.cpu().numpy())
     pid = e.id.cpu().numpy()[pslot]
     ref_rows = ref.neighbors_sample(q, L, ids, rs=e.params.rs, grid=grid)
     for k in range(len(ids)):
@@ -80,6 +81,8 @@ def test_full_size_sampled_parity(ref, config, precision, tol, steps):
     e.step(steps)
     assert e.rebuilds > 3
     e.prepare()
+    # mixed runs use the tiled list (the benchmark's configuration)
+    assert int(e.state.list_tiled) == (1 if precision == "mixed" else 0)
     _check_state(ref, e, L, _sample_ids(n, 2048, 1), tol)
 
 
@@ -96,4 +99,5 @@ def test_largest_workload_sampled_parity(ref):
     del q, v
     e.step(12)
     e.prepare()
+    assert int(e.state.list_tiled) == 1
     _check_state(ref, e, L, _sample_ids(n, 1024, 2), 1e-5)

@@ -1,0 +1,128 @@
+"""GPU tests of the tiled list layout of the simulation state (mixed precision).
+
+The state's list is tiled when the slots are in cell order: entries are 16-bit
+indices into the staged neighbourhood of the key's tile, and the force pass
+reads partners from LDS.  These tests check:
+
+  * when the library chooses the tiled layout, and that it falls back to slot
+    entries when a tile's neighbourhood is too large to stage;
+  * index work, bit-exact: every tiled row, decoded on the host from the
+    documented layout, equals the slot-layout row of the same key entry by
+    entry, and both equal the oracle's neighbour sets;
+  * forces after md_prepare against the FP64 oracle (1e-5 of the pair-force
+    scale) for several tile lengths, including tiles that wrap the box in z;
+  * a run with the tiled list tracks the FP64 oracle (energy per particle to
+    1e-5) and the slot-layout run.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import lj_inputs as li
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _cuda():
+    assert torch.cuda.is_available()
+    import paper_1012_2677_amd  # noqa: F401
+
+
+def _engine(q, v, L, **kw):
+    from paper_1012_2677_amd import Engine
+
+    return Engine(q, v, L, device="cuda:0", **kw)
+
+
+def _jittered(n_fcc, seed, rho=0.5, amp=0.15):
+    q, L = li.jittered_fcc(n_fcc, amp=amp, seed=seed, rho=rho)
+    q, _, _ = li.shuffle_labels(q, seed=seed)
+    return q, L
+
+
+def test_layout_selection():
+    q, L = li.fcc_lattice(10)
+    v = li.maxwell_boltzmann(q.shape[0], seed=0)
+    e = _engine(q, v, L, precision="mixed")
+    e.prepare()
+    assert int(e.state.list_tiled) == 1
+    assert int(e.state.tile_cells) == 5          # clipped to nz - 2 with 7 cells per axis
+    assert 0 < int(e.state.tile_stage) <= 3500
+    for kw in (dict(precision="fp64"), dict(precision="mixed", resort_every=0),
+               dict(precision="mixed", list_layout="slots")):
+        f = _engine(q, v, L, **kw)
+        f.prepare()
+        assert int(f.state.list_tiled) == 0, kw
+
+
+@pytest.mark.parametrize("tile_cells", [0, 1, 2, 3])
+def test_tiled_rows_equal_slot_rows_and_oracle(ref, tile_cells):
+    q, L = _jittered(10, seed=11)
+    v = li.maxwell_boltzmann(q.shape[0], seed=11)
+    t = _engine(q, v, L, precision="mixed", tile_cells=tile_cells)
+    s = _engine(q, v, L, precision="mixed", list_layout="slots")
+    t.prepare()
+    s.prepare()
+    assert int(t.state.list_tiled) == 1 and int(s.state.list_tiled) == 0
+    assert torch.equal(t.id, s.id)
+    n = q.shape[0]
+    slots = np.arange(n)
+    kt, pt = G.rows_for_slots_state(t, slots)
+    ks, ps = G.rows_for_slots_state(s, slots)
+    assert np.array_equal(kt, ks)
+    assert np.array_equal(pt, ps)
+    # and the oracle's neighbour sets, by particle id
+    ids = t.id.cpu().numpy()
+    qp = t.positions()
+    rows = ref.neighbors_sample(qp, L, ids, rs=2.8)
+    for k in range(n):
+        assert np.array_equal(np.sort(ids[pt[kt == k]]), rows[k])
+
+
+@pytest.mark.parametrize("tile_cells", [0, 1, 2, 4, 5, 1023])
+def test_tiled_forces_match_oracle(ref, tile_cells):
+    q, L = _jittered(10, seed=3)
+    v = li.maxwell_boltzmann(q.shape[0], seed=3)
+    e = _engine(q, v, L, precision="mixed", tile_cells=tile_cells)
+    e.prepare()
+    assert int(e.state.list_tiled) == 1
+    idx = np.arange(q.shape[0], dtype=np.int64)
+    Fr, S, pe_i, w_i, _ = ref.forces_sample(e.positions(), L, idx)
+    assert G.force_error(e.forces(), Fr, S) <= 1e-5
+    en = e.energies()   # per-particle shares of the oracle sum to the totals
+    assert abs(en[1] - pe_i.sum()) / q.shape[0] < 1e-5
+    assert abs(en[2] - w_i.sum()) / q.shape[0] < 1e-4
+
+
+def test_tiled_run_tracks_oracle_and_slot_run(ref):
+    q, L = li.fcc_lattice(10)
+    v = li.maxwell_boltzmann(q.shape[0], T=1.0, seed=0)
+    t = _engine(q, v, L, precision="mixed")
+    s = _engine(q, v, L, precision="mixed", list_layout="slots")
+    lt = t.step(100, sample_every=10)
+    ls = s.step(100, sample_every=10)
+    assert int(t.state.list_tiled) == 1
+    _, _, rlog, rreb = ref.run(q, v, L, 100, dt=0.005, sample_every=10)
+    n = q.shape[0]
+    for log in (lt, ls):
+        assert np.abs(log[:, 3] - rlog[:, 3]).max() / n < 1e-5
+        assert np.abs(log[:, 1] - rlog[:, 1]).max() / n < 1e-5
+    assert np.abs(lt - ls).max() / n < 1e-5
+    assert t.rebuilds == s.rebuilds
+
+
+def test_oversized_tiles_fall_back_to_slot_entries(ref):
+    # a dense solid (rho = 1) with long tiles: the staged neighbourhood of a
+    # tile (~9 * 20 cells * 23 particles) exceeds what the force pass stages
+    q, L = li.fcc_lattice(36, rho=1.0)
+    v = li.maxwell_boltzmann(q.shape[0], T=0.2, seed=1)
+    e = _engine(q, v, L, precision="mixed", tile_cells=18)
+    e.prepare()
+    assert int(e.state.list_tiled) == 0
+    e.step(5)
+    idx = np.random.default_rng(0).choice(q.shape[0], 300, replace=False).astype(np.int64)
+    Fr, S, _, _, _ = ref.forces_sample(e.positions(), L, idx)
+    assert G.force_error(e.forces()[idx], Fr, S) <= 1e-5
