@@ -87,9 +87,10 @@ extern "C" {
  *   re-sort), the list's cell_stride is even and every tile's neighbourhood
  *   fits, the tiled layout: the cells
  *   are cut into tiles of tile_cells consecutive cells along z, and an entry
- *   is the 16-bit index of the partner in the tile's neighbourhood (the runs
- *   of cells around the tile in the 9 columns next to it, which the force
- *   pass stages in LDS); otherwise, and always with MD_LIST_SLOTS, entries are
+ *   is 16 times the index of the partner in the tile's neighbourhood (its
+ *   byte offset in the copy of the runs of cells around the tile in the 9
+ *   columns next to it, which the force pass stages in LDS, 16 bytes per
+ *   particle); otherwise, and always with MD_LIST_SLOTS, entries are
  *   32-bit partner slots as in md_build_pairlist.  Both layouts hold the same
  *   pairs in the same row order.
  *   tile_cells: cells per tile along z (0 = about 224 keys per tile at the
@@ -192,8 +193,9 @@ typedef struct md_timers {
  *   list_tiled: 1 when st->list holds the tiled layout (set by the library):
  *   nbr is then read as uint16 entries, offsets count uint16 units, and the
  *   rows of cell c live in ((uint16_t*)nbr)[c*cell_stride ..), each row
- *   starting at an even entry (a row of odd length is followed by one unused
- *   entry, counted in the list status); tile_stage:
+ *   starting at an even entry (a row of odd length is followed by one entry
+ *   naming the stand-in just past the tile's neighbourhood, counted in the
+ *   list status but not in the row's count); tile_stage:
  *   the largest neighbourhood of a tile, in particles; tile_cells: the tile
  *   length along z in cells. */
 typedef struct md_state {

@@ -192,25 +192,47 @@ __device__ __forceinline__ void block_epilogue(const PairArgs& a, int64_t blk, d
 }
 
 // Integrator epilogue of one key (lane): kicks, drift, wrap, displacement since
-// the last build.  Same arithmetic as the stand-alone integrator.
+// the last build.  Same arithmetic as the stand-alone integrator.  The loads
+// (load_key) and the arithmetic and stores (integrate_loaded) are separate so
+// that a kernel can issue the loads early.
+struct KeyIn {
+    double vx, vy, vz;
+    double4 p;
+    double rx, ry, rz;
+    int32_t c;
+};
+
+template <int MODE, bool MIXED>
+__device__ __forceinline__ KeyIn load_key(const PairArgs& a, int64_t k)
+{
+    const int64_t n = a.n;
+    KeyIn in;
+    in.vx = a.vel[k];
+    in.vy = a.vel[n + k];
+    in.vz = a.vel[2 * n + k];
+    in.p = make_double4(0.0, 0.0, 0.0, 0.0);
+    in.rx = in.ry = in.rz = 0.0;
+    in.c = 0;
+    if (MODE == MODE_KKD) {
+        in.p = a.pos[k];
+        in.rx = a.pos_ref[k];
+        in.ry = a.pos_ref[n + k];
+        in.rz = a.pos_ref[2 * n + k];
+        if (MIXED) in.c = a.cell_xyz[k];
+    }
+    return in;
+}
+
 template <int MODE, bool MIXED, bool VMAX>
-__device__ __forceinline__ void integrate_key(const PairArgs& a, int64_t k, double fx, double fy, double fz,
-                                              double& ke, double& d2, double& v2)
+__device__ __forceinline__ void integrate_loaded(const PairArgs& a, int64_t k, const KeyIn& in, double fx,
+                                                 double fy, double fz, double& ke, double& d2, double& v2)
 {
     const int64_t n = a.n;
     const double h = 0.5 * a.dt;
     double* __restrict__ vel = a.vel;
-    double vx = vel[k], vy = vel[n + k], vz = vel[2 * n + k];
-    double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
-    double rx = 0.0, ry = 0.0, rz = 0.0;
-    int32_t c = 0;
-    if (MODE == MODE_KKD) {
-        p = a.pos[k];
-        rx = a.pos_ref[k];
-        ry = a.pos_ref[n + k];
-        rz = a.pos_ref[2 * n + k];
-        if (MIXED) c = a.cell_xyz[k];
-    }
+    double vx = in.vx, vy = in.vy, vz = in.vz;
+    double4 p = in.p;
+    const int32_t c = in.c;
     vx = vx + h * fx;
     vy = vy + h * fy;
     vz = vz + h * fz;
@@ -223,7 +245,7 @@ __device__ __forceinline__ void integrate_key(const PairArgs& a, int64_t k, doub
         p.x = wrap_coord(p.x + a.dt * vx, a.L[0], a.invL[0]);
         p.y = wrap_coord(p.y + a.dt * vy, a.L[1], a.invL[1]);
         p.z = wrap_coord(p.z + a.dt * vz, a.L[2], a.invL[2]);
-        double ex = p.x - rx, ey = p.y - ry, ez = p.z - rz;
+        double ex = p.x - in.rx, ey = p.y - in.ry, ez = p.z - in.rz;
         ex -= a.L[0] * rint(ex * a.invL[0]);
         ey -= a.L[1] * rint(ey * a.invL[1]);
         ez -= a.L[2] * rint(ez * a.invL[2]);
@@ -238,6 +260,13 @@ __device__ __forceinline__ void integrate_key(const PairArgs& a, int64_t k, doub
     vel[k] = vx;
     vel[n + k] = vy;
     vel[2 * n + k] = vz;
+}
+
+template <int MODE, bool MIXED, bool VMAX>
+__device__ __forceinline__ void integrate_key(const PairArgs& a, int64_t k, double fx, double fy, double fz,
+                                              double& ke, double& d2, double& v2)
+{
+    integrate_loaded<MODE, MIXED, VMAX>(a, k, load_key<MODE, MIXED>(a, k), fx, fy, fz, ke, d2, v2);
 }
 
 template <int U, bool ENERGY, int MODE, bool VMAX>
@@ -486,9 +515,7 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
 {
     constexpr int NW = kTileBlock / 64;
     extern __shared__ float4 s_nb[];      // staged neighbourhood, then one stand-in
-    __shared__ float4 s_l[NW][64];
-    __shared__ int64_t s_off[NW][64];
-    __shared__ int32_t s_cnt[NW][64];
+    __shared__ uint8_t s_perm[NW][64];
     __shared__ int32_t s_run[9][4];
     __shared__ int32_t s_base[10];
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -558,36 +585,65 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         }
     }
     __syncthreads();
-    const uint32_t dummy = (uint32_t)s_base[9];
+    const uint32_t dummy = (uint32_t)s_base[9] << 4;   // byte offset of the stand-in partner
     const int64_t colc = ((int64_t)cx * ny + cy) * nz;
     const int64_t kb = a.start[colc + z0];
     const int64_t kend = (int64_t)a.start[colc + z1 - 1] + a.count[colc + z1 - 1];
     const int wave = tid >> 6, lane = tid & 63, sub = lane & 7, grp = lane >> 3;
     const float rc2 = (float)a.lj.rc2, A = (float)a.lj.A, B = (float)a.lj.B, C8 = (float)a.lj.C8;
     double pe = 0.0, w = 0.0, ke = 0.0, d2 = 0.0, v2 = 0.0;
-    for (int64_t base = kb + wave * 64; base < kend; base += NW * 64) {
+    // the tile's keys split evenly over the waves, in chunks of at most 64
+    // (a multiple of 8): nr rounds per chunk instead of always 8
+    const int64_t nk = kend - kb;
+    const int csz_k = nk >= NW * 64 ? 64 : (int)((((nk + NW - 1) / NW) + 7) & ~(int64_t)7);
+    for (int64_t base = kb + wave * csz_k; base < kend; base += NW * csz_k) {
+    const int64_t cend = base + csz_k < kend ? base + csz_k : kend;
+    const int nr = (int)((cend - base + 7) >> 3);
     const int64_t mykey = base + lane;
-    const bool myvalid = mykey < kend;
+    const bool myvalid = mykey < cend;
+    // the lane's own key: local coordinates with its run position in w, row
+    // offset and length; rounds fetch them from the owner lane by shuffles
+    float4 own;
+    int64_t own_off;
+    int own_cnt;
     {
         const int64_t k = myvalid ? mykey : kend - 1;
-        float4 l = a.pos32[k];
-        l.w = (float)(((__float_as_int(l.w) >> 20) & 1023) - z0 + 1);   // own run position
-        s_l[wave][lane] = l;
-        s_off[wave][lane] = a.offsets[k];
-        s_cnt[wave][lane] = myvalid ? a.counts[k] : 0;
+        own = a.pos32[k];
+        own.w = (float)(((__float_as_int(own.w) >> 20) & 1023) - z0 + 1);
+        own_off = a.offsets[k];
+        own_cnt = myvalid ? a.counts[k] : 0;
+    }
+    // round order: the chunk's keys grouped by row length in steps of 16
+    // entries (longest first), so that the 8 rows a round walks to a common
+    // bound have similar lengths; lane L's key is walked in round pr >> 3 by
+    // group pr & 7
+    int pr;
+    {
+        const int b = min((own_cnt + 15) >> 4, 7);
+        int off = 0;
+        pr = 0;
+#pragma unroll
+        for (int v = 7; v >= 0; --v) {
+            const uint64_t m = __ballot(b == v);
+            if (b == v) pr = off + (int)mbcnt64(m);
+            off += __popcll(m);
+        }
+        s_perm[wave][pr] = (uint8_t)lane;
     }
     __builtin_amdgcn_wave_barrier();
     // the first kPrefetch entries of the 8 rows each lane walks, two per
-    // 32-bit load (rows start at even entries): lane j of a group takes
-    // entries 2j + 16u and 2j + 16u + 1; all loads of the chunk go out at once
+    // 32-bit load (rows start at even entries, a row of odd length ends with
+    // the stand-in): lane j of a group takes entries 2j + 16u and 2j + 16u + 1;
+    // all loads of the chunk go out at once
     constexpr int UP = kPrefetch / 16;
     const uint32_t dummy2 = dummy | (dummy << 16);
     uint32_t E[8][UP];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int ks = (r << 3) | grp;
-        const int cnt = s_cnt[wave][ks];
-        const uint32_t* row2 = (const uint32_t*)((const uint16_t*)a.nbr + s_off[wave][ks]);
+        if (r >= nr) break;
+        const int ks = s_perm[wave][(r << 3) | grp];
+        const int cnt = __shfl(own_cnt, ks, 64);
+        const uint32_t* row2 = (const uint32_t*)((const uint16_t*)a.nbr + __shfl(own_off, ks, 64));
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
             const int t = 2 * sub + 16 * u;
@@ -614,27 +670,27 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
             w += (double)(g * r2);
         }
     };
+    auto nb = [&](uint32_t byte) { return *(const float4*)((const char*)s_nb + byte); };
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int ks = (r << 3) | grp;
-        const int cmax = __builtin_amdgcn_readfirstlane(group8_max(s_cnt[wave][(r << 3) | sub]));
-        const int cnt = s_cnt[wave][ks];
-        const float4 li = s_l[wave][ks];
+        if (r >= nr) break;
+        const int ks = s_perm[wave][(r << 3) | grp];
+        const int cmax = __builtin_amdgcn_readfirstlane(group8_max(__shfl(own_cnt, s_perm[wave][(r << 3) | sub], 64)));
+        const int cnt = __shfl(own_cnt, ks, 64);
+        const float4 li = make_float4(__shfl(own.x, ks, 64), __shfl(own.y, ks, 64), __shfl(own.z, ks, 64),
+                                      __shfl(own.w, ks, 64));
         float fx = 0.f, fy = 0.f, fz = 0.f;
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
             if (16 * u < cmax) {
-                const int t = 2 * sub + 16 * u;
-                const uint32_t e0 = E[r][u] & 0xFFFFu;
-                const uint32_t e1 = t + 1 < cnt ? E[r][u] >> 16 : dummy;
-                const float4 p0 = s_nb[e0], p1 = s_nb[e1];
+                const float4 p0 = nb(E[r][u] & 0xFFFFu), p1 = nb(E[r][u] >> 16);
                 pair(p0, li, fx, fy, fz);
                 pair(p1, li, fx, fy, fz);
             }
         }
         if (cmax > kPrefetch) {
             // the rest of rows longer than the prefetched part
-            const uint16_t* row = (const uint16_t*)a.nbr + s_off[wave][ks];
+            const uint16_t* row = (const uint16_t*)a.nbr + __shfl(own_off, ks, 64);
             for (int t0 = kPrefetch + sub; t0 - sub < cmax; t0 += 8 * U) {
                 uint32_t e[U];
 #pragma unroll
@@ -644,13 +700,14 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (t0 - sub + u * 8 < cmax) pair(s_nb[e[u]], li, fx, fy, fz);
+                    if (t0 - sub + u * 8 < cmax) pair(nb(e[u]), li, fx, fy, fz);
             }
         }
-        fx = __shfl(group8_sum(fx), sub << 3, 64);
-        fy = __shfl(group8_sum(fy), sub << 3, 64);
-        fz = __shfl(group8_sum(fz), sub << 3, 64);
-        if (grp == r) {
+        const int src = (pr & 7) << 3;
+        fx = __shfl(group8_sum(fx), src, 64);
+        fy = __shfl(group8_sum(fy), src, 64);
+        fz = __shfl(group8_sum(fz), src, 64);
+        if ((pr >> 3) == r) {
             kfx = fx;
             kfy = fy;
             kfz = fz;

@@ -42,11 +42,12 @@ constexpr int kCodeShift = 27;
 #define MD_TILE_BLOCK 256
 #endif
 #ifndef MD_TILE_KEYS
-#define MD_TILE_KEYS 180
+#define MD_TILE_KEYS 200
 #endif
 constexpr int kTileBlock = MD_TILE_BLOCK;     // threads of the tiled force kernel (one block per tile)
 constexpr int kTileKeys = MD_TILE_KEYS;       // target keys per tile (automatic tile length)
-constexpr int kTileMaxStage = 3500;      // staged particles per tile: 16-bit entries, under 64 KB of LDS with the rest
+constexpr int kTileMaxStage = 3500;      // staged particles per tile: 16-bit byte offsets, under 64 KB of LDS
+static_assert((kTileMaxStage + 1) * 16 < 65536, "tiled entries are 16-bit byte offsets");
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

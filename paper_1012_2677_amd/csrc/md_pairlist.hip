@@ -69,13 +69,24 @@ __device__ __forceinline__ void write_row(const BuildArgs& a, int32_t kslot, int
 constexpr int kMaxOwn = 64;     // own-cell particles kept in LDS for the key loop
 
 // Tiled (16-bit) rows start at even entries, so the force pass can read two
-// entries with one 32-bit load; slot-entry rows are packed.
+// entries with one 32-bit load; the entry after a row of odd length holds the
+// tile's stand-in partner.  Slot-entry rows are packed.
 template <typename E>
 __device__ __forceinline__ uint32_t row_start(uint32_t end)
 {
     return sizeof(E) == 2 ? (end + 1u) & ~1u : end;
 }
+
 constexpr int kRowBuf = 1024;   // entries of one cell's rows staged in LDS before the block is written
+
+template <typename E>
+__device__ __forceinline__ void pad_row(E* blk, uint32_t stride, uint32_t* s_rows, uint32_t end, uint32_t pad)
+{
+    if (sizeof(E) == 2 && (end & 1u) && lane_id() == 0) {
+        if (end < (uint32_t)kRowBuf) s_rows[end] = pad;
+        else if (end < stride) blk[end] = (E)pad;
+    }
+}
 
 // Keys of one cell against candidates held in registers (at most NCH*64).
 // Empty candidate slots carry NaN coordinates, so r2 < rs2 fails for them in
@@ -141,7 +152,8 @@ template <bool MINIMG, int NCH, typename E>
 __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* blk, uint32_t stride,
                                                        int T, int own_pref, int own_cnt, const double4* s_key,
                                                        const double* cx, const double* cy, const double* cz,
-                                                       const uint32_t* meta, uint32_t* s_rows, uint32_t* s_rowend)
+                                                       const uint32_t* meta, uint32_t* s_rows, uint32_t* s_rowend,
+                                                       uint32_t pad)
 {
     uint32_t used = 0;
     for (int kk = 0; kk < own_cnt; ++kk) {
@@ -151,6 +163,7 @@ __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* b
             used = row_chunks<MINIMG, NCH, E>(a, blk, stride, T, s_key[kk], own_pref + kk, used, cx, cy, cz,
                                               meta, s_rows);
         if (lane_id() == 0) s_rowend[kk] = used;
+        pad_row<E>(blk, stride, s_rows, used, pad);
         used = row_start<E>(used);
     }
     __syncthreads();
@@ -170,7 +183,8 @@ __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* b
 // liquid densities, kept for generality).
 template <bool MINIMG, typename E>
 __device__ uint32_t rows_from_memory(const BuildArgs& a, E* blk, uint32_t stride, int T, int own_start,
-                                     int own_cnt, const int* s_pref, const int* s_nstart, const int* s_lbase)
+                                     int own_cnt, const int* s_pref, const int* s_nstart, const int* s_lbase,
+                                     uint32_t pad)
 {
     uint32_t used = 0;
     for (int kk = 0; kk < own_cnt; ++kk) {
@@ -190,14 +204,18 @@ __device__ uint32_t rows_from_memory(const BuildArgs& a, E* blk, uint32_t stride
                 const double4 p = a.pos[slot];
                 const double r2 = pair_r2<MINIMG>(a, p.x, p.y, p.z, kp.x, kp.y, kp.z);
                 pass = r2 < a.rs2 && slot != kslot;
-                meta = s_lbase ? (uint32_t)(s_lbase[q] + (t - s_pref[q])) : (uint32_t)slot | ((uint32_t)q << kCodeShift);
+                meta = s_lbase ? (uint32_t)(s_lbase[q] + (t - s_pref[q])) << 4
+                               : (uint32_t)slot | ((uint32_t)q << kCodeShift);
             }
             const uint64_t m = __ballot(pass);
             const uint32_t w = used + wpos + mbcnt64(m);
             if (pass && w < stride) blk[w] = (E)meta;
             wpos += (uint32_t)__popcll(m);
         }
-        if (lane_id() == 0) write_row(a, kslot, (int64_t)(blk - (E*)a.nbr), used, wpos);
+        if (lane_id() == 0) {
+            write_row(a, kslot, (int64_t)(blk - (E*)a.nbr), used, wpos);
+            if (sizeof(E) == 2 && ((used + wpos) & 1u) && used + wpos < stride) blk[used + wpos] = (E)pad;
+        }
         used = row_start<E>(used + wpos);
     }
     return used;
@@ -221,6 +239,14 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     __shared__ uint32_t s_rows[kRowBuf + 1];   // + a spare word for lanes that store nothing
     __shared__ uint32_t s_rowend[kMaxOwn];
     __shared__ int s_lbase[27];
+    __shared__ uint32_t s_pad;
+    // tiled: the tile's 9 column runs (lanes 0..8), loaded together with the
+    // neighbour cells below
+    const int z0 = TILED ? (cz / a.tc) * a.tc : 0, z1 = TILED ? min(z0 + a.tc, nz) : 0;
+    TileRun run = {0, 0, 0, 0};
+    if (TILED && lane < 9)
+        run = tile_run(a.start, a.count, wrap_cell(cx + lane / 3 - 1, nx), wrap_cell(cy + lane % 3 - 1, ny), ny, nz,
+                       z0, z1);
     int cnt = 0, st = 0;
     if (lane < 27) {
         int ax = cx + lane / 9 - 1, ay = cy + (lane / 3) % 3 - 1, az = cz + lane % 3 - 1;
@@ -246,16 +272,11 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     }
     if (lane == 0) s_pref[0] = 0;
     if (TILED) {
-        // the tile's staged layout: the 9 column runs (lanes 0..8), their
-        // bases (exclusive prefix of the run lengths), then the staged index of
+        // the tile's staged layout: the bases of the 9 column runs (exclusive
+        // prefix of the run lengths), then the staged index of
         // the first particle of each neighbour cell q (lanes 0..26; q / 3 is
         // the column of q)
-        const int z0 = (cz / a.tc) * a.tc, z1 = min(z0 + a.tc, nz);
         const int jw = tile_jw(z0, z1, nz);
-        TileRun run = {0, 0, 0, 0};
-        if (lane < 9)
-            run = tile_run(a.start, a.count, wrap_cell(cx + lane / 3 - 1, nx), wrap_cell(cy + lane % 3 - 1, ny), ny,
-                           nz, z0, z1);
         const int len = lane < 9 ? run.lenA + run.lenB : 0;
         int inc = len;
 #pragma unroll
@@ -271,11 +292,15 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
             const int j = cz + lane % 3 - 1 - z0 + 1;
             s_lbase[lane] = cbase + (j < jw ? st - sA : lenA + st - sB);
         }
-        if (lane == 0 && cz == z0) atomicMax(a.tile_max, (unsigned long long)total);
+        if (lane == 0) {
+            s_pad = (uint32_t)total << 4;   // the stand-in partner of the force pass
+            if (cz == z0) atomicMax(a.tile_max, (unsigned long long)total);
+        }
     }
     __syncthreads();
 
     const int T = s_pref[27];
+    const uint32_t pad = TILED ? s_pad : 0u;
     const int own_pref = s_pref[13];
     const int own_start = s_nstart[13];
     const int own_cnt = s_pref[14] - own_pref;
@@ -313,19 +338,20 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
             px[ch] = ok ? p.x : qnan;
             py[ch] = ok ? p.y : qnan;
             pz[ch] = ok ? p.z : qnan;
-            meta[ch] = TILED ? (uint32_t)(s_lbase[lo] + (tt - s_pref[lo])) : (uint32_t)slot | ((uint32_t)lo << kCodeShift);
+            meta[ch] = TILED ? (uint32_t)(s_lbase[lo] + (tt - s_pref[lo])) << 4
+                             : (uint32_t)slot | ((uint32_t)lo << kCodeShift);
             const int k = t - own_pref;
             if (ok && k >= 0 && k < own_cnt) s_key[k] = make_double4(p.x, p.y, p.z, __longlong_as_double((long long)slot));
         }
         __syncthreads();
         used = minimg ? rows_from_registers<true, NCH, E>(a, blk, stride, T, own_pref, own_cnt, s_key, px, py, pz,
-                                                          meta, s_rows, s_rowend)
+                                                          meta, s_rows, s_rowend, pad)
                       : rows_from_registers<false, NCH, E>(a, blk, stride, T, own_pref, own_cnt, s_key, px, py,
-                                                           pz, meta, s_rows, s_rowend);
+                                                           pz, meta, s_rows, s_rowend, pad);
     } else if (own_cnt > 0) {
         const int* lb = TILED ? s_lbase : nullptr;
-        used = minimg ? rows_from_memory<true, E>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart, lb)
-                      : rows_from_memory<false, E>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart, lb);
+        used = minimg ? rows_from_memory<true, E>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart, lb, pad)
+                      : rows_from_memory<false, E>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart, lb, pad);
     }
     if (lane == 0) {
         a.cell_rows[c] = used > 0x7FFFFFFFu ? 0x7FFFFFFF : (int32_t)used;

@@ -136,8 +136,8 @@ def _wrap(z, n):
 
 
 def tile_slots(start, count, nc, tc, key_cell_xyz, entries):
-    """Partner slots of tiled entries (16-bit indices into the staged
-    neighbourhood of the key's tile), decoded on the host from the layout the
+    """Partner slots of tiled entries (16-bit byte offsets, 16 per particle,
+    into the staged neighbourhood of the key's tile), decoded on the host from the layout the
     C header states: tiles of tc cells along z; a tile's neighbourhood lists
     the runs of cells z0-1 .. z1 (periodic) of the 9 columns (cx+sx, cy+sy),
     column (sx+1)*3 + (sy+1) after column, each run in z order from z0-1.
@@ -161,7 +161,8 @@ def tile_slots(start, count, nc, tc, key_cell_xyz, entries):
                     slots.extend(range(int(start[cell]), int(start[cell]) + int(count[cell])))
                 pieces.extend(slots)
             cache[key] = np.asarray(pieces, np.int64)
-        out[i] = cache[key][e]
+        assert e % 16 == 0, e
+        out[i] = cache[key][e // 16]
     return out
 
 
