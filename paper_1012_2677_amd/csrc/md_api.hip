@@ -125,9 +125,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 //   [0], [1]  cell-grid error flags         [2]  md_forces non-finite flag
 //   [4]       large-displacement members    [5]  large-displacement violation
 //   [6]       largest squared displacement (md_ldc_check)
-//   [8]       largest staged neighbourhood of a tile (tiled list build)
 //   [16..31]  flags gathered for one read-back (layout in k_gather_flags)
-constexpr int kScalTileMax = 8;
 constexpr int kScalOut = 16;
 
 WsLayout ws_layout(const Geo& g, int64_t ldc_max)
@@ -149,6 +147,7 @@ WsLayout ws_layout(const Geo& g, int64_t ldc_max)
     L.red = off;       off = align256(off + sizeof(int64_t) * 2 * 1024);
     L.ldc = off;       off = align256(off + sizeof(int32_t) * (size_t)(ldc_max > 0 ? ldc_max : 1));
     L.scal = off;      off = align256(off + sizeof(int64_t) * 32);
+    L.tmax = off;      off = align256(off + sizeof(int64_t) * kTileMaxSlots);
     L.total = off;
     return L;
 }
@@ -432,11 +431,11 @@ static int read_flags(const Ctx& c, md_state* st, hipStream_t s, int64_t out[16]
 // else slot entries.
 static int build_list(const Ctx& c, const md_params* p, md_state* st, bool tiled, Timer& T, hipStream_t s)
 {
-    int64_t* scal = (int64_t*)((char*)st->ws + c.W.scal);
-    if (tiled) MD_HIP(launch_fill_i32((int32_t*)(scal + kScalTileMax), 0, 2, s), "rebuild/tile-max");
+    int64_t* tmax = (int64_t*)((char*)st->ws + c.W.tmax);
+    if (tiled) MD_HIP(launch_fill_i32((int32_t*)tmax, 0, 2 * kTileMaxSlots, s), "rebuild/tile-max");
     tick(T, MD_T_BUILD, 0, s);
     MD_HIP(launch_build(c.g, p->rs, st->pos, st->cells, st->list, st->ws, c.W, tiled,
-                        (unsigned long long*)(scal + kScalTileMax), s),
+                        (unsigned long long*)tmax, s),
            "rebuild/build");
     tick(T, MD_T_BUILD, 1, s);
     st->list_tiled = tiled ? 1 : 0;
@@ -508,7 +507,9 @@ static TileIo tile_io(const md_state* st)
 static int read_flags(const Ctx& c, md_state* st, hipStream_t s, int64_t out[16])
 {
     int64_t* scal = (int64_t*)((char*)st->ws + c.W.scal);
-    MD_HIP(launch_gather_flags(st->list.status, scal, st->flags, st->energy, scal + kScalOut, s), "flags/gather");
+    MD_HIP(launch_gather_flags(st->list.status, scal, st->flags, st->energy, (const int64_t*)((char*)st->ws + c.W.tmax),
+                               scal + kScalOut, s),
+           "flags/gather");
     int64_t local[16];
     int64_t* dst = st->host_scratch ? st->host_scratch : local;
     MD_HIP(hipMemcpyAsync(dst, scal + kScalOut, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, s), "flags/copy");

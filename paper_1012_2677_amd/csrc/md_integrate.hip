@@ -310,8 +310,13 @@ hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t* s
 
 __global__ void k_gather_flags(const int64_t* __restrict__ status, const int64_t* __restrict__ err,
                                const int64_t* __restrict__ flags, const double* __restrict__ energy,
-                               int64_t* __restrict__ out)
+                               const int64_t* __restrict__ tmax, int64_t* __restrict__ out)
 {
+    // largest staged tile neighbourhood: a wave-wide max over the slots
+    int64_t m = 0;
+    for (int k = threadIdx.x; k < kTileMaxSlots; k += 64) m = max(m, tmax[k]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (int64_t)__shfl_xor((long long)m, o, 64));
     if (threadIdx.x != 0) return;
     out[0] = status[0];
     out[1] = status[1];
@@ -324,13 +329,13 @@ __global__ void k_gather_flags(const int64_t* __restrict__ status, const int64_t
     out[8] = __double_as_longlong(energy[5]);
     out[9] = err[4];    // large-displacement check: member count
     out[10] = err[5];   // large-displacement check: violation flag
-    out[11] = err[8];   // tiled list: largest staged neighbourhood of a tile
+    out[11] = m;        // tiled list: largest staged neighbourhood of a tile
 }
 
 hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags,
-                               const double* energy, int64_t* out, hipStream_t s)
+                               const double* energy, const int64_t* tmax, int64_t* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_flags, dim3(1), dim3(64), 0, s, status, err, flags, energy, out);
+    hipLaunchKernelGGL(k_gather_flags, dim3(1), dim3(64), 0, s, status, err, flags, energy, tmax, out);
     return hipGetLastError();
 }
 

@@ -48,6 +48,7 @@ constexpr int kTileBlock = MD_TILE_BLOCK;     // threads of the tiled force kern
 constexpr int kTileKeys = MD_TILE_KEYS;       // target keys per tile (automatic tile length)
 constexpr int kTileMaxStage = 3500;      // staged particles per tile: 16-bit byte offsets, under 64 KB of LDS
 static_assert((kTileMaxStage + 1) * 16 < 65536, "tiled entries are 16-bit byte offsets");
+constexpr int kTileMaxSlots = 256;
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -100,6 +101,7 @@ struct WsLayout {
     size_t red;        // int64[2*1024]  partials of the list statistics
     size_t ldc;        // int32[ldc_max] members of the large-displacement check
     size_t scal;       // int64[32]      small device scalars (layout in md_api.hip)
+    size_t tmax;       // int64[kTileMaxSlots]  largest staged tile neighbourhood, spread over slots
     size_t total;
     int64_t nbs;       // scan blocks
     int64_t nbf;       // force-kernel blocks
@@ -209,7 +211,8 @@ hipError_t launch_ref_copy(const Geo& g, const double* pos, const int32_t* cell_
 // md_pairlist.hip
 // tiled: write 16-bit entries that index the staged copy of the key's tile
 // (slots must be in cell order); the largest staged count of any tile goes to
-// tile_max (atomic max).
+// tile_max[0 .. kTileMaxSlots) (atomic max into slot tile % kTileMaxSlots, so
+// that the atomics do not all meet at one address).
 hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cells& cells,
                         const md_pairlist& list, void* ws, const WsLayout& L, bool tiled,
                         unsigned long long* tile_max, hipStream_t s);
@@ -285,7 +288,7 @@ hipError_t launch_reduce_energy(const double* part_pw, int64_t nbf, const double
 hipError_t launch_reduce_pair(const double* part, int64_t nb, double scale0, double scale1,
                               double* out2, hipStream_t s, bool accumulate = false);
 hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags,
-                               const double* energy, int64_t* out, hipStream_t s);
+                               const double* energy, const int64_t* tmax, int64_t* out, hipStream_t s);
 hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t* status, long long* part,
                              hipStream_t s);
 

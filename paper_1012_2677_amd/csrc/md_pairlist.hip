@@ -169,7 +169,17 @@ __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* b
     __syncthreads();
     // the staged part of the block, then the row headers, with full-wave stores
     const uint32_t staged = min(min(used, (uint32_t)kRowBuf), stride);
-    for (uint32_t t = lane_id(); t < staged; t += 64) blk[t] = (E)s_rows[t];
+    if (sizeof(E) == 2) {
+        // two 16-bit entries per 32-bit store (rows start at even entries, the
+        // block base is 4-byte aligned and staged is even)
+        uint32_t* blk2 = (uint32_t*)blk;
+        for (uint32_t t = lane_id(); 2 * t < staged; t += 64) {
+            const uint2 v = *(const uint2*)(s_rows + 2 * t);
+            blk2[t] = (v.x & 0xFFFFu) | (v.y << 16);
+        }
+    } else {
+        for (uint32_t t = lane_id(); t < staged; t += 64) blk[t] = (E)s_rows[t];
+    }
     const int kk = (int)lane_id();
     if (kk < own_cnt) {
         const uint32_t end = s_rowend[kk], beg = kk > 0 ? row_start<E>(s_rowend[kk - 1]) : 0u;
@@ -236,7 +246,7 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     __shared__ int s_nstart[27];
     __shared__ int s_pref[28];
     __shared__ double4 s_key[kMaxOwn];
-    __shared__ uint32_t s_rows[kRowBuf + 1];   // + a spare word for lanes that store nothing
+    __shared__ __align__(8) uint32_t s_rows[kRowBuf + 2];   // + a spare word for lanes that store nothing
     __shared__ uint32_t s_rowend[kMaxOwn];
     __shared__ int s_lbase[27];
     __shared__ uint32_t s_pad;
@@ -294,7 +304,10 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
         }
         if (lane == 0) {
             s_pad = (uint32_t)total << 4;   // the stand-in partner of the force pass
-            if (cz == z0) atomicMax(a.tile_max, (unsigned long long)total);
+            if (cz == z0) {
+                const int64_t tile = ((int64_t)cx * ny + cy) * ((nz + a.tc - 1) / a.tc) + cz / a.tc;
+                atomicMax(a.tile_max + (tile & (kTileMaxSlots - 1)), (unsigned long long)total);
+            }
         }
     }
     __syncthreads();
