@@ -83,18 +83,19 @@ extern "C" {
  *   ldc_max: the most particles the large-displacement check takes (N_l of
  *   the algorithm); more invalidate the list outright.  0 <= ldc_max <= 2^22.
  *   list_layout: how md_prepare / md_step / md_energy store the state's list.
- *   MD_LIST_AUTO: in MD_MIXED, whenever the slots are in cell order (after a
- *   re-sort), the list's cell_stride is even and every tile's neighbourhood
- *   fits, the tiled layout: the cells
+ *   MD_LIST_AUTO: whenever the slots are in cell order (after a re-sort), the
+ *   list's cell_stride is even and every tile's neighbourhood fits (3500
+ *   particles in MD_MIXED, 1950 in MD_FP64), the tiled layout: the cells
  *   are cut into tiles of tile_cells consecutive cells along z, and an entry
  *   is 16 times the index of the partner in the tile's neighbourhood (its
  *   byte offset in the copy of the runs of cells around the tile in the 9
- *   columns next to it, which the force pass stages in LDS, 16 bytes per
- *   particle); otherwise, and always with MD_LIST_SLOTS, entries are
+ *   columns next to it, which the force pass stages in LDS: 16 bytes per
+ *   particle in MD_MIXED, 32 in MD_FP64, where the offset is twice the
+ *   entry); otherwise, and always with MD_LIST_SLOTS, entries are
  *   32-bit partner slots as in md_build_pairlist.  Both layouts hold the same
  *   pairs in the same row order.
- *   tile_cells: cells per tile along z (0 = about 224 keys per tile at the
- *   mean density); clipped to [1, nz - 2]. */
+ *   tile_cells: cells per tile along z (0 = about 200 keys per tile at the
+ *   mean density in MD_MIXED, 135 in MD_FP64); clipped to [1, nz - 2]. */
 typedef struct md_params {
     int64_t n;
     double  box[3];

@@ -80,10 +80,11 @@ Geo make_geo(const md_params& p, const int32_t nc[3])
     int tc = p.tile_cells;
     if (tc == 0) {
         const double mean = (double)p.n / (double)g.ncell;
-        tc = (int)std::lround((double)kTileKeys / (mean > 1e-9 ? mean : 1e-9));
+        const int keys = p.precision == MD_MIXED ? kTileKeys : kTileKeys64;
+        tc = (int)std::lround((double)keys / (mean > 1e-9 ? mean : 1e-9));
     }
     tc = std::max(1, std::min(tc, nz - 2));
-    const bool tiles = p.precision == MD_MIXED && p.list_layout == MD_LIST_AUTO;
+    const bool tiles = p.list_layout == MD_LIST_AUTO;
     g.tc = tiles ? tc : 0;
     g.nt = tiles ? (int32_t)ceil_div(nz, tc) : 0;
     g.ntile = tiles ? (int64_t)nc[0] * nc[1] * g.nt : 0;
@@ -135,13 +136,14 @@ WsLayout ws_layout(const Geo& g, int64_t ldc_max)
     L.nbs = ceil_div(ncell, kScanItems);
     L.nbf = ceil_div(n, kKeysPerBlock);
     const int64_t np = std::max(pair_blocks(g), g.ntile);
-    L.nbf = std::max(L.nbf, g.ntile);
     L.nbi = ceil_div(n, kStreamBlock);
     size_t off = 0;
     L.rank = off;      off = align256(off + sizeof(int32_t) * (size_t)n);
     L.bsum = off;      off = align256(off + sizeof(int32_t) * (size_t)(L.nbs + 1));
     L.cell_rows = off; off = align256(off + sizeof(int32_t) * (size_t)ncell);
-    L.part_a = off;    off = align256(off + sizeof(double) * 2 * (size_t)L.nbf);
+    // (PE, W) partials of the adjoint kernels (nbf blocks) or of a force pass
+    // (one per block or tile)
+    L.part_a = off;    off = align256(off + sizeof(double) * 2 * (size_t)std::max(L.nbf, np));
     L.part_b = off;    off = align256(off + sizeof(double) * (size_t)(np > L.nbi ? np : L.nbi));
     L.pos32 = off;     off = align256(off + 16 * (size_t)n);
     L.red = off;       off = align256(off + sizeof(int64_t) * 2 * 1024);
@@ -480,7 +482,7 @@ static int rebuild(const Ctx& c, const md_params* p, md_state* st, bool allow_re
     if (rc != MD_OK) return rc;
     if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
     if (st->list_tiled) {
-        if (f[11] > kTileMaxStage) {
+        if (f[11] > tile_stage_cap(p->precision)) {
             timer_collect(T);
             if ((rc = build_list(c, p, st, false, T, s)) != MD_OK) return rc;
             if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;

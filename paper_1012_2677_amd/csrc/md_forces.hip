@@ -495,26 +495,53 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed
     if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE, VMAX>(a, blk, pe, w, ke, d2, v2);
 }
 
-// Tiled force pass (mixed): one block per tile of tc cells along z.  The block
-// first copies the tile's neighbourhood (the runs of cells z0-1 .. z1 of the
-// 9 columns around it, in the order of the list build) from the local
-// coordinates into LDS, each particle as (x + sx cs_x, y + sy cs_y, z, j)
-// with (sx, sy) its column offset and j its position in the run; entries are
-// 16-bit indices into that copy.  With the key's (x, y, z) local and its own
-// run position jk, d = (x_j - x_i, y_j - y_i, (z_j - z_i) + (j - jk) cs_z),
-// the last term exact ((j - jk) is -1, 0 or 1).  The row walk, group sums and
-// integrator epilogue are those of k_pairs_mixed; partners come from LDS
-// instead of global gathers.
+// Tiled force pass: one block per tile of tc cells along z.  The block first
+// copies the tile's neighbourhood (the runs of cells z0-1 .. z1 of the 9
+// columns around it, in the order of the list build) into LDS; entries are
+// 16-bit byte offsets into that copy (16 bytes per particle) and a row of odd
+// length ends with a stand-in partner beyond the cutoff.
+//   Mixed: each particle is staged from its local coordinates as
+//   (x + sx cs_x, y + sy cs_y, z, j) with (sx, sy) its column offset and j its
+//   position in the run.  With the key's (x, y, z) local and its own run
+//   position jk, d = (x_j - x_i, y_j - y_i, (z_j - z_i) + (j - jk) cs_z), the
+//   last term exact ((j - jk) is -1, 0 or 1).
+//   FP64: particles are staged as their FP64 positions (32 bytes, the entry
+//   doubled), and displacements take the minimum image in tiles that touch
+//   the box boundary (a no-op for pairs that do not wrap), as in k_pairs_fp64.
+// The tile's keys are split evenly over the waves.  In each 64-key chunk the
+// rows are walked in rounds of 8 keys grouped by row length, the first
+// kPrefetch entries of all 8 rounds loaded up front, two per 32-bit load.  Key
+// data reach the round's lanes by shuffles; group sums and the integrator
+// epilogue are those of the other pair kernels.
 #ifndef MD_TILE_PREFETCH
 #define MD_TILE_PREFETCH 64
 #endif
 constexpr int kPrefetch = MD_TILE_PREFETCH;     // row entries per key loaded up front (multiple of 16)
 
-template <int U, bool ENERGY, int MODE, bool VMAX>
+template <bool MIXED>
+struct TileT;
+template <>
+struct TileT<true> {
+    using R = float;
+    using V4 = float4;
+    static constexpr int kScale = 1;   // entry -> byte offset
+};
+template <>
+struct TileT<false> {
+    using R = double;
+    using V4 = double4;
+    static constexpr int kScale = 2;
+};
+
+template <int U, bool ENERGY, int MODE, bool VMAX, bool MIXED>
 __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(PairArgs a)
 {
+    using R = typename TileT<MIXED>::R;
+    using V4 = typename TileT<MIXED>::V4;
+    constexpr int SC = TileT<MIXED>::kScale;
     constexpr int NW = kTileBlock / 64;
-    extern __shared__ float4 s_nb[];      // staged neighbourhood, then one stand-in
+    extern __shared__ float4 s_lds[];     // staged neighbourhood, then one stand-in
+    V4* s_nb = (V4*)s_lds;
     __shared__ uint8_t s_perm[NW][64];
     __shared__ int32_t s_run[9][4];
     __shared__ int32_t s_base[10];
@@ -525,6 +552,10 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     const int cy = (int)(cxy % ny), cx = (int)(cxy / ny);
     const int z0 = tz * a.tc, z1 = min(z0 + a.tc, nz);
     const int tid = threadIdx.x;
+    // FP64: the tile's pairs need minimum images only when it touches the box
+    // boundary (or when some axis has fewer than 5 cells)
+    const bool minimg = !MIXED && (a.exact_all || cx == 0 || cx == nx - 1 || cy == 0 || cy == ny - 1 || z0 == 0 ||
+                                   z1 == nz);
     if (tid < 9) {
         const TileRun r = tile_run(a.start, a.count, wrap_cell(cx + tid / 3 - 1, nx), wrap_cell(cy + tid % 3 - 1, ny),
                                    ny, nz, z0, z1);
@@ -541,34 +572,56 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
             b += s_run[col][1] + s_run[col][3];
         }
         s_base[9] = b;
-        s_nb[b] = make_float4(1.0e3f, 0.0f, 0.0f, 0.0f);   // stand-in partner, far beyond the cutoff
+        // stand-in partner beyond the cutoff of every key of the tile: in mixed
+        // mode far outside the cell frame; in FP64 half a box away from the
+        // tile's column in x, which the minimum image leaves at least
+        // L/2 - cs/2 >= cs >= rs away
+        if constexpr (MIXED) {
+            s_nb[b] = make_float4(1.0e3f, 0.0f, 0.0f, 0.0f);
+        } else {
+            double x = ((double)cx + 0.5) * a.cs[0] + 0.5 * a.L[0];
+            x -= x >= a.L[0] ? a.L[0] : 0.0;
+            s_nb[b] = make_double4(x, ((double)cy + 0.5) * a.cs[1], ((double)z0 + 0.5) * a.cs[2], 0.0);
+        }
     }
     __syncthreads();
-    const float csx = (float)a.cs[0], csy = (float)a.cs[1], csz = (float)a.cs[2];
+    const float csx = (float)a.cs[0], csy = (float)a.cs[1];
+    const R csz = (R)a.cs[2];
     {
         // every thread takes elements tid and tid + kTileBlock of each column
-        // run (the loads of all 9 columns in flight together), then writes them
-        // shifted by the column offset and tagged with their run position;
-        // longer runs finish in a plain loop
-        float4 p[9][2];
+        // run (the loads of all 9 columns in flight together), then writes
+        // them (mixed: shifted by the column offset and tagged with their run
+        // position); longer runs finish in a plain loop
+        V4 p[9][2];
+        auto src_of = [&](int col, int i) {
+            const int lenA = s_run[col][1];
+            return i < lenA ? s_run[col][0] + i : s_run[col][2] + (i - lenA);
+        };
+        auto load = [&](int slot) -> V4 {
+            if constexpr (MIXED) return a.pos32[slot];
+            else return a.pos[slot];
+        };
+        auto put = [&](const V4& q, int col, int i) {
+            if constexpr (MIXED) {
+                int j = ((__float_as_int(q.w) >> 20) & 1023) - z0 + 1;
+                j += j < 0 ? nz : 0;
+                j -= j >= nz ? nz : 0;
+                s_nb[s_base[col] + i] = make_float4(q.x + (float)(col / 3 - 1) * csx, q.y + (float)(col % 3 - 1) * csy,
+                                                    q.z, (float)j);
+            } else {
+                s_nb[s_base[col] + i] = q;
+            }
+        };
 #pragma unroll
         for (int col = 0; col < 9; ++col) {
-            const int sA = s_run[col][0], lenA = s_run[col][1], sB = s_run[col][2], len = lenA + s_run[col][3];
+            const int len = s_run[col][1] + s_run[col][3];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 // unconditional loads (slot 0 past the run's end, result unused)
                 const int i = tid + u * kTileBlock;
-                const int src = i < lenA ? sA + i : sB + (i - lenA);
-                p[col][u] = a.pos32[i < len ? src : 0];
+                p[col][u] = load(i < len ? src_of(col, i) : 0);
             }
         }
-        auto put = [&](const float4& q, int col, int i) {
-            int j = ((__float_as_int(q.w) >> 20) & 1023) - z0 + 1;
-            j += j < 0 ? nz : 0;
-            j -= j >= nz ? nz : 0;
-            s_nb[s_base[col] + i] = make_float4(q.x + (float)(col / 3 - 1) * csx, q.y + (float)(col % 3 - 1) * csy,
-                                                q.z, (float)j);
-        };
 #pragma unroll
         for (int col = 0; col < 9; ++col) {
             const int len = s_run[col][1] + s_run[col][3];
@@ -579,19 +632,50 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
             }
         }
         for (int col = 0; col < 9; ++col) {
-            const int sA = s_run[col][0], lenA = s_run[col][1], sB = s_run[col][2], len = lenA + s_run[col][3];
-            for (int i = tid + 2 * kTileBlock; i < len; i += kTileBlock)
-                put(a.pos32[i < lenA ? sA + i : sB + (i - lenA)], col, i);
+            const int len = s_run[col][1] + s_run[col][3];
+            for (int i = tid + 2 * kTileBlock; i < len; i += kTileBlock) put(load(src_of(col, i)), col, i);
         }
     }
     __syncthreads();
-    const uint32_t dummy = (uint32_t)s_base[9] << 4;   // byte offset of the stand-in partner
+    const uint32_t dummy = (uint32_t)s_base[9] << 4;   // entry of the stand-in partner
     const int64_t colc = ((int64_t)cx * ny + cy) * nz;
     const int64_t kb = a.start[colc + z0];
     const int64_t kend = (int64_t)a.start[colc + z1 - 1] + a.count[colc + z1 - 1];
     const int wave = tid >> 6, lane = tid & 63, sub = lane & 7, grp = lane >> 3;
-    const float rc2 = (float)a.lj.rc2, A = (float)a.lj.A, B = (float)a.lj.B, C8 = (float)a.lj.C8;
+    const R rc2 = (R)a.lj.rc2, A = (R)a.lj.A, B = (R)a.lj.B, C8 = (R)a.lj.C8;
     double pe = 0.0, w = 0.0, ke = 0.0, d2 = 0.0, v2 = 0.0;
+    auto nb = [&](uint32_t e) { return *(const V4*)((const char*)s_nb + SC * e); };
+    auto pair = [&](const V4& pj, const V4& li, R& fx, R& fy, R& fz) {
+        R dx = pj.x - li.x;
+        R dy = pj.y - li.y;
+        R dz;
+        if constexpr (MIXED) {
+            dz = __builtin_fmaf(pj.w - li.w, csz, pj.z - li.z);
+        } else {
+            dz = pj.z - li.z;
+            if (minimg) {
+                dx -= a.L[0] * rint(dx * a.invL[0]);
+                dy -= a.L[1] * rint(dy * a.invL[1]);
+                dz -= a.L[2] * rint(dz * a.invL[2]);
+            }
+        }
+        const R r2 = dx * dx + dy * dy + dz * dz;
+        R r2i;
+        if constexpr (MIXED) r2i = __builtin_amdgcn_rcpf(r2);
+        else r2i = rcp64(r2);
+        const R r6i = r2i * r2i * r2i;
+        R g = r2i * r6i * (A * r6i - B) - C8;
+        const bool in = r2 < rc2;
+        g = in ? g : (R)0;
+        fx -= g * dx;
+        fy -= g * dy;
+        fz -= g * dz;
+        if (ENERGY) {
+            const R V = r6i * ((R)a.lj.A4 * r6i - (R)a.lj.B4) + (R)a.lj.C2 * r2 + (R)a.lj.C0;
+            pe += in ? (double)V : 0.0;
+            w += (double)(g * r2);
+        }
+    };
     // the tile's keys split evenly over the waves, in chunks of at most 64
     // (a multiple of 8): nr rounds per chunk instead of always 8
     const int64_t nk = kend - kb;
@@ -601,15 +685,19 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     const int nr = (int)((cend - base + 7) >> 3);
     const int64_t mykey = base + lane;
     const bool myvalid = mykey < cend;
-    // the lane's own key: local coordinates with its run position in w, row
-    // offset and length; rounds fetch them from the owner lane by shuffles
-    float4 own;
+    // the lane's own key: coordinates (mixed: local, with its run position in
+    // w), row offset and length; rounds fetch them from the owner lane
+    V4 own;
     int64_t own_off;
     int own_cnt;
     {
         const int64_t k = myvalid ? mykey : kend - 1;
-        own = a.pos32[k];
-        own.w = (float)(((__float_as_int(own.w) >> 20) & 1023) - z0 + 1);
+        if constexpr (MIXED) {
+            own = a.pos32[k];
+            own.w = (float)(((__float_as_int(own.w) >> 20) & 1023) - z0 + 1);
+        } else {
+            own = a.pos[k];
+        }
         own_off = a.offsets[k];
         own_cnt = myvalid ? a.counts[k] : 0;
     }
@@ -631,10 +719,9 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         s_perm[wave][pr] = (uint8_t)lane;
     }
     __builtin_amdgcn_wave_barrier();
-    // the first kPrefetch entries of the 8 rows each lane walks, two per
-    // 32-bit load (rows start at even entries, a row of odd length ends with
-    // the stand-in): lane j of a group takes entries 2j + 16u and 2j + 16u + 1;
-    // all loads of the chunk go out at once
+    // the first kPrefetch entries of the rows each lane walks, two per 32-bit
+    // load: lane j of a group takes entries 2j + 16u and 2j + 16u + 1; all
+    // loads of the chunk go out at once
     constexpr int UP = kPrefetch / 16;
     const uint32_t dummy2 = dummy | (dummy << 16);
     uint32_t E[8][UP];
@@ -650,40 +737,23 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
             E[r][u] = t < cnt ? row2[t >> 1] : dummy2;
         }
     }
-    float kfx = 0.f, kfy = 0.f, kfz = 0.f;
-    auto pair = [&](const float4& pj, const float4& li, float& fx, float& fy, float& fz) {
-        const float dx = pj.x - li.x;
-        const float dy = pj.y - li.y;
-        const float dz = __builtin_fmaf(pj.w - li.w, csz, pj.z - li.z);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const float r2i = __builtin_amdgcn_rcpf(r2);
-        const float r6i = r2i * r2i * r2i;
-        float g = r2i * r6i * (A * r6i - B) - C8;
-        const bool in = r2 < rc2;
-        g = in ? g : 0.0f;
-        fx -= g * dx;
-        fy -= g * dy;
-        fz -= g * dz;
-        if (ENERGY) {
-            const float V = r6i * ((float)a.lj.A4 * r6i - (float)a.lj.B4) + (float)a.lj.C2 * r2 + (float)a.lj.C0;
-            pe += in ? (double)V : 0.0;
-            w += (double)(g * r2);
-        }
-    };
-    auto nb = [&](uint32_t byte) { return *(const float4*)((const char*)s_nb + byte); };
+    R kfx = 0, kfy = 0, kfz = 0;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         if (r >= nr) break;
         const int ks = s_perm[wave][(r << 3) | grp];
         const int cmax = __builtin_amdgcn_readfirstlane(group8_max(__shfl(own_cnt, s_perm[wave][(r << 3) | sub], 64)));
         const int cnt = __shfl(own_cnt, ks, 64);
-        const float4 li = make_float4(__shfl(own.x, ks, 64), __shfl(own.y, ks, 64), __shfl(own.z, ks, 64),
-                                      __shfl(own.w, ks, 64));
-        float fx = 0.f, fy = 0.f, fz = 0.f;
+        V4 li;
+        li.x = __shfl(own.x, ks, 64);
+        li.y = __shfl(own.y, ks, 64);
+        li.z = __shfl(own.z, ks, 64);
+        if constexpr (MIXED) li.w = __shfl(own.w, ks, 64);
+        R fx = 0, fy = 0, fz = 0;
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
             if (16 * u < cmax) {
-                const float4 p0 = nb(E[r][u] & 0xFFFFu), p1 = nb(E[r][u] >> 16);
+                const V4 p0 = nb(E[r][u] & 0xFFFFu), p1 = nb(E[r][u] >> 16);
                 pair(p0, li, fx, fy, fz);
                 pair(p1, li, fx, fy, fz);
             }
@@ -716,14 +786,14 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     if (myvalid) {
         if (!isfinite(kfx + kfy + kfz)) atomicOr((unsigned long long*)a.flags, 1ull);
         if (MODE != MODE_KKD) {
-            float* F = (float*)a.force;
+            R* F = (R*)a.force;
             F[mykey] = kfx;
             F[a.n + mykey] = kfy;
             F[2 * a.n + mykey] = kfz;
         }
         if (MODE != MODE_FORCE) {
             double kk = 0.0, dd = 0.0, vv = 0.0;
-            integrate_key<MODE, true, VMAX>(a, mykey, kfx, kfy, kfz, kk, dd, vv);
+            integrate_key<MODE, MIXED, VMAX>(a, mykey, kfx, kfy, kfz, kk, dd, vv);
             ke += kk;
             d2 = fmax(d2, dd);
             v2 = fmax(v2, vv);
@@ -773,9 +843,12 @@ template <bool ENERGY, int MODE, bool VMAX = false>
 static void launch_pairs_mode(const Geo& g, int precision, const PairArgs& a, hipStream_t s, int stage)
 {
     if (stage > 0) {
-        const size_t lds = sizeof(float4) * (size_t)(stage + 1);
-        hipLaunchKernelGGL((k_pairs_tiled<kForceUnroll, ENERGY, MODE, VMAX>), dim3((unsigned)g.ntile),
-                           dim3(kTileBlock), lds, s, a);
+        if (precision == MD_MIXED)
+            hipLaunchKernelGGL((k_pairs_tiled<kForceUnroll, ENERGY, MODE, VMAX, true>), dim3((unsigned)g.ntile),
+                               dim3(kTileBlock), sizeof(float4) * (size_t)(stage + 1), s, a);
+        else
+            hipLaunchKernelGGL((k_pairs_tiled<kForceUnroll64, ENERGY, MODE, VMAX, false>), dim3((unsigned)g.ntile),
+                               dim3(kTileBlock), sizeof(double4) * (size_t)(stage + 1), s, a);
         return;
     }
     const dim3 grid((unsigned)pair_blocks(g)), block(kForceBlock);
@@ -788,8 +861,7 @@ static void launch_pairs_mode(const Geo& g, int precision, const PairArgs& a, hi
 static hipError_t check_tiles(const Geo& g, int precision, const TileIo& t)
 {
     if (t.stage <= 0) return hipSuccess;
-    if (precision != MD_MIXED || g.tc <= 0 || !t.start || !t.count || t.stage > kTileMaxStage)
-        return hipErrorInvalidValue;
+    if (g.tc <= 0 || !t.start || !t.count || t.stage > tile_stage_cap(precision)) return hipErrorInvalidValue;
     return hipSuccess;
 }
 

@@ -46,8 +46,17 @@ constexpr int kCodeShift = 27;
 #endif
 constexpr int kTileBlock = MD_TILE_BLOCK;     // threads of the tiled force kernel (one block per tile)
 constexpr int kTileKeys = MD_TILE_KEYS;       // target keys per tile (automatic tile length)
+#ifndef MD_TILE_KEYS_FP64
+#define MD_TILE_KEYS_FP64 135
+#endif
+constexpr int kTileKeys64 = MD_TILE_KEYS_FP64;  // same for FP64 (32-byte staged particles)
 constexpr int kTileMaxStage = 3500;      // staged particles per tile: 16-bit byte offsets, under 64 KB of LDS
+constexpr int kTileMaxStage64 = 1950;    // FP64: 32 bytes per staged particle, under 64 KB of LDS
 static_assert((kTileMaxStage + 1) * 16 < 65536, "tiled entries are 16-bit byte offsets");
+__host__ __device__ inline int tile_stage_cap(int precision)
+{
+    return precision == MD_MIXED ? kTileMaxStage : kTileMaxStage64;
+}
 constexpr int kTileMaxSlots = 256;
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -104,7 +113,7 @@ struct WsLayout {
     size_t tmax;       // int64[kTileMaxSlots]  largest staged tile neighbourhood, spread over slots
     size_t total;
     int64_t nbs;       // scan blocks
-    int64_t nbf;       // force-kernel blocks
+    int64_t nbf;       // adjoint-kernel blocks (kKeysPerBlock keys each)
     int64_t nbi;       // streaming-kernel blocks
 };
 WsLayout ws_layout(const Geo& g, int64_t ldc_max);

@@ -3,8 +3,8 @@ times (re-sort at every rebuild; mixed precision at 32M and 131M, FP64 at 4M),
 on sampled particles the oracle can check one by one:
 
   * the pair-list rows of the sampled particles equal the oracle's neighbour
-    sets within rs (exact set equality, ids; mixed runs hold the tiled list,
-    decoded on the host);
+    sets within rs (exact set equality, ids; the tiled list, decoded on the
+    host);
   * the forces on the sampled particles equal the oracle's to the precision
     bar (1e-5 mixed, 1e-12 FP64, relative to the pair-force scale S_i);
   * the list's total entry count equals twice the number of pairs implied by
@@ -81,8 +81,8 @@ def test_full_size_sampled_parity(ref, config, precision, tol, steps):
     e.step(steps)
     assert e.rebuilds > 3
     e.prepare()
-    # mixed runs use the tiled list (the benchmark's configuration)
-    assert int(e.state.list_tiled) == (1 if precision == "mixed" else 0)
+    # the tiled list (the benchmark's configuration)
+    assert int(e.state.list_tiled) == 1
     _check_state(ref, e, L, _sample_ids(n, 2048, 1), tol)
 
 

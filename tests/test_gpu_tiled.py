@@ -1,4 +1,4 @@
-"""GPU tests of the tiled list layout of the simulation state (mixed precision).
+"""GPU tests of the tiled list layout of the simulation state (FP64 and mixed).
 
 The state's list is tiled when the slots are in cell order: entries are 16-bit
 indices into the staged neighbourhood of the key's tile, and the force pass
@@ -9,10 +9,12 @@ reads partners from LDS.  These tests check:
   * index work, bit-exact: every tiled row, decoded on the host from the
     documented layout, equals the slot-layout row of the same key entry by
     entry, and both equal the oracle's neighbour sets;
-  * forces after md_prepare against the FP64 oracle (1e-5 of the pair-force
-    scale) for several tile lengths, including tiles that wrap the box in z;
-  * a run with the tiled list tracks the FP64 oracle (energy per particle to
-    1e-5) and the slot-layout run.
+  * forces after md_prepare against the FP64 oracle (1e-12 in FP64, 1e-5 in
+    mixed, of the pair-force scale) for several tile lengths, including tiles
+    that wrap the box in z;
+  * runs with the tiled list match the oracle's run (FP64: energy log to
+    1e-10 relative, same rebuilds; mixed: energy per particle to 1e-5) and the
+    slot-layout run.
 """
 
 import numpy as np
@@ -46,24 +48,27 @@ def _jittered(n_fcc, seed, rho=0.5, amp=0.15):
 def test_layout_selection():
     q, L = li.fcc_lattice(10)
     v = li.maxwell_boltzmann(q.shape[0], seed=0)
-    e = _engine(q, v, L, precision="mixed")
-    e.prepare()
-    assert int(e.state.list_tiled) == 1
-    assert int(e.state.tile_cells) == 5          # clipped to nz - 2 with 7 cells per axis
-    assert 0 < int(e.state.tile_stage) <= 3500
-    for kw in (dict(precision="fp64"), dict(precision="mixed", resort_every=0),
-               dict(precision="mixed", list_layout="slots")):
+    for precision, cap in (("mixed", 3500), ("fp64", 1950)):
+        e = _engine(q, v, L, precision=precision)
+        e.prepare()
+        assert int(e.state.list_tiled) == 1
+        assert int(e.state.tile_cells) == 5          # clipped to nz - 2 with 7 cells per axis
+        assert 0 < int(e.state.tile_stage) <= cap
+    for kw in (dict(precision="fp64", resort_every=0), dict(precision="mixed", resort_every=0),
+               dict(precision="mixed", list_layout="slots"), dict(precision="fp64", list_layout="slots"),
+               dict(precision="mixed", cell_stride=1153)):
         f = _engine(q, v, L, **kw)
         f.prepare()
         assert int(f.state.list_tiled) == 0, kw
 
 
-@pytest.mark.parametrize("tile_cells", [0, 1, 2, 3])
-def test_tiled_rows_equal_slot_rows_and_oracle(ref, tile_cells):
+@pytest.mark.parametrize("precision,tile_cells", [("mixed", 0), ("mixed", 1), ("mixed", 2), ("mixed", 3),
+                                                  ("fp64", 0), ("fp64", 4)])
+def test_tiled_rows_equal_slot_rows_and_oracle(ref, precision, tile_cells):
     q, L = _jittered(10, seed=11)
     v = li.maxwell_boltzmann(q.shape[0], seed=11)
-    t = _engine(q, v, L, precision="mixed", tile_cells=tile_cells)
-    s = _engine(q, v, L, precision="mixed", list_layout="slots")
+    t = _engine(q, v, L, precision=precision, tile_cells=tile_cells)
+    s = _engine(q, v, L, precision=precision, list_layout="slots")
     t.prepare()
     s.prepare()
     assert int(t.state.list_tiled) == 1 and int(s.state.list_tiled) == 0
@@ -82,47 +87,63 @@ def test_tiled_rows_equal_slot_rows_and_oracle(ref, tile_cells):
         assert np.array_equal(np.sort(ids[pt[kt == k]]), rows[k])
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
 @pytest.mark.parametrize("tile_cells", [0, 1, 2, 4, 5, 1023])
-def test_tiled_forces_match_oracle(ref, tile_cells):
+def test_tiled_forces_match_oracle(ref, precision, tile_cells):
     q, L = _jittered(10, seed=3)
     v = li.maxwell_boltzmann(q.shape[0], seed=3)
-    e = _engine(q, v, L, precision="mixed", tile_cells=tile_cells)
+    e = _engine(q, v, L, precision=precision, tile_cells=tile_cells)
     e.prepare()
     assert int(e.state.list_tiled) == 1
     idx = np.arange(q.shape[0], dtype=np.int64)
     Fr, S, pe_i, w_i, _ = ref.forces_sample(e.positions(), L, idx)
-    assert G.force_error(e.forces(), Fr, S) <= 1e-5
     en = e.energies()   # per-particle shares of the oracle sum to the totals
-    assert abs(en[1] - pe_i.sum()) / q.shape[0] < 1e-5
-    assert abs(en[2] - w_i.sum()) / q.shape[0] < 1e-4
+    if precision == "fp64":
+        assert G.force_error(e.forces(), Fr, S) <= 1e-12
+        assert en[1] == pytest.approx(pe_i.sum(), rel=1e-12)
+        assert en[2] == pytest.approx(w_i.sum(), rel=1e-12)
+    else:
+        assert G.force_error(e.forces(), Fr, S) <= 1e-5
+        assert abs(en[1] - pe_i.sum()) / q.shape[0] < 1e-5
+        assert abs(en[2] - w_i.sum()) / q.shape[0] < 1e-4
 
 
-def test_tiled_run_tracks_oracle_and_slot_run(ref):
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_tiled_run_tracks_oracle_and_slot_run(ref, precision):
     q, L = li.fcc_lattice(10)
     v = li.maxwell_boltzmann(q.shape[0], T=1.0, seed=0)
-    t = _engine(q, v, L, precision="mixed")
-    s = _engine(q, v, L, precision="mixed", list_layout="slots")
+    t = _engine(q, v, L, precision=precision)
+    s = _engine(q, v, L, precision=precision, list_layout="slots")
     lt = t.step(100, sample_every=10)
     ls = s.step(100, sample_every=10)
     assert int(t.state.list_tiled) == 1
-    _, _, rlog, rreb = ref.run(q, v, L, 100, dt=0.005, sample_every=10)
+    rq, _, rlog, rreb = ref.run(q, v, L, 100, dt=0.005, sample_every=10)
     n = q.shape[0]
-    for log in (lt, ls):
-        assert np.abs(log[:, 3] - rlog[:, 3]).max() / n < 1e-5
-        assert np.abs(log[:, 1] - rlog[:, 1]).max() / n < 1e-5
-    assert np.abs(lt - ls).max() / n < 1e-5
+    if precision == "fp64":
+        for log in (lt, ls):
+            assert np.abs(log - rlog).max() <= 1e-10 * np.abs(rlog).max()
+        d = t.positions() - rq
+        assert np.abs(d - L * np.rint(d / L)).max() < 1e-8
+        assert t.rebuilds - 1 == rreb
+    else:
+        for log in (lt, ls):
+            assert np.abs(log[:, 3] - rlog[:, 3]).max() / n < 1e-5
+            assert np.abs(log[:, 1] - rlog[:, 1]).max() / n < 1e-5
+        assert np.abs(lt - ls).max() / n < 1e-5
     assert t.rebuilds == s.rebuilds
 
 
-def test_oversized_tiles_fall_back_to_slot_entries(ref):
+@pytest.mark.parametrize("precision,tile_cells", [("mixed", 18), ("fp64", 10)])
+def test_oversized_tiles_fall_back_to_slot_entries(ref, precision, tile_cells):
     # a dense solid (rho = 1) with long tiles: the staged neighbourhood of a
-    # tile (~9 * 20 cells * 23 particles) exceeds what the force pass stages
+    # tile (~9 * (tile_cells + 2) cells * 23 particles) exceeds what the force
+    # pass stages (3500 particles in mixed, 1950 in FP64)
     q, L = li.fcc_lattice(36, rho=1.0)
     v = li.maxwell_boltzmann(q.shape[0], T=0.2, seed=1)
-    e = _engine(q, v, L, precision="mixed", tile_cells=18)
+    e = _engine(q, v, L, precision=precision, tile_cells=tile_cells)
     e.prepare()
     assert int(e.state.list_tiled) == 0
     e.step(5)
     idx = np.random.default_rng(0).choice(q.shape[0], 300, replace=False).astype(np.int64)
     Fr, S, _, _, _ = ref.forces_sample(e.positions(), L, idx)
-    assert G.force_error(e.forces()[idx], Fr, S) <= 1e-5
+    assert G.force_error(e.forces()[idx], Fr, S) <= (1e-12 if precision == "fp64" else 1e-5)
