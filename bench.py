@@ -41,21 +41,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def force_bytes_per_key(mean_entries: float, mixed: bool, entry_bytes: int = 4) -> float:
+def force_bytes_per_key(mean_entries: float, mixed: bool, tiled: bool = False) -> float:
     """Algorithmic HBM bytes of one key in the timed force pass, which inside a
     run is fused with the integrator (second half kick, next first half kick,
-    drift): row offset (8) + row length (4) + entry_bytes per list entry (4 for
-    slot entries, 2 for the tiled list) + the
-    key's own coordinates (FP32 local 16 B in mixed mode; FP64 32 B plus its
-    4 B packed cell in FP64 mode) + the integrator's streams: velocity read and
+    drift): row offset (8) + row length (4) + 4 bytes per slot entry or 2 per
+    tiled entry + the
+    key's own coordinates (FP32 local 16 B in mixed mode; FP64 32 B in FP64
+    mode, plus its 4 B packed cell with slot entries) + the integrator's streams: velocity read and
     write (48), reference position (24), position written (32; mixed mode also
     reads the FP64 position, 32, its packed cell, 4, and writes new local
     coordinates, 16).  Partner coordinates are re-reads of coordinates counted
     once as keys (in the tiled pass: staged into LDS from the same array)."""
-    idx = 8 + 4 + entry_bytes * mean_entries
+    idx = 8 + 4 + (2 if tiled else 4) * mean_entries
     if mixed:
         return idx + 16 + 32 + 4 + 48 + 24 + 32 + 16
-    return idx + 32 + 4 + 48 + 24 + 32
+    return idx + 32 + (0 if tiled else 4) + 48 + 24 + 32
 
 
 def force_sources_sha256() -> str:
@@ -193,7 +193,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
     fm, fl = tim.get("force", (0.0, 0))
     if fl > 0:
         avg_ms = fm / fl
-        per_launch = n * force_bytes_per_key(entries / n, precision == "mixed", 2 if tiled else 4)
+        per_launch = n * force_bytes_per_key(entries / n, precision == "mixed", bool(tiled))
         gbs = per_launch / (avg_ms * 1e-3) / 1e9
         out["force_kernel"] = {"avg_ms": avg_ms, "launches": fl, "algorithmic_bytes_per_launch": per_launch,
                                "achieved_GBs": gbs}
@@ -287,7 +287,10 @@ def main():
     log(f"[bench] plain copy: {copy['GBs']:.0f} GB/s")
     roofline = None
     if fk:
-        kname = ("k_pairs_tiled" if head.get("list_tiled") else "k_pairs_mixed") if modes[0] == "mixed" else "k_pairs_fp64"
+        if modes[0] == "mixed":
+            kname = "k_pairs_tiled" if head.get("list_tiled") else "k_pairs_mixed"
+        else:
+            kname = "k_pairs_tiled_fp64" if head.get("list_tiled") else "k_pairs_fp64"
         traffic, tsrc = counter_traffic(kname, args.config)
         roofline = {"bound": "hbm", "achieved": round(fk["achieved_GBs"], 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(fk["achieved_GBs"] / HBM_PEAK_GBS, 4),

@@ -150,6 +150,7 @@ WsLayout ws_layout(const Geo& g, int64_t ldc_max)
     L.ldc = off;       off = align256(off + sizeof(int32_t) * (size_t)(ldc_max > 0 ? ldc_max : 1));
     L.scal = off;      off = align256(off + sizeof(int64_t) * 32);
     L.tmax = off;      off = align256(off + sizeof(int64_t) * kTileMaxSlots);
+    L.mx = off;        off = align256(off + sizeof(int64_t) * 2 * kMaxSlots * kMaxSlotStride);
     L.total = off;
     return L;
 }
@@ -428,6 +429,17 @@ static int check_state(const Ctx& c, const md_params* p, md_state* st)
 // bin + optional re-sort + reference copy + list build (no wait)
 static int read_flags(const Ctx& c, md_state* st, hipStream_t s, int64_t out[16]);
 
+// slot arrays of the block maxima of d2 (which = 0) and v2 (which = 1)
+static unsigned long long* mx_slots(const Ctx& c, md_state* st, int which)
+{
+    return (unsigned long long*)((char*)st->ws + c.W.mx) + (size_t)which * kMaxSlots * kMaxSlotStride;
+}
+
+static hipError_t clear_maxima(const Ctx& c, md_state* st, hipStream_t s)
+{
+    return launch_fill_i32((int32_t*)mx_slots(c, st, 0), 0, 2 * 2 * kMaxSlots * kMaxSlotStride, s);
+}
+
 // Pair list of the state: tiled (16-bit entries into each tile's staged
 // neighbourhood) when the geometry has tiles and the slots are in cell order,
 // else slot entries.
@@ -510,7 +522,7 @@ static int read_flags(const Ctx& c, md_state* st, hipStream_t s, int64_t out[16]
 {
     int64_t* scal = (int64_t*)((char*)st->ws + c.W.scal);
     MD_HIP(launch_gather_flags(st->list.status, scal, st->flags, st->energy, (const int64_t*)((char*)st->ws + c.W.tmax),
-                               scal + kScalOut, s),
+                               mx_slots(c, st, 0), scal + kScalOut, s),
            "flags/gather");
     int64_t local[16];
     int64_t* dst = st->host_scratch ? st->host_scratch : local;
@@ -544,8 +556,8 @@ static IntArgs int_args(const Ctx& c, const md_params* p, md_state* st, bool ke)
     a.pos32 = st->pos32;
     a.cell_xyz = st->cells.cell_xyz;
     a.part_ke = ke ? (double*)((char*)st->ws + c.W.part_b) : nullptr;
-    a.max_d2 = (unsigned long long*)(st->energy + 4);
-    a.max_v2 = (unsigned long long*)(st->energy + 5);
+    a.max_d2 = mx_slots(c, st, 0);
+    a.max_v2 = mx_slots(c, st, 1);
     a.dt = p->dt;
     a.precision = p->precision;
     return a;
@@ -663,6 +675,7 @@ int md_prepare(const md_params* p, md_state* st, hipStream_t s)
     timer_begin(T, nullptr);
     MD_HIP(launch_fill_i32((int32_t*)st->flags, 0, 2, s), "prepare/flags");
     MD_HIP(launch_fill_i32((int32_t*)((char*)st->ws + c.W.scal), 0, 4, s), "prepare/err");
+    MD_HIP(clear_maxima(c, st, s), "prepare/maxima");
     int64_t f[16];
     if ((rc = rebuild(c, p, st, true, T, s, f)) != MD_OK) return rc;
     st->rebuilds += 1;
@@ -732,7 +745,7 @@ int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_eve
         if (need_drift) {
             // first half kick and drift of this step (the previous step ended
             // with a completed kick, or this is the first step of the call)
-            MD_HIP(launch_fill_i32((int32_t*)(st->energy + 4), 0, 4, s), "step/maxd2");
+            MD_HIP(clear_maxima(c, st, s), "step/maxd2");
             tick(T, MD_T_INTEGRATE, 0, s);
             MD_HIP(launch_integrate(c.g, INT_KD, int_args(c, p, st, false), s), "step/kd");
             tick(T, MD_T_INTEGRATE, 1, s);
@@ -787,13 +800,13 @@ int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_eve
         io.pos_ref = st->pos_ref;
         io.pos_out = mixed ? st->pos : st->pos_alt;
         io.pos32_out = mixed ? st->pos32_alt : nullptr;
-        io.max_d2 = (unsigned long long*)(st->energy + 4);
-        io.max_v2 = (unsigned long long*)(st->energy + 5);
+        io.max_d2 = mx_slots(c, st, 0);
+        io.max_v2 = mx_slots(c, st, 1);
         io.dt = p->dt;
         io.drift = !last;
         io.track_speed = p->rebuild_rule == MD_REBUILD_DUTC_LDC;
         io.tile = tile_io(st);
-        if (!last) MD_HIP(launch_fill_i32((int32_t*)(st->energy + 4), 0, 4, s), "step/maxd2");
+        if (!last) MD_HIP(clear_maxima(c, st, s), "step/maxd2");
         tick(T, MD_T_FORCE, 0, s);
         MD_HIP(launch_force_step(c.g, c.lj, p->precision, io, s), "step/force");
         tick(T, MD_T_FORCE, 1, s);

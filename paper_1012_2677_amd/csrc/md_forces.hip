@@ -185,8 +185,8 @@ __device__ __forceinline__ void block_epilogue(const PairArgs& a, int64_t blk, d
             if (MODE != MODE_FORCE) a.part_ke[blk] = 0.5 * ske;
         }
         if (MODE == MODE_KKD) {
-            atomicMax(a.max_d2, (unsigned long long)__double_as_longlong(m));
-            if (VMAX) atomicMax(a.max_v2, (unsigned long long)__double_as_longlong(mv));
+            atomicMax(max_slot(a.max_d2, blk), (unsigned long long)__double_as_longlong(m));
+            if (VMAX) atomicMax(max_slot(a.max_v2, blk), (unsigned long long)__double_as_longlong(mv));
         }
     }
 }

@@ -120,8 +120,8 @@ __global__ __launch_bounds__(kStreamBlock) void k_integrate(Geo g, IntArgs a)
                 m = fmax(m, s_v[w]);
                 mv = fmax(mv, s_u[w]);
             }
-            atomicMax(a.max_d2, (unsigned long long)__double_as_longlong(m));
-            atomicMax(a.max_v2, (unsigned long long)__double_as_longlong(mv));
+            atomicMax(max_slot(a.max_d2, blockIdx.x), (unsigned long long)__double_as_longlong(m));
+            atomicMax(max_slot(a.max_v2, blockIdx.x), (unsigned long long)__double_as_longlong(mv));
         }
     }
     if (KE) {
@@ -309,15 +309,29 @@ hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t* s
 }
 
 __global__ void k_gather_flags(const int64_t* __restrict__ status, const int64_t* __restrict__ err,
-                               const int64_t* __restrict__ flags, const double* __restrict__ energy,
-                               const int64_t* __restrict__ tmax, int64_t* __restrict__ out)
+                               const int64_t* __restrict__ flags, double* __restrict__ energy,
+                               const int64_t* __restrict__ tmax, const unsigned long long* __restrict__ mx,
+                               int64_t* __restrict__ out)
 {
-    // largest staged tile neighbourhood: a wave-wide max over the slots
+    // wave-wide maxima over the slots: largest staged tile neighbourhood,
+    // largest squared displacement and drift speed (bit patterns of
+    // non-negative doubles order like the values)
     int64_t m = 0;
+    unsigned long long md = 0, mv = 0;
     for (int k = threadIdx.x; k < kTileMaxSlots; k += 64) m = max(m, tmax[k]);
+    for (int k = threadIdx.x; k < kMaxSlots; k += 64) {
+        md = max(md, mx[k * kMaxSlotStride]);
+        mv = max(mv, mx[(kMaxSlots + k) * kMaxSlotStride]);
+    }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = max(m, (int64_t)__shfl_xor((long long)m, o, 64));
+    for (int o = 32; o > 0; o >>= 1) {
+        m = max(m, (int64_t)__shfl_xor((long long)m, o, 64));
+        md = max(md, (unsigned long long)__shfl_xor((long long)md, o, 64));
+        mv = max(mv, (unsigned long long)__shfl_xor((long long)mv, o, 64));
+    }
     if (threadIdx.x != 0) return;
+    energy[4] = __longlong_as_double((long long)md);
+    energy[5] = __longlong_as_double((long long)mv);
     out[0] = status[0];
     out[1] = status[1];
     out[2] = status[2];
@@ -332,10 +346,10 @@ __global__ void k_gather_flags(const int64_t* __restrict__ status, const int64_t
     out[11] = m;        // tiled list: largest staged neighbourhood of a tile
 }
 
-hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags,
-                               const double* energy, const int64_t* tmax, int64_t* out, hipStream_t s)
+hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags, double* energy,
+                               const int64_t* tmax, const unsigned long long* mx, int64_t* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_flags, dim3(1), dim3(64), 0, s, status, err, flags, energy, tmax, out);
+    hipLaunchKernelGGL(k_gather_flags, dim3(1), dim3(64), 0, s, status, err, flags, energy, tmax, mx, out);
     return hipGetLastError();
 }
 

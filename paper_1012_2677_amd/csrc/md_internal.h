@@ -58,6 +58,16 @@ __host__ __device__ inline int tile_stage_cap(int precision)
     return precision == MD_MIXED ? kTileMaxStage : kTileMaxStage64;
 }
 constexpr int kTileMaxSlots = 256;
+// Block maxima (squared displacement, squared drift speed) go to one of
+// kMaxSlots slots by block index, each on its own 64-byte line, so that the
+// atomics of many blocks do not meet at one address; the flag read-back takes
+// the maximum over the slots.
+constexpr int kMaxSlots = 256;
+constexpr int kMaxSlotStride = 8;   // int64 words between slots
+__host__ __device__ inline unsigned long long* max_slot(unsigned long long* base, int64_t blk)
+{
+    return base + (blk & (kMaxSlots - 1)) * kMaxSlotStride;
+}
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -111,6 +121,7 @@ struct WsLayout {
     size_t ldc;        // int32[ldc_max] members of the large-displacement check
     size_t scal;       // int64[32]      small device scalars (layout in md_api.hip)
     size_t tmax;       // int64[kTileMaxSlots]  largest staged tile neighbourhood, spread over slots
+    size_t mx;         // int64[2][kMaxSlots * kMaxSlotStride]  block maxima of d2 and v2
     size_t total;
     int64_t nbs;       // scan blocks
     int64_t nbf;       // adjoint-kernel blocks (kKeysPerBlock keys each)
@@ -296,8 +307,9 @@ hipError_t launch_reduce_energy(const double* part_pw, int64_t nbf, const double
                                 int64_t nbi, double* energy, double* log_row, hipStream_t s);
 hipError_t launch_reduce_pair(const double* part, int64_t nb, double scale0, double scale1,
                               double* out2, hipStream_t s, bool accumulate = false);
-hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags,
-                               const double* energy, const int64_t* tmax, int64_t* out, hipStream_t s);
+// Also folds the slot maxima of d2 and v2 (mx) into energy[4] and energy[5].
+hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags, double* energy,
+                               const int64_t* tmax, const unsigned long long* mx, int64_t* out, hipStream_t s);
 hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t* status, long long* part,
                              hipStream_t s);
 
