@@ -722,7 +722,9 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     // the first kPrefetch entries of the rows each lane walks, two per 32-bit
     // load: lane j of a group takes entries 2j + 16u and 2j + 16u + 1; all
     // loads of the chunk go out at once
-    constexpr int UP = kPrefetch / 16;
+    // (48 entries when the drift speed is tracked, to stay within 128 VGPRs)
+    constexpr int PF = VMAX ? 48 : kPrefetch;
+    constexpr int UP = PF / 16;
     const uint32_t dummy2 = dummy | (dummy << 16);
     uint32_t E[8][UP];
 #pragma unroll
@@ -758,10 +760,10 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
                 pair(p1, li, fx, fy, fz);
             }
         }
-        if (cmax > kPrefetch) {
+        if (cmax > PF) {
             // the rest of rows longer than the prefetched part
             const uint16_t* row = (const uint16_t*)a.nbr + __shfl(own_off, ks, 64);
-            for (int t0 = kPrefetch + sub; t0 - sub < cmax; t0 += 8 * U) {
+            for (int t0 = PF + sub; t0 - sub < cmax; t0 += 8 * U) {
                 uint32_t e[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
