@@ -7,7 +7,10 @@
   * Newton's third law (sum of forces ~ 0) on disordered inputs;
   * F = -grad U by central differences along random directions;
   * forces do not depend on the search length once rs >= rc;
-  * the per-particle sampling routine equals the full computation.
+  * the per-particle sampling routine equals the full computation;
+  * forces, PE and virial equal an independent O(N^2) torch enumeration
+    differentiated by autograd (forces as -grad U, the virial as -dU/ds for
+    displacements scaled by s), on jittered lattices at three densities.
 """
 
 from fractions import Fraction as Fr
@@ -124,3 +127,40 @@ def test_neighbor_rows_equal_pair_set(ref):
     got = ref.neighbors_sample(q, L, idx)
     for i in range(n):
         assert got[i].tolist() == sorted(rows[i])
+
+
+def _torch_energy_scaled(q, L, s, rc=2.5):
+    """Brute-force truncated LJ energy (eps = sigma = 1) over all pairs with the
+    minimum-image displacements scaled by s: dU/ds at s = 1 is -W."""
+    import torch
+
+    n = q.shape[0]
+    i, j = torch.triu_indices(n, n, 1)
+    d = q[j] - q[i]
+    d = (d - L * torch.round(d / L)) * s
+    r2 = (d * d).sum(-1)
+    x = 1.0 / rc
+    c2 = 6 * x ** 14 - 3 * x ** 8
+    c0 = -7 * x ** 12 + 4 * x ** 6
+    s6 = (1.0 / r2) ** 3
+    V = 4 * (s6 * s6 - s6 + c2 * r2 + c0)
+    return torch.where(r2 < rc * rc, V, torch.zeros_like(V)).sum()
+
+
+@pytest.mark.parametrize("n_fcc,rho,seed", [(5, 0.5, 31), (6, 0.8, 32), (4, 0.3, 33)])
+def test_forces_match_independent_brute_force(ref, n_fcc, rho, seed):
+    # an O(N^2) enumeration in torch, differentiated by autograd, against the
+    # oracle's cell-list loop with its analytic pair forces: the pair set
+    # (minimum image included), the force direction and sign, PE and the
+    # virial W = sum g r^2 = -dU/ds for displacements scaled by s
+    import torch
+
+    q, L = li.jittered_fcc(n_fcc, amp=0.2, rho=rho, seed=seed)
+    F, pe, w = ref.forces(q, L)
+    qt = torch.tensor(q, dtype=torch.float64, requires_grad=True)
+    s = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    U = _torch_energy_scaled(qt, L, s)
+    gq, gs = torch.autograd.grad(U, (qt, s))
+    assert pe == pytest.approx(U.item(), rel=1e-12)
+    assert np.abs(F + gq.numpy()).max() <= 1e-10 * np.abs(F).max()
+    assert w == pytest.approx(-gs.item(), rel=1e-11)
