@@ -14,7 +14,8 @@ reads partners from LDS.  These tests check:
     that wrap the box in z;
   * runs with the tiled list match the oracle's run (FP64: energy log to
     1e-10 relative, same rebuilds; mixed: energy per particle to 1e-5) and the
-    slot-layout run.
+    slot-layout run;
+  * anisotropic boxes with 3-cell axes (3 neighbour columns, one-cell tiles).
 """
 
 import numpy as np
@@ -147,3 +148,32 @@ def test_oversized_tiles_fall_back_to_slot_entries(ref, precision, tile_cells):
     idx = np.random.default_rng(0).choice(q.shape[0], 300, replace=False).astype(np.int64)
     Fr, S, _, _, _ = ref.forces_sample(e.positions(), L, idx)
     assert G.force_error(e.forces()[idx], Fr, S) <= (1e-12 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("cells", [(5, 8, 14), (14, 5, 5), (5, 5, 20)])
+def test_tiled_anisotropic_boxes(ref, precision, cells):
+    # 3-column axes (the neighbour columns cx - 1 and cx + 1 are the only two
+    # others), a 3-cell z axis (tiles of one cell), long z columns; jittered
+    q, L = li.fcc_lattice_box(*cells)
+    rng = np.random.default_rng(sum(cells))
+    q = q + rng.normal(0.0, 0.1, q.shape)
+    q = q - np.asarray(L) * np.floor(q / np.asarray(L))
+    v = li.maxwell_boltzmann(q.shape[0], seed=1)
+    t = _engine(q, v, L, precision=precision)
+    s = _engine(q, v, L, precision=precision, list_layout="slots")
+    t.prepare()
+    s.prepare()
+    assert int(t.state.list_tiled) == 1
+    slots = np.arange(q.shape[0])
+    kt, pt = G.rows_for_slots_state(t, slots)
+    ks, ps = G.rows_for_slots_state(s, slots)
+    assert np.array_equal(kt, ks) and np.array_equal(pt, ps)
+    idx = np.arange(q.shape[0], dtype=np.int64)
+    Fr, S, _, _, _ = ref.forces_sample(t.positions(), L, idx)
+    assert G.force_error(t.forces(), Fr, S) <= (1e-12 if precision == "fp64" else 1e-5)
+    # a short run keeps matching the slot-entry run
+    lt = t.step(20, sample_every=10)
+    ls = s.step(20, sample_every=10)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert np.abs(lt - ls).max() <= tol * max(1.0, np.abs(ls).max())
