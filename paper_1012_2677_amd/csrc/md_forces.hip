@@ -513,6 +513,10 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed
 // kPrefetch entries of all 8 rounds loaded up front, two per 32-bit load.  Key
 // data reach the round's lanes by shuffles; group sums and the integrator
 // epilogue are those of the other pair kernels.
+#ifndef MD_TILE_STRIP
+#define MD_TILE_STRIP 8
+#endif
+constexpr int kTileStrip = MD_TILE_STRIP;       // x-columns per strip of the tile order
 #ifndef MD_TILE_PREFETCH
 #define MD_TILE_PREFETCH 64
 #endif
@@ -548,8 +552,13 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
     const int tz = (int)(blk % a.nt);
-    const int64_t cxy = blk / a.nt;
-    const int cy = (int)(cxy % ny), cx = (int)(cxy / ny);
+    // columns in strips of kTileStrip x-columns walked along y, so that the
+    // tiles an XCD runs close in time share their neighbour columns in L2
+    const int64_t seq = blk / a.nt;
+    const int64_t strip = seq / ((int64_t)kTileStrip * ny);
+    const int sw = (int)min((int64_t)kTileStrip, (int64_t)nx - strip * kTileStrip);
+    const int64_t in = seq - strip * kTileStrip * ny;
+    const int cy = (int)(in / sw), cx = (int)(strip * kTileStrip + in % sw);
     const int z0 = tz * a.tc, z1 = min(z0 + a.tc, nz);
     const int tid = threadIdx.x;
     // FP64: the tile's pairs need minimum images only when it touches the box
