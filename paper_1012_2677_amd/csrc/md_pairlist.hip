@@ -67,6 +67,10 @@ __device__ __forceinline__ void write_row(const BuildArgs& a, int32_t kslot, int
 }
 
 constexpr int kMaxOwn = 64;     // own-cell particles kept in LDS for the key loop
+#ifndef MD_BUILD_STRIP
+#define MD_BUILD_STRIP 8
+#endif
+constexpr int kBuildStrip = MD_BUILD_STRIP;   // x-columns per strip of the cell order
 
 // Tiled (16-bit) rows start at even entries, so the force pass can read two
 // entries with one 32-bit load; the entry after a row of odd length holds the
@@ -235,13 +239,20 @@ template <int NCH, bool TILED>
 __global__ __launch_bounds__(64) void k_build(BuildArgs a)
 {
     using E = typename std::conditional<TILED, uint16_t, uint32_t>::type;
-    const int64_t c = xcd_remap(blockIdx.x, gridDim.x);
-    if (c >= a.ncell) return;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    if (t >= a.ncell) return;
     const int lane = (int)threadIdx.x;
     const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
-    const int cz = (int)(c % nz);
-    const int cy = (int)((c / nz) % ny);
-    const int cx = (int)(c / ((int64_t)nz * ny));
+    // cells in strips of kBuildStrip x-columns walked along y (a column's
+    // cells consecutive), so that cells built close in time share their
+    // neighbour cells in L2
+    const int cz = (int)(t % nz);
+    const int64_t seq = t / nz;
+    const int64_t strip = seq / ((int64_t)kBuildStrip * ny);
+    const int sw = (int)min((int64_t)kBuildStrip, (int64_t)nx - strip * kBuildStrip);
+    const int64_t in = seq - strip * kBuildStrip * ny;
+    const int cy = (int)(in / sw), cx = (int)(strip * kBuildStrip + in % sw);
+    const int64_t c = ((int64_t)cx * ny + cy) * nz + cz;
 
     __shared__ int s_nstart[27];
     __shared__ int s_pref[28];
