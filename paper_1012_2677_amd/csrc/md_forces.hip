@@ -597,11 +597,14 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     const float csx = (float)a.cs[0], csy = (float)a.cs[1];
     const R csz = (R)a.cs[2];
     {
-        // every thread takes elements tid and tid + kTileBlock of each column
-        // run (the loads of all 9 columns in flight together), then writes
-        // them (mixed: shifted by the column offset and tagged with their run
-        // position); longer runs finish in a plain loop
-        V4 p[9][2];
+        // every thread takes elements tid, tid + kTileBlock, ... (SB of them) of
+        // each column run (the loads of all 9 columns in flight together),
+        // then writes them (mixed: shifted by the column offset and tagged
+        // with their run position); longer runs finish in a plain loop.  FP64
+        // takes one element per column (its runs are shorter, and 18 double4
+        // would hold 144 registers)
+        constexpr int SB = MIXED ? 2 : 1;
+        V4 p[9][SB];
         auto src_of = [&](int col, int i) {
             const int lenA = s_run[col][1];
             return i < lenA ? s_run[col][0] + i : s_run[col][2] + (i - lenA);
@@ -625,7 +628,7 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         for (int col = 0; col < 9; ++col) {
             const int len = s_run[col][1] + s_run[col][3];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < SB; ++u) {
                 // unconditional loads (slot 0 past the run's end, result unused)
                 const int i = tid + u * kTileBlock;
                 p[col][u] = load(i < len ? src_of(col, i) : 0);
@@ -635,14 +638,14 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         for (int col = 0; col < 9; ++col) {
             const int len = s_run[col][1] + s_run[col][3];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = 0; u < SB; ++u) {
                 const int i = tid + u * kTileBlock;
                 if (i < len) put(p[col][u], col, i);
             }
         }
         for (int col = 0; col < 9; ++col) {
             const int len = s_run[col][1] + s_run[col][3];
-            for (int i = tid + 2 * kTileBlock; i < len; i += kTileBlock) put(load(src_of(col, i)), col, i);
+            for (int i = tid + SB * kTileBlock; i < len; i += kTileBlock) put(load(src_of(col, i)), col, i);
         }
     }
     __syncthreads();
