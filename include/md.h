@@ -145,7 +145,13 @@ typedef struct md_cells {
  *             1 <= cell_stride <= 2^29
  *   status    device int64[4]: [0] total entries, [1] largest per-cell block,
  *             [2] 1 if some cell block overflowed cell_stride (list invalid),
- *             [3] reserved.                                               */
+ *             [3] reserved.
+ *   tiled     set by the library: 0 after md_build_pairlist (the entries
+ *             above); 1 when md_prepare / md_step left the tiled layout of a
+ *             simulation state in this list (see md_state).  md_forces,
+ *             md_hvp, md_param_grad and md_adjoint_kick read slot entries
+ *             only and return MD_ERR_ARG for a tiled list.
+ *   reserved  0.                                                         */
 typedef struct md_pairlist {
     int64_t*  offsets;
     int32_t*  counts;
@@ -153,6 +159,8 @@ typedef struct md_pairlist {
     int64_t   cell_stride;
     int64_t   capacity;
     int64_t*  status;
+    int32_t   tiled;
+    int32_t   reserved;
 } md_pairlist;
 
 /* Per-kernel-class timers filled by md_step when md_state.timers != NULL:

@@ -60,7 +60,8 @@ class MdCells(C.Structure):
 
 class MdPairlist(C.Structure):
     _fields_ = [("offsets", C.c_void_p), ("counts", C.c_void_p), ("nbr", C.c_void_p),
-                ("cell_stride", C.c_int64), ("capacity", C.c_int64), ("status", C.c_void_p)]
+                ("cell_stride", C.c_int64), ("capacity", C.c_int64), ("status", C.c_void_p),
+                ("tiled", C.c_int32), ("reserved", C.c_int32)]
 
 
 class MdTimers(C.Structure):

@@ -199,6 +199,17 @@ static int check_list(const Ctx& c, const md_pairlist* list)
     return MD_OK;
 }
 
+// The standalone force, Hessian and adjoint passes decode slot entries; a
+// state's tiled list holds offsets into staged tiles instead.
+static int check_slot_list(const Ctx& c, const md_pairlist* list)
+{
+    int rc = check_list(c, list);
+    if (rc != MD_OK) return rc;
+    if (list->tiled)
+        return fail(MD_ERR_ARG, "pair list holds the tiled layout of a state; build one with md_build_pairlist");
+    return MD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // timers
 // ---------------------------------------------------------------------------
@@ -318,6 +329,7 @@ int md_build_pairlist(const md_params* p, const double* pos, const md_cells* cel
     if ((rc = check_list(c, list)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
     MD_HIP(launch_build(c.g, p->rs, pos, *cells, *list, ws, c.W, false, nullptr, stream), "md_build_pairlist");
+    list->tiled = 0;
     return MD_OK;
 }
 
@@ -329,7 +341,7 @@ int md_forces(const md_params* p, const double* pos, const md_cells* cells, cons
     if (rc != MD_OK) return rc;
     if (!pos || !force) return fail(MD_ERR_ARG, "pos or force is NULL");
     if ((rc = check_cells(c, cells)) != MD_OK) return rc;
-    if ((rc = check_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_slot_list(c, list)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
     char* w = (char*)ws;
     float* pos32 = nullptr;
@@ -356,7 +368,7 @@ int md_hvp(const md_params* p, const double* pos, const md_cells* cells, const m
     if (rc != MD_OK) return rc;
     if (!pos || !u || !Hu) return fail(MD_ERR_ARG, "pos, u or Hu is NULL");
     if ((rc = check_cells(c, cells)) != MD_OK) return rc;
-    if ((rc = check_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_slot_list(c, list)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
     double* part = dparam ? (double*)((char*)ws + c.W.part_a) : nullptr;
     MD_HIP(launch_hvp(c.g, c.lj, pos, cells->cell_xyz, *list, u, Hu, part, stream), "md_hvp");
@@ -372,7 +384,7 @@ int md_param_grad(const md_params* p, const double* pos, const md_cells* cells, 
     if (rc != MD_OK) return rc;
     if (!pos || !dU) return fail(MD_ERR_ARG, "pos or dU is NULL");
     if ((rc = check_cells(c, cells)) != MD_OK) return rc;
-    if ((rc = check_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_slot_list(c, list)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
     double* part = (double*)((char*)ws + c.W.part_a);
     MD_HIP(launch_param_grad(c.g, c.lj, pos, cells->cell_xyz, *list, part, stream), "md_param_grad");
@@ -391,7 +403,7 @@ int md_adjoint_kick(const md_params* p, const double* pos, const md_cells* cells
     if (u_out && (u_out == u || u_out == out)) return fail(MD_ERR_ARG, "u_out must not alias u or out");
     if (out == u) return fail(MD_ERR_ARG, "out must not alias u");
     if ((rc = check_cells(c, cells)) != MD_OK) return rc;
-    if ((rc = check_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_slot_list(c, list)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
     AdjCoef k;
     k.alpha = coef[0];
@@ -453,6 +465,7 @@ static int build_list(const Ctx& c, const md_params* p, md_state* st, bool tiled
            "rebuild/build");
     tick(T, MD_T_BUILD, 1, s);
     st->list_tiled = tiled ? 1 : 0;
+    st->list.tiled = st->list_tiled;
     st->tile_stage = 0;
     st->tile_cells = tiled ? c.g.tc : 0;
     return MD_OK;

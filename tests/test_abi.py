@@ -53,7 +53,7 @@ int main() {
   std::printf("md_state %zu\n", sizeof(md_state));
   OFF(md_params, precision); OFF(md_params, resort_every); OFF(md_params, dt);
   OFF(md_cells, cell_of); OFF(md_cells, order);
-  OFF(md_pairlist, cell_stride); OFF(md_pairlist, status);
+  OFF(md_pairlist, cell_stride); OFF(md_pairlist, status); OFF(md_pairlist, tiled);
   OFF(md_state, cells); OFF(md_state, list); OFF(md_state, energy); OFF(md_state, ws_bytes);
   OFF(md_state, timers); OFF(md_state, step); OFF(md_state, phase); OFF(md_state, list_valid);
   OFF(md_params, list_layout); OFF(md_params, tile_cells); OFF(md_state, list_tiled); OFF(md_state, tile_stage);
@@ -136,6 +136,34 @@ def test_null_pointers_rejected_before_launch(A):
     with pytest.raises(A.MdError) as e:
         A.md_step(p, state, 10, 0, None, None)
     assert e.value.code == A.MD_ERR_ARG
+
+
+def test_tiled_list_rejected_by_standalone_passes(A):
+    # a state's tiled list holds tile offsets, not slots: the standalone
+    # passes refuse it before any launch; the same list marked as slot
+    # entries gets past the list check and fails on the workspace size
+    p = _params(A)
+    fake = 1 << 20  # never dereferenced: validation fails first
+    cells = A.MdCells()
+    for k, m in enumerate(A.md_cell_dims(p)):
+        cells.ncell[k] = m
+    cells.cell_of = cells.cell_xyz = cells.count = cells.start = cells.order = fake
+    plist = A.MdPairlist()
+    plist.offsets = plist.counts = plist.nbr = plist.status = fake
+    plist.cell_stride = 64
+    plist.capacity = 64 * 7 * 7 * 7
+    calls = [
+        lambda: A.md_forces(p, fake, cells, plist, fake, None, fake, 16, None),
+        lambda: A.md_hvp(p, fake, cells, plist, fake, fake, None, fake, 16, None),
+        lambda: A.md_param_grad(p, fake, cells, plist, fake, fake, 16, None),
+        lambda: A.md_adjoint_kick(p, fake, cells, plist, fake, fake + 64, None, [0.0] * 5, fake, fake, 16, None),
+    ]
+    for tiled, code in ((1, A.MD_ERR_ARG), (0, A.MD_ERR_WORKSPACE)):
+        plist.tiled = tiled
+        for call in calls:
+            with pytest.raises(A.MdError) as e:
+                call()
+            assert e.value.code == code, (tiled, e.value)
 
 
 def test_workspace_too_small(A):

@@ -177,3 +177,35 @@ def test_tiled_anisotropic_boxes(ref, precision, cells):
     ls = s.step(20, sample_every=10)
     tol = 1e-12 if precision == "fp64" else 1e-5
     assert np.abs(lt - ls).max() <= tol * max(1.0, np.abs(ls).max())
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_standalone_force_pass_refuses_a_tiled_state_list(precision):
+    # the library marks the state's list as tiled; md_forces then returns
+    # MD_ERR_ARG instead of reading tile offsets as slots.  A slot-layout
+    # state list is accepted and gives the state's own forces.
+    from paper_1012_2677_amd import _abi as A
+    from paper_1012_2677_amd.engine import Workspace
+
+    q, L = _jittered(8, seed=5)
+    v = li.maxwell_boltzmann(q.shape[0], seed=5)
+    dt = torch.float32 if precision == "mixed" else torch.float64
+    for layout, tiled in (("auto", 1), ("slots", 0)):
+        e = _engine(q, v, L, precision=precision, list_layout=layout)
+        e.prepare()
+        assert int(e.state.list.tiled) == tiled == int(e.state.list_tiled)
+        ws = Workspace(e.params, G.device())
+        F = torch.zeros((3, q.shape[0]), dtype=dt, device=G.device())
+        args = (e.params, e.state.pos, e.state.cells, e.state.list, F.data_ptr(), None, ws.ptr, ws.nbytes,
+                e.stream())
+        if tiled:
+            with pytest.raises(A.MdError) as err:
+                A.md_forces(*args)
+            assert err.value.code == A.MD_ERR_ARG
+            continue
+        A.md_forces(*args)
+        torch.cuda.synchronize()
+        got = F.double().cpu().numpy()
+        want = e.force.double().cpu().numpy()
+        tol = 1e-12 if precision == "fp64" else 1e-5
+        assert np.abs(got - want).max() <= tol * np.abs(want).max()
