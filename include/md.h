@@ -62,6 +62,7 @@ extern "C" {
 /* list layouts of the simulation state (md_params.list_layout) */
 #define MD_LIST_AUTO  0   /* tiled when possible (mixed precision, slots in cell order) */
 #define MD_LIST_SLOTS 1   /* always 32-bit slot entries                                 */
+#define MD_LIST_HALF  2   /* 32-bit slot entries, each pair once (half stencil)          */
 
 /* pair-list rebuild rules (md_params.rebuild_rule) */
 #define MD_REBUILD_HALF_SKIN 0   /* rebuild once some particle moved more than (rs - rc)/2         */
@@ -94,6 +95,14 @@ extern "C" {
  *   entry); otherwise, and always with MD_LIST_SLOTS, entries are
  *   32-bit partner slots as in md_build_pairlist.  Both layouts hold the same
  *   pairs in the same row order.
+ *   MD_LIST_HALF: every pair once (Sec. 2.4, the key/partner list with
+ *   Newton's third law), in md_build_pairlist as well as in the state: the
+ *   row of key i holds the partners in its own cell with a larger slot, then
+ *   those in the 13 neighbour cells of stencil codes 14 .. 26, in the order
+ *   of a full row (code, then slot).  The force passes add each pair's force
+ *   to the key in registers and to the partner with a device atomic, so the
+ *   rounding of a force sum depends on the order of the atomics; in a
+ *   simulation state the integrator then runs as a pass of its own.
  *   tile_cells: cells per tile along z (0 = about 200 keys per tile at the
  *   mean density in MD_MIXED, 135 in MD_FP64); clipped to [1, nz - 2]. */
 typedef struct md_params {
@@ -106,7 +115,7 @@ typedef struct md_params {
     int32_t resort_every;
     int32_t rebuild_rule;  /* MD_REBUILD_HALF_SKIN or MD_REBUILD_DUTC_LDC */
     int32_t ldc_max;
-    int32_t list_layout;   /* MD_LIST_AUTO or MD_LIST_SLOTS */
+    int32_t list_layout;   /* MD_LIST_AUTO, MD_LIST_SLOTS or MD_LIST_HALF */
     int32_t tile_cells;    /* 0 = automatic, else 1 .. 1023 */
 } md_params;
 
@@ -151,7 +160,11 @@ typedef struct md_cells {
  *             simulation state in this list (see md_state).  md_forces,
  *             md_hvp, md_param_grad and md_adjoint_kick read slot entries
  *             only and return MD_ERR_ARG for a tiled list.
- *   reserved  0.                                                         */
+ *   half      set by the library: 1 when the rows hold each pair once
+ *             (md_params.list_layout = MD_LIST_HALF: a key's row keeps the
+ *             partners of stencil code 13 with a larger slot and those of
+ *             codes 14 .. 26).  md_forces takes half lists; md_hvp,
+ *             md_param_grad and md_adjoint_kick return MD_ERR_ARG for them. */
 typedef struct md_pairlist {
     int64_t*  offsets;
     int32_t*  counts;
@@ -160,7 +173,7 @@ typedef struct md_pairlist {
     int64_t   capacity;
     int64_t*  status;
     int32_t   tiled;
-    int32_t   reserved;
+    int32_t   half;
 } md_pairlist;
 
 /* Per-kernel-class timers filled by md_step when md_state.timers != NULL:
@@ -277,7 +290,10 @@ int md_resort(const md_params* p, md_state* st, hipStream_t stream);
  *   r^2 = fma(dz, dz, fma(dy, dy, dx * dx))   (FP64, bit-exact),
  * found among the 27 cells around the key's cell.  cells must come from
  * md_bin_cells (and md_resort, if applied) on the same pos.  Overflow of a cell
- * block is reported in list->status ([2] = 1, [1] = the stride needed). */
+ * block is reported in list->status ([2] = 1, [1] = the stride needed).
+ * With p->list_layout = MD_LIST_HALF the rows hold each pair once (the own
+ * cell's partners with a larger slot, then stencil codes 14 .. 26, found among
+ * those 14 cells) and list->half is set to 1; otherwise to 0. */
 int md_build_pairlist(const md_params* p, const double* pos, const md_cells* cells,
                       md_pairlist* list, void* ws, size_t ws_bytes, hipStream_t stream);
 
@@ -286,7 +302,10 @@ int md_build_pairlist(const md_params* p, const double* pos, const md_cells* cel
  * force: device double[3][n] (MD_FP64) or float[3][n] (MD_MIXED).
  * pe_w: device double[2] receiving PE = sum_pairs V and the virial
  * W = sum_pairs g r^2, or NULL to skip the energy terms.  pos may have moved
- * since the list was built as long as no particle moved more than (rs-rc)/2. */
+ * since the list was built as long as no particle moved more than (rs-rc)/2.
+ * A half list (list->half) adds each pair to both ends, the partner's share
+ * F_j += g d by a device atomic into force (cleared first on the stream), so
+ * the rounding of each force sum depends on the order of the atomics. */
 int md_forces(const md_params* p, const double* pos, const md_cells* cells,
               const md_pairlist* list, void* force, double* pe_w,
               void* ws, size_t ws_bytes, hipStream_t stream);

@@ -28,6 +28,7 @@ MD_MAX_N = 1 << 27
 
 MD_LIST_AUTO = 0
 MD_LIST_SLOTS = 1
+MD_LIST_HALF = 2
 MD_REBUILD_HALF_SKIN = 0
 MD_REBUILD_DUTC_LDC = 1
 
@@ -61,7 +62,7 @@ class MdCells(C.Structure):
 class MdPairlist(C.Structure):
     _fields_ = [("offsets", C.c_void_p), ("counts", C.c_void_p), ("nbr", C.c_void_p),
                 ("cell_stride", C.c_int64), ("capacity", C.c_int64), ("status", C.c_void_p),
-                ("tiled", C.c_int32), ("reserved", C.c_int32)]
+                ("tiled", C.c_int32), ("half", C.c_int32)]
 
 
 class MdTimers(C.Structure):

@@ -47,8 +47,8 @@ static int check_params(const md_params* p, int32_t nc[3])
     if (p->rebuild_rule != MD_REBUILD_HALF_SKIN && p->rebuild_rule != MD_REBUILD_DUTC_LDC)
         return fail(MD_ERR_ARG, "rebuild_rule must be 0 or 1");
     if (p->ldc_max < 0 || p->ldc_max > (1 << 22)) return fail(MD_ERR_ARG, "ldc_max must be in [0, 2^22]");
-    if (p->list_layout != MD_LIST_AUTO && p->list_layout != MD_LIST_SLOTS)
-        return fail(MD_ERR_ARG, "list_layout must be 0 or 1");
+    if (p->list_layout != MD_LIST_AUTO && p->list_layout != MD_LIST_SLOTS && p->list_layout != MD_LIST_HALF)
+        return fail(MD_ERR_ARG, "list_layout must be 0, 1 or 2");
     if (p->tile_cells < 0 || p->tile_cells > 1023) return fail(MD_ERR_ARG, "tile_cells must be in [0, 1023]");
     for (int k = 0; k < 3; ++k) {
         const double m = std::floor(p->box[k] / p->rs);
@@ -200,13 +200,16 @@ static int check_list(const Ctx& c, const md_pairlist* list)
 }
 
 // The standalone force, Hessian and adjoint passes decode slot entries; a
-// state's tiled list holds offsets into staged tiles instead.
-static int check_slot_list(const Ctx& c, const md_pairlist* list)
+// state's tiled list holds offsets into staged tiles instead.  Only the force
+// pass also takes a half list (each pair once).
+static int check_slot_list(const Ctx& c, const md_pairlist* list, bool allow_half)
 {
     int rc = check_list(c, list);
     if (rc != MD_OK) return rc;
     if (list->tiled)
         return fail(MD_ERR_ARG, "pair list holds the tiled layout of a state; build one with md_build_pairlist");
+    if (list->half && !allow_half)
+        return fail(MD_ERR_ARG, "this pass needs a full list (each pair in both rows), not a half list");
     return MD_OK;
 }
 
@@ -328,8 +331,11 @@ int md_build_pairlist(const md_params* p, const double* pos, const md_cells* cel
     if ((rc = check_cells(c, cells)) != MD_OK) return rc;
     if ((rc = check_list(c, list)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
-    MD_HIP(launch_build(c.g, p->rs, pos, *cells, *list, ws, c.W, false, nullptr, stream), "md_build_pairlist");
+    const bool half = p->list_layout == MD_LIST_HALF;
+    MD_HIP(launch_build(c.g, p->rs, pos, *cells, *list, ws, c.W, false, half, nullptr, stream),
+           "md_build_pairlist");
     list->tiled = 0;
+    list->half = half ? 1 : 0;
     return MD_OK;
 }
 
@@ -341,7 +347,7 @@ int md_forces(const md_params* p, const double* pos, const md_cells* cells, cons
     if (rc != MD_OK) return rc;
     if (!pos || !force) return fail(MD_ERR_ARG, "pos or force is NULL");
     if ((rc = check_cells(c, cells)) != MD_OK) return rc;
-    if ((rc = check_slot_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_slot_list(c, list, true)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
     char* w = (char*)ws;
     float* pos32 = nullptr;
@@ -368,7 +374,7 @@ int md_hvp(const md_params* p, const double* pos, const md_cells* cells, const m
     if (rc != MD_OK) return rc;
     if (!pos || !u || !Hu) return fail(MD_ERR_ARG, "pos, u or Hu is NULL");
     if ((rc = check_cells(c, cells)) != MD_OK) return rc;
-    if ((rc = check_slot_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_slot_list(c, list, false)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
     double* part = dparam ? (double*)((char*)ws + c.W.part_a) : nullptr;
     MD_HIP(launch_hvp(c.g, c.lj, pos, cells->cell_xyz, *list, u, Hu, part, stream), "md_hvp");
@@ -384,7 +390,7 @@ int md_param_grad(const md_params* p, const double* pos, const md_cells* cells, 
     if (rc != MD_OK) return rc;
     if (!pos || !dU) return fail(MD_ERR_ARG, "pos or dU is NULL");
     if ((rc = check_cells(c, cells)) != MD_OK) return rc;
-    if ((rc = check_slot_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_slot_list(c, list, false)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
     double* part = (double*)((char*)ws + c.W.part_a);
     MD_HIP(launch_param_grad(c.g, c.lj, pos, cells->cell_xyz, *list, part, stream), "md_param_grad");
@@ -403,7 +409,7 @@ int md_adjoint_kick(const md_params* p, const double* pos, const md_cells* cells
     if (u_out && (u_out == u || u_out == out)) return fail(MD_ERR_ARG, "u_out must not alias u or out");
     if (out == u) return fail(MD_ERR_ARG, "out must not alias u");
     if ((rc = check_cells(c, cells)) != MD_OK) return rc;
-    if ((rc = check_slot_list(c, list)) != MD_OK) return rc;
+    if ((rc = check_slot_list(c, list, false)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
     AdjCoef k;
     k.alpha = coef[0];
@@ -460,12 +466,14 @@ static int build_list(const Ctx& c, const md_params* p, md_state* st, bool tiled
     int64_t* tmax = (int64_t*)((char*)st->ws + c.W.tmax);
     if (tiled) MD_HIP(launch_fill_i32((int32_t*)tmax, 0, 2 * kTileMaxSlots, s), "rebuild/tile-max");
     tick(T, MD_T_BUILD, 0, s);
-    MD_HIP(launch_build(c.g, p->rs, st->pos, st->cells, st->list, st->ws, c.W, tiled,
+    const bool half = p->list_layout == MD_LIST_HALF;
+    MD_HIP(launch_build(c.g, p->rs, st->pos, st->cells, st->list, st->ws, c.W, tiled, half,
                         (unsigned long long*)tmax, s),
            "rebuild/build");
     tick(T, MD_T_BUILD, 1, s);
     st->list_tiled = tiled ? 1 : 0;
     st->list.tiled = st->list_tiled;
+    st->list.half = half ? 1 : 0;
     st->tile_stage = 0;
     st->tile_cells = tiled ? c.g.tc : 0;
     return MD_OK;

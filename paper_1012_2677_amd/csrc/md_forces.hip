@@ -139,10 +139,12 @@ __device__ __forceinline__ float local_coord(double x, int c, double cs, double 
     return (float)l;
 }
 
-// Block-level epilogue: (PE, W) and KE partials, displacement maximum.
+// Block-level epilogue: (PE, W) and KE partials, displacement maximum.  A
+// full list meets every pair twice, so PE and W are halved (pscale = 1/2); a
+// half list passes pscale = 1.
 template <bool ENERGY, int MODE, bool VMAX, int NW = kForceBlock / 64>
 __device__ __forceinline__ void block_epilogue(const PairArgs& a, int64_t blk, double pe, double w, double ke,
-                                               double d2, double v2)
+                                               double d2, double v2, double pscale = 0.5)
 {
     __shared__ double s_r[5][NW];
     const int wave = threadIdx.x >> 6;
@@ -180,8 +182,8 @@ __device__ __forceinline__ void block_epilogue(const PairArgs& a, int64_t blk, d
             mv = fmax(mv, s_r[4][k]);
         }
         if (ENERGY) {
-            a.part_pw[2 * blk] = 0.5 * spe;
-            a.part_pw[2 * blk + 1] = 0.5 * sw;
+            a.part_pw[2 * blk] = pscale * spe;
+            a.part_pw[2 * blk + 1] = pscale * sw;
             if (MODE != MODE_FORCE) a.part_ke[blk] = 0.5 * ske;
         }
         if (MODE == MODE_KKD) {
@@ -493,6 +495,212 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed
     __builtin_amdgcn_wave_barrier();
     }
     if (ENERGY || MODE == MODE_KKD) block_epilogue<ENERGY, MODE, VMAX>(a, blk, pe, w, ke, d2, v2);
+}
+
+// Half list (Sec. 2.4 with Newton's third law): each pair is listed once, in
+// the row of one of its particles.  The rows are walked as in k_pairs_fp64 /
+// k_pairs_mixed (8 lanes per key, 8 rounds per 64-key chunk, the same pair
+// arithmetic); the key's share -g d is summed in registers, the partner's
+// share +g d goes to the force array with one device atomic per component
+// (pairs beyond the cutoff and stand-ins add nothing), and the key's sum is
+// added with atomics at the end.  The caller clears the force array first.
+// PE and W count each pair once.
+template <int U, bool ENERGY, bool MIXED>
+__global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_half(PairArgs a)
+{
+    using R = typename std::conditional<MIXED, float, double>::type;
+    using P = typename std::conditional<MIXED, float4, double4>::type;
+    constexpr int NW = kForceBlock / 64;
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    __shared__ float4 s_shift[32];
+    __shared__ P s_p[NW][64];           // own coordinates; .w: mixed, the key's slot; FP64, 1 if minimum images
+    __shared__ int64_t s_off[NW][64];
+    __shared__ int32_t s_cnt[NW][64];
+    if (MIXED) {
+        // code 27 is the stand-in of masked slots, displaced far beyond the cutoff
+        if (threadIdx.x < 32)
+            s_shift[threadIdx.x] = threadIdx.x < 27 ? make_float4(a.shift[threadIdx.x][0], a.shift[threadIdx.x][1],
+                                                                  a.shift[threadIdx.x][2], 0.0f)
+                                                    : make_float4(1.0e3f, 0.0f, 0.0f, 0.0f);
+        __syncthreads();
+    }
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, sub = lane & 7, grp = lane >> 3;
+    int64_t kb, kend;
+    block_keys(a, blk, kb, kend);
+    const R rc2 = (R)a.lj.rc2, A = (R)a.lj.A, B = (R)a.lj.B, C8 = (R)a.lj.C8;
+    const R A4 = (R)a.lj.A4, B4 = (R)a.lj.B4, C2 = (R)a.lj.C2, C0 = (R)a.lj.C0;
+    R* __restrict__ F = (R*)a.force;
+    const int64_t n = a.n;
+    double pe = 0.0, w = 0.0;
+    for (int64_t base = kb + wave * 64; base < kend; base += NW * 64) {
+    const int64_t mykey = base + lane;
+    const bool myvalid = mykey < kend;
+    {
+        const int64_t k = myvalid ? mykey : kend - 1;
+        P p;
+        if constexpr (MIXED) {
+            p = a.pos32[k];
+            p.w = __int_as_float((int)k);
+        } else {
+            p = a.pos[k];
+            p.w = (a.exact_all || boundary_cell(a.cell_xyz[k], a.nc)) ? 1.0 : 0.0;
+        }
+        s_p[wave][lane] = p;
+        s_off[wave][lane] = a.offsets[k];
+        s_cnt[wave][lane] = myvalid ? a.counts[k] : 0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    R kfx = 0, kfy = 0, kfz = 0;
+    for (int r = 0; r < 8; ++r) {
+        const int ks = (r << 3) | grp;
+        const int cmax = __builtin_amdgcn_readfirstlane(group8_max(s_cnt[wave][(r << 3) | sub]));
+        const int cnt = s_cnt[wave][ks];
+        const uint32_t* row = a.nbr + s_off[wave][ks];
+        const P pi = s_p[wave][ks];
+        R fx = 0, fy = 0, fz = 0;
+        for (int t0 = sub; t0 - sub < cmax; t0 += 8 * U) {
+            uint32_t e[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * 8;
+                e[u] = t < cnt ? row[t] : kNone;
+            }
+            P pj[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (t0 - sub + u * 8 < cmax) {
+                    if constexpr (MIXED) {
+                        // masked slots read the key itself, moved by the stand-in shift
+                        pj[u] = a.pos32[e[u] != kNone ? (e[u] & kSlotMask) : (uint32_t)__float_as_int(pi.w)];
+                    } else {
+                        // half a box away along x: beyond rs, left in place by the minimum image
+                        if (e[u] != kNone) pj[u] = a.pos[e[u] & kSlotMask];
+                        else pj[u] = make_double4(pi.x + 0.5 * a.L[0], pi.y, pi.z, 0.0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (t0 - sub + u * 8 < cmax) {
+                    R dx, dy, dz;
+                    if constexpr (MIXED) {
+                        const float4 sh = s_shift[e[u] != kNone ? (e[u] >> kCodeShift) : 27u];
+                        dx = (pj[u].x - pi.x) + sh.x;
+                        dy = (pj[u].y - pi.y) + sh.y;
+                        dz = (pj[u].z - pi.z) + sh.z;
+                    } else {
+                        dx = pj[u].x - pi.x;
+                        dy = pj[u].y - pi.y;
+                        dz = pj[u].z - pi.z;
+                        if (pi.w != 0.0) {
+                            dx -= a.L[0] * rint(dx * a.invL[0]);
+                            dy -= a.L[1] * rint(dy * a.invL[1]);
+                            dz -= a.L[2] * rint(dz * a.invL[2]);
+                        }
+                    }
+                    const R r2 = dx * dx + dy * dy + dz * dz;
+                    R r2i;
+                    if constexpr (MIXED) r2i = __builtin_amdgcn_rcpf(r2);
+                    else r2i = rcp64(r2);
+                    const R r6i = r2i * r2i * r2i;
+                    R g = r2i * r6i * (A * r6i - B) - C8;
+                    const bool in = r2 < rc2;
+                    g = in ? g : (R)0;
+                    const R gx = g * dx, gy = g * dy, gz = g * dz;
+                    fx -= gx;
+                    fy -= gy;
+                    fz -= gz;
+                    if (ENERGY) {
+                        const R V = r6i * (A4 * r6i - B4) + C2 * r2 + C0;
+                        pe += in ? (double)V : 0.0;
+                        w += (double)(g * r2);
+                    }
+                    if (in && e[u] != kNone) {
+                        const int64_t j = e[u] & kSlotMask;
+                        unsafeAtomicAdd(F + j, gx);
+                        unsafeAtomicAdd(F + n + j, gy);
+                        unsafeAtomicAdd(F + 2 * n + j, gz);
+                    }
+                }
+            }
+        }
+        fx = __shfl(group8_sum(fx), sub << 3, 64);
+        fy = __shfl(group8_sum(fy), sub << 3, 64);
+        fz = __shfl(group8_sum(fz), sub << 3, 64);
+        if (grp == r) {
+            kfx = fx;
+            kfy = fy;
+            kfz = fz;
+        }
+    }
+    if (myvalid) {
+        if (!isfinite(kfx + kfy + kfz)) atomicOr((unsigned long long*)a.flags, 1ull);
+        unsafeAtomicAdd(F + mykey, kfx);
+        unsafeAtomicAdd(F + n + mykey, kfy);
+        unsafeAtomicAdd(F + 2 * n + mykey, kfz);
+    }
+    __builtin_amdgcn_wave_barrier();
+    }
+    if (ENERGY) block_epilogue<true, MODE_FORCE, false>(a, blk, pe, w, 0.0, 0.0, 0.0, 1.0);
+}
+
+// Integrator of a half-list step: the force of a particle is complete only
+// when the whole pair pass has run, so the kicks and the drift (the fused
+// epilogue's arithmetic) run here as a pass of their own, one lane per slot,
+// in the same blocks of kForceBlock slots as the pair pass (KE partials).
+template <int MODE, bool MIXED, bool VMAX, bool ENERGY>
+__global__ __launch_bounds__(kForceBlock) void k_integrate_half(PairArgs a)
+{
+    constexpr int NW = kForceBlock / 64;
+    __shared__ double s_r[3][NW];
+    const int64_t blk = blockIdx.x;
+    const int64_t k = blk * kForceBlock + threadIdx.x;
+    double ke = 0.0, d2 = 0.0, v2 = 0.0;
+    if (k < a.n) {
+        double fx, fy, fz;
+        if constexpr (MIXED) {
+            const float* F = (const float*)a.force;
+            fx = F[k];
+            fy = F[a.n + k];
+            fz = F[2 * a.n + k];
+        } else {
+            const double* F = (const double*)a.force;
+            fx = F[k];
+            fy = F[a.n + k];
+            fz = F[2 * a.n + k];
+        }
+        if (!isfinite(fx + fy + fz)) atomicOr((unsigned long long*)a.flags, 1ull);
+        integrate_key<MODE, MIXED, VMAX>(a, k, fx, fy, fz, ke, d2, v2);
+    }
+    if (!ENERGY && MODE != MODE_KKD) return;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        if (ENERGY) ke += __shfl_xor(ke, o, 64);
+        if (MODE == MODE_KKD) d2 = fmax(d2, __shfl_xor(d2, o, 64));
+        if (VMAX) v2 = fmax(v2, __shfl_xor(v2, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_r[0][wave] = ke;
+        s_r[1][wave] = d2;
+        s_r[2][wave] = v2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ske = 0.0, m = 0.0, mv = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            ske += s_r[0][q];
+            m = fmax(m, s_r[1][q]);
+            mv = fmax(mv, s_r[2][q]);
+        }
+        if (ENERGY) a.part_ke[blk] = 0.5 * ske;
+        if (MODE == MODE_KKD) {
+            atomicMax(max_slot(a.max_d2, blk), (unsigned long long)__double_as_longlong(m));
+            if (VMAX) atomicMax(max_slot(a.max_v2, blk), (unsigned long long)__double_as_longlong(mv));
+        }
+    }
 }
 
 // Tiled force pass: one block per tile of tc cells along z.  The block first
@@ -872,6 +1080,30 @@ static void launch_pairs_mode(const Geo& g, int precision, const PairArgs& a, hi
         hipLaunchKernelGGL((k_pairs_fp64<kForceUnroll64, ENERGY, MODE, VMAX>), grid, block, 0, s, a);
 }
 
+// Half list: clear the force array, then the pair pass with atomics.
+template <bool ENERGY>
+static hipError_t launch_pairs_half(const Geo& g, int precision, const PairArgs& a, hipStream_t s)
+{
+    const int64_t words = (precision == MD_MIXED ? 3 : 6) * g.n;
+    if (hipError_t e = launch_fill_i32((int32_t*)a.force, 0, words, s)) return e;
+    const dim3 grid((unsigned)pair_blocks(g)), block(kForceBlock);
+    if (precision == MD_MIXED)
+        hipLaunchKernelGGL((k_pairs_half<kForceUnroll, ENERGY, true>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_pairs_half<kForceUnroll64, ENERGY, false>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <int MODE, bool VMAX, bool ENERGY>
+static void launch_integrate_half(const Geo& g, int precision, const PairArgs& a, hipStream_t s)
+{
+    const dim3 grid((unsigned)pair_blocks(g)), block(kForceBlock);
+    if (precision == MD_MIXED)
+        hipLaunchKernelGGL((k_integrate_half<MODE, true, VMAX, ENERGY>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_integrate_half<MODE, false, VMAX, ENERGY>), grid, block, 0, s, a);
+}
+
 static hipError_t check_tiles(const Geo& g, int precision, const TileIo& t)
 {
     if (t.stage <= 0) return hipSuccess;
@@ -890,6 +1122,10 @@ hipError_t launch_forces(const Geo& g, const LJ& lj, int precision, const double
     a.force = out.force;
     a.part_pw = out.part;
     a.flags = out.flags;
+    if (list.half) {
+        if (tio.stage > 0 || !out.force) return hipErrorInvalidValue;
+        return out.part ? launch_pairs_half<true>(g, precision, a, s) : launch_pairs_half<false>(g, precision, a, s);
+    }
     if (out.part)
         launch_pairs_mode<true, MODE_FORCE>(g, precision, a, s, tio.stage);
     else
@@ -915,6 +1151,24 @@ hipError_t launch_force_step(const Geo& g, const LJ& lj, int precision, const St
     a.max_v2 = io.max_v2;
     a.dt = io.dt;
     const bool energy = io.part_pw != nullptr;
+    if (io.list.half) {
+        // pair pass into the cleared force array, then the integrator
+        if (io.tile.stage > 0 || !io.force) return hipErrorInvalidValue;
+        hipError_t e = energy ? launch_pairs_half<true>(g, precision, a, s)
+                              : launch_pairs_half<false>(g, precision, a, s);
+        if (e != hipSuccess) return e;
+        if (io.drift && io.track_speed) {
+            if (energy) launch_integrate_half<MODE_KKD, true, true>(g, precision, a, s);
+            else launch_integrate_half<MODE_KKD, true, false>(g, precision, a, s);
+        } else if (io.drift) {
+            if (energy) launch_integrate_half<MODE_KKD, false, true>(g, precision, a, s);
+            else launch_integrate_half<MODE_KKD, false, false>(g, precision, a, s);
+        } else {
+            if (energy) launch_integrate_half<MODE_KICK, false, true>(g, precision, a, s);
+            else launch_integrate_half<MODE_KICK, false, false>(g, precision, a, s);
+        }
+        return hipGetLastError();
+    }
     if (io.drift && io.track_speed) {
         // the largest drift speed is needed by the DUTC rule only
         if (energy) launch_pairs_mode<true, MODE_KKD, true>(g, precision, a, s, io.tile.stage);

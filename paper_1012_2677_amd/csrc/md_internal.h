@@ -234,7 +234,7 @@ hipError_t launch_ref_copy(const Geo& g, const double* pos, const int32_t* cell_
 // tile_max[0 .. kTileMaxSlots) (atomic max into slot tile % kTileMaxSlots, so
 // that the atomics do not all meet at one address).
 hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cells& cells,
-                        const md_pairlist& list, void* ws, const WsLayout& L, bool tiled,
+                        const md_pairlist& list, void* ws, const WsLayout& L, bool tiled, bool half,
                         unsigned long long* tile_max, hipStream_t s);
 
 // md_forces.hip

@@ -98,11 +98,15 @@ __device__ __forceinline__ void pad_row(E* blk, uint32_t stride, uint32_t* s_row
 // candidate number self_t.  Output positions come from mbcnt of the row mask,
 // counted on from the row's start.
 //
+// Half rows (HALF): the candidates are the own cell first (ascending slots),
+// then the cells of codes 14 .. 26, so "partner slot > key slot in the own
+// cell" is "candidate number > self_t"; candidates up to self_t are dropped.
+//
 // Fast form (the key's row surely fits in the LDS row buffer): the row mask is
 // the ballot of the distance test minus the key's own lane; every lane stores,
 // those outside the mask into a spare LDS word, so there is no branch and no
 // exec-mask change per chunk.
-template <bool MINIMG, int NCH>
+template <bool MINIMG, int NCH, bool HALF>
 __device__ __forceinline__ uint32_t row_chunks_lds(const BuildArgs& a, int T, const double4& kp, int self_t,
                                                    uint32_t w0, const double* cx, const double* cy,
                                                    const double* cz, const uint32_t* meta, uint32_t* s_rows)
@@ -113,7 +117,8 @@ __device__ __forceinline__ uint32_t row_chunks_lds(const BuildArgs& a, int T, co
     for (int ch = 0; ch < NCH; ++ch) {
         if (ch * 64 < T) {
             const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
-            const bool in = r2 < a.rs2, self = lane == self_t - ch * 64;
+            const bool in = r2 < a.rs2;
+            const bool self = HALF ? ch * 64 + lane <= self_t : lane == self_t - ch * 64;
             const uint64_t m = __builtin_amdgcn_ballot_w64(in) & ~__builtin_amdgcn_ballot_w64(self);
             const uint32_t wb = (mbcnt64(m) + wpos) << 2;   // byte offset in the row buffer
             *(uint32_t*)((char*)s_rows + (__builtin_amdgcn_inverse_ballot_w64(m) ? wb : 4u * kRowBuf)) = meta[ch];
@@ -125,7 +130,7 @@ __device__ __forceinline__ uint32_t row_chunks_lds(const BuildArgs& a, int T, co
 
 // General form: entries go to the LDS row buffer while they fit in it, past
 // that straight to the cell block with a capacity test.
-template <bool MINIMG, int NCH, typename E>
+template <bool MINIMG, int NCH, typename E, bool HALF>
 __device__ __forceinline__ uint32_t row_chunks(const BuildArgs& a, E* blk, uint32_t stride, int T,
                                                const double4& kp, int self_t, uint32_t w0, const double* cx,
                                                const double* cy, const double* cz, const uint32_t* meta,
@@ -140,9 +145,11 @@ __device__ __forceinline__ uint32_t row_chunks(const BuildArgs& a, E* blk, uint3
             const bool in = r2 < a.rs2;
             uint64_t m = __builtin_amdgcn_ballot_w64(in);
             const int sl = self_t - ch * 64;          // the key's own lane in this chunk, if any
-            if (sl >= 0 && sl < 64) m &= ~(1ull << sl);
+            const bool drop = HALF ? lane <= sl : lane == sl;
+            if (HALF) m &= ~__builtin_amdgcn_ballot_w64(drop);
+            else if (sl >= 0 && sl < 64) m &= ~(1ull << sl);
             const uint32_t w = mbcnt64(m) + wpos;
-            if (in && lane != sl) {
+            if (in && !drop) {
                 if (w < (uint32_t)kRowBuf) s_rows[w] = meta[ch];
                 else if (w < stride) blk[w] = (E)meta[ch];
             }
@@ -152,7 +159,7 @@ __device__ __forceinline__ uint32_t row_chunks(const BuildArgs& a, E* blk, uint3
     return wpos;
 }
 
-template <bool MINIMG, int NCH, typename E>
+template <bool MINIMG, int NCH, typename E, bool HALF>
 __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* blk, uint32_t stride,
                                                        int T, int own_pref, int own_cnt, const double4* s_key,
                                                        const double* cx, const double* cy, const double* cz,
@@ -162,10 +169,11 @@ __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* b
     uint32_t used = 0;
     for (int kk = 0; kk < own_cnt; ++kk) {
         if (used + (uint32_t)T <= (uint32_t)kRowBuf)
-            used = row_chunks_lds<MINIMG, NCH>(a, T, s_key[kk], own_pref + kk, used, cx, cy, cz, meta, s_rows);
+            used = row_chunks_lds<MINIMG, NCH, HALF>(a, T, s_key[kk], own_pref + kk, used, cx, cy, cz, meta,
+                                                     s_rows);
         else
-            used = row_chunks<MINIMG, NCH, E>(a, blk, stride, T, s_key[kk], own_pref + kk, used, cx, cy, cz,
-                                              meta, s_rows);
+            used = row_chunks<MINIMG, NCH, E, HALF>(a, blk, stride, T, s_key[kk], own_pref + kk, used, cx, cy, cz,
+                                                    meta, s_rows);
         if (lane_id() == 0) s_rowend[kk] = used;
         pad_row<E>(blk, stride, s_rows, used, pad);
         used = row_start<E>(used);
@@ -195,7 +203,7 @@ __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* b
 // Same rows, candidates re-read from memory for every key (neighbourhoods with
 // more than NCH*64 particles or cells with more than 64 particles: never at
 // liquid densities, kept for generality).
-template <bool MINIMG, typename E>
+template <bool MINIMG, typename E, bool HALF>
 __device__ uint32_t rows_from_memory(const BuildArgs& a, E* blk, uint32_t stride, int T, int own_start,
                                      int own_cnt, const int* s_pref, const int* s_nstart, const int* s_lbase,
                                      uint32_t pad)
@@ -217,7 +225,7 @@ __device__ uint32_t rows_from_memory(const BuildArgs& a, E* blk, uint32_t stride
                 const int32_t slot = a.order ? a.order[idx] : idx;
                 const double4 p = a.pos[slot];
                 const double r2 = pair_r2<MINIMG>(a, p.x, p.y, p.z, kp.x, kp.y, kp.z);
-                pass = r2 < a.rs2 && slot != kslot;
+                pass = r2 < a.rs2 && (HALF ? (q > 13 || slot > kslot) : slot != kslot);
                 meta = s_lbase ? (uint32_t)(s_lbase[q] + (t - s_pref[q])) << 4
                                : (uint32_t)slot | ((uint32_t)q << kCodeShift);
             }
@@ -235,7 +243,7 @@ __device__ uint32_t rows_from_memory(const BuildArgs& a, E* blk, uint32_t stride
     return used;
 }
 
-template <int NCH, bool TILED>
+template <int NCH, bool TILED, bool HALF>
 __global__ __launch_bounds__(64) void k_build(BuildArgs a)
 {
     using E = typename std::conditional<TILED, uint16_t, uint32_t>::type;
@@ -268,8 +276,10 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     if (TILED && lane < 9)
         run = tile_run(a.start, a.count, wrap_cell(cx + lane / 3 - 1, nx), wrap_cell(cy + lane % 3 - 1, ny), ny, nz,
                        z0, z1);
+    // half rows take candidates from the own cell (code 13) and codes 14 .. 26
+    // only: the other 13 cells count as empty
     int cnt = 0, st = 0;
-    if (lane < 27) {
+    if (lane < 27 && (!HALF || lane >= 13)) {
         int ax = cx + lane / 9 - 1, ay = cy + (lane / 3) % 3 - 1, az = cz + lane % 3 - 1;
         ax += ax < 0 ? nx : 0;
         ax -= ax >= nx ? nx : 0;
@@ -368,14 +378,16 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
             if (ok && k >= 0 && k < own_cnt) s_key[k] = make_double4(p.x, p.y, p.z, __longlong_as_double((long long)slot));
         }
         __syncthreads();
-        used = minimg ? rows_from_registers<true, NCH, E>(a, blk, stride, T, own_pref, own_cnt, s_key, px, py, pz,
-                                                          meta, s_rows, s_rowend, pad)
-                      : rows_from_registers<false, NCH, E>(a, blk, stride, T, own_pref, own_cnt, s_key, px, py,
-                                                           pz, meta, s_rows, s_rowend, pad);
+        used = minimg ? rows_from_registers<true, NCH, E, HALF>(a, blk, stride, T, own_pref, own_cnt, s_key, px,
+                                                                py, pz, meta, s_rows, s_rowend, pad)
+                      : rows_from_registers<false, NCH, E, HALF>(a, blk, stride, T, own_pref, own_cnt, s_key, px,
+                                                                 py, pz, meta, s_rows, s_rowend, pad);
     } else if (own_cnt > 0) {
         const int* lb = TILED ? s_lbase : nullptr;
-        used = minimg ? rows_from_memory<true, E>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart, lb, pad)
-                      : rows_from_memory<false, E>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart, lb, pad);
+        used = minimg ? rows_from_memory<true, E, HALF>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart,
+                                                        lb, pad)
+                      : rows_from_memory<false, E, HALF>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart,
+                                                         lb, pad);
     }
     if (lane == 0) {
         a.cell_rows[c] = used > 0x7FFFFFFFu ? 0x7FFFFFFF : (int32_t)used;
@@ -384,7 +396,7 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
 }
 
 hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cells& cells,
-                        const md_pairlist& list, void* ws, const WsLayout& L, bool tiled,
+                        const md_pairlist& list, void* ws, const WsLayout& L, bool tiled, bool half,
                         unsigned long long* tile_max, hipStream_t s)
 {
     BuildArgs a;
@@ -408,13 +420,15 @@ hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cel
     a.status = list.status;
     a.tc = g.tc;
     a.tile_max = tile_max;
-    if (tiled && (!cells.sorted || g.tc <= 0 || !tile_max)) return hipErrorInvalidValue;
+    if (tiled && (half || !cells.sorted || g.tc <= 0 || !tile_max)) return hipErrorInvalidValue;
     // status[2] (overflow) is cleared by the statistics kernel of the previous
     // build or by the caller; clear it here on the stream before the build.
     hipError_t e = launch_fill_i32((int32_t*)list.status, 0, 8, s);
     if (e != hipSuccess) return e;
-    if (tiled) hipLaunchKernelGGL((k_build<kBuildChunks, true>), dim3((unsigned)g.ncell), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL((k_build<kBuildChunks, false>), dim3((unsigned)g.ncell), dim3(64), 0, s, a);
+    const dim3 grid((unsigned)g.ncell);
+    if (tiled) hipLaunchKernelGGL((k_build<kBuildChunks, true, false>), grid, dim3(64), 0, s, a);
+    else if (half) hipLaunchKernelGGL((k_build<kBuildChunks, false, true>), grid, dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((k_build<kBuildChunks, false, false>), grid, dim3(64), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_list_stats(a.cell_rows, g.ncell, list.status, (long long*)((char*)ws + L.red), s);

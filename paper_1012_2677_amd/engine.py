@@ -22,7 +22,7 @@ def _ptr(t: torch.Tensor | None) -> int | None:
 REBUILD_RULES = {"half_skin": A.MD_REBUILD_HALF_SKIN, "dutc_ldc": A.MD_REBUILD_DUTC_LDC}
 
 
-LIST_LAYOUTS = {"auto": A.MD_LIST_AUTO, "slots": A.MD_LIST_SLOTS}
+LIST_LAYOUTS = {"auto": A.MD_LIST_AUTO, "slots": A.MD_LIST_SLOTS, "half": A.MD_LIST_HALF}
 
 
 def make_params(n, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precision="fp64",

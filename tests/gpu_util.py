@@ -24,7 +24,8 @@ def to_pos4(q: np.ndarray) -> torch.Tensor:
 class Standalone:
     """Grid + pair list + workspace for standalone entry-point calls."""
 
-    def __init__(self, q, L, *, rs=2.8, rc=2.5, eps=1.0, sigma=1.0, precision="fp64", cell_stride=None):
+    def __init__(self, q, L, *, rs=2.8, rc=2.5, eps=1.0, sigma=1.0, precision="fp64", cell_stride=None,
+                 list_layout="auto"):
         from paper_1012_2677_amd import _abi as A
         from paper_1012_2677_amd.engine import Grid, PairList, Workspace, make_params, stream_handle
 
@@ -32,7 +33,7 @@ class Standalone:
         self.q = np.ascontiguousarray(q, dtype=np.float64)
         self.n = self.q.shape[0]
         self.params = make_params(self.n, L, eps=eps, sigma=sigma, rc=rc, rs=rs, precision=precision,
-                                  resort_every=0)
+                                  resort_every=0, list_layout=list_layout)
         dev = device()
         self.grid = Grid(self.params, dev)
         self.plist = PairList(self.params, self.grid.ncell, dev, cell_stride)

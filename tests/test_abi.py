@@ -53,7 +53,7 @@ int main() {
   std::printf("md_state %zu\n", sizeof(md_state));
   OFF(md_params, precision); OFF(md_params, resort_every); OFF(md_params, dt);
   OFF(md_cells, cell_of); OFF(md_cells, order);
-  OFF(md_pairlist, cell_stride); OFF(md_pairlist, status); OFF(md_pairlist, tiled);
+  OFF(md_pairlist, cell_stride); OFF(md_pairlist, status); OFF(md_pairlist, tiled); OFF(md_pairlist, half);
   OFF(md_state, cells); OFF(md_state, list); OFF(md_state, energy); OFF(md_state, ws_bytes);
   OFF(md_state, timers); OFF(md_state, step); OFF(md_state, phase); OFF(md_state, list_valid);
   OFF(md_params, list_layout); OFF(md_params, tile_cells); OFF(md_state, list_tiled); OFF(md_state, tile_stage);
@@ -103,7 +103,7 @@ def test_cell_dims_and_workspace(A):
 @pytest.mark.parametrize("kw,code", [
     (dict(n=0), -1), (dict(n=1 << 27), -1), (dict(L=8.0), -2), (dict(L=3000.0), -2),
     (dict(rc=3.0, rs=2.8), -1), (dict(eps=-1.0), -1), (dict(precision=7), -1),
-    (dict(list_layout=5), -1), (dict(tile_cells=-1), -1), (dict(tile_cells=1024), -1),
+    (dict(list_layout=3), -1), (dict(tile_cells=-1), -1), (dict(tile_cells=1024), -1),
 ])
 def test_validation_codes(A, kw, code):
     p = _params(A, **{k: v for k, v in kw.items() if k not in ("precision", "list_layout", "tile_cells")})
@@ -138,6 +138,12 @@ def test_null_pointers_rejected_before_launch(A):
     assert e.value.code == A.MD_ERR_ARG
 
 
+def test_half_layout_accepted(A):
+    p = _params(A, list_layout="half")
+    assert p.list_layout == A.MD_LIST_HALF
+    assert A.md_cell_dims(p) == (7, 7, 7)
+
+
 def test_tiled_list_rejected_by_standalone_passes(A):
     # a state's tiled list holds tile offsets, not slots: the standalone
     # passes refuse it before any launch; the same list marked as slot
@@ -164,6 +170,12 @@ def test_tiled_list_rejected_by_standalone_passes(A):
             with pytest.raises(A.MdError) as e:
                 call()
             assert e.value.code == code, (tiled, e.value)
+    # a half list: the force pass takes it, the Hessian and adjoint passes do not
+    plist.half = 1
+    for k, call in enumerate(calls):
+        with pytest.raises(A.MdError) as e:
+            call()
+        assert e.value.code == (A.MD_ERR_WORKSPACE if k == 0 else A.MD_ERR_ARG), (k, e.value)
 
 
 def test_workspace_too_small(A):
