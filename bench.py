@@ -41,7 +41,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def force_bytes_per_key(mean_entries: float, mixed: bool, tiled: bool = False) -> float:
+def force_bytes_per_key(mean_entries: float, mixed: bool, tiled: bool = False, half: bool = False) -> float:
     """Algorithmic HBM bytes of one key in the timed force pass, which inside a
     run is fused with the integrator (second half kick, next first half kick,
     drift): row offset (8) + row length (4) + 4 bytes per slot entry or 2 per
@@ -51,11 +51,16 @@ def force_bytes_per_key(mean_entries: float, mixed: bool, tiled: bool = False) -
     write (48), reference position (24), position written (32; mixed mode also
     reads the FP64 position, 32, its packed cell, 4, and writes new local
     coordinates, 16).  Partner coordinates are re-reads of coordinates counted
-    once as keys (in the tiled pass: staged into LDS from the same array)."""
+    once as keys (in the tiled pass: staged into LDS from the same array).
+    A half list (each pair once, mean_entries of them per key) is not fused:
+    the force array (12 B per key in mixed mode, 24 in FP64) is written by the
+    clear, read and written once by the atomics of the pair pass (counted
+    once) and read by the integrator pass, 4 times in all."""
     idx = 8 + 4 + (2 if tiled else 4) * mean_entries
+    fbytes = 4 * (12 if mixed else 24) if half else 0
     if mixed:
-        return idx + 16 + 32 + 4 + 48 + 24 + 32 + 16
-    return idx + 32 + (0 if tiled else 4) + 48 + 24 + 32
+        return idx + 16 + 32 + 4 + 48 + 24 + 32 + 16 + fbytes
+    return idx + 32 + (0 if tiled else 4) + 48 + 24 + 32 + fbytes
 
 
 def force_sources_sha256() -> str:
@@ -162,6 +167,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
     dt = t2 - t1
     entries = int(e.plist.status[0].item())
     tiled = int(e.state.list_tiled)
+    half = int(e.state.list.half)
     tim = e.timer_dict()
     rebuilds = e.rebuilds - reb0
     log(f"[bench] {precision}: {steps} steps in {dt:.3f}s, {rebuilds} rebuilds, timers {tim}")
@@ -180,6 +186,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
         "ldc_checks_kept": [e.ldc_stats[0] - ldc0[0], e.ldc_stats[1] - ldc0[1]],
         "mean_list_entries": entries / n,
         "list_tiled": tiled,
+        "list_half": half,
         "tile_cells": int(e.state.tile_cells),
         "timers_ms": {k: [round(m, 3), c] for k, (m, c) in tim.items()},
         "energy_per_particle_start": float(e0[3] / n),
@@ -193,7 +200,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
     fm, fl = tim.get("force", (0.0, 0))
     if fl > 0:
         avg_ms = fm / fl
-        per_launch = n * force_bytes_per_key(entries / n, precision == "mixed", bool(tiled))
+        per_launch = n * force_bytes_per_key(entries / n, precision == "mixed", bool(tiled), bool(half))
         gbs = per_launch / (avg_ms * 1e-3) / 1e9
         out["force_kernel"] = {"avg_ms": avg_ms, "launches": fl, "algorithmic_bytes_per_launch": per_launch,
                                "achieved_GBs": gbs}
@@ -239,8 +246,9 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="also time the headline precision without re-sorting, labels shuffled first")
     ap.add_argument("--sample-every", type=int, default=50)
-    ap.add_argument("--list-layout", default="auto", choices=["auto", "slots"],
-                    help="list of the simulation state: tiled when possible (auto) or slot entries")
+    ap.add_argument("--list-layout", default="auto", choices=["auto", "slots", "half"],
+                    help="list of the simulation state: tiled when possible (auto), slot entries (slots) "
+                         "or each pair once with atomic partner forces (half)")
     ap.add_argument("--tile-cells", type=int, default=0, help="tile length along z in cells (0 = automatic)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
@@ -287,7 +295,10 @@ def main():
     log(f"[bench] plain copy: {copy['GBs']:.0f} GB/s")
     roofline = None
     if fk:
-        if modes[0] == "mixed":
+        if head.get("list_half"):
+            # not one kernel: the force clear, k_pairs_half and k_integrate_half
+            kname = "force_step_half" + ("" if modes[0] == "mixed" else "_fp64")
+        elif modes[0] == "mixed":
             kname = "k_pairs_tiled" if head.get("list_tiled") else "k_pairs_mixed"
         else:
             kname = "k_pairs_tiled_fp64" if head.get("list_tiled") else "k_pairs_fp64"
