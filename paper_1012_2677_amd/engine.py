@@ -138,8 +138,10 @@ class Engine:
     "half_skin" or "dutc_ldc" (DUTC, then the large-displacement check with at
     most ldc_max members).  list_layout: "auto" (in mixed precision, the tiled
     list whose force pass stages each tile's neighbourhood in LDS, whenever the
-    slots are in cell order) or "slots"; tile_cells: tile length along z in
-    cells (0 = automatic).
+    slots are in cell order), "slots", or "half" (each pair once, Sec. 2.4:
+    the partner's force added by device atomics, the integrator in a pass of
+    its own; much slower on this GPU, kept for comparison); tile_cells: tile
+    length along z in cells (0 = automatic).
     """
 
     def __init__(self, pos, vel, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precision="fp64",

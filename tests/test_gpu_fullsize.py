@@ -12,7 +12,8 @@ on sampled particles the oracle can check one by one:
 
 The state is first advanced some steps (a disordered fluid with several
 rebuilds and re-sorts behind it), then md_prepare rebuilds the list at the
-current positions.
+current positions.  The half list (each pair once) gets the same row and
+force checks at 32M, its rows cut from the oracle's sets by the half rule.
 """
 
 import numpy as np
@@ -101,3 +102,56 @@ def test_largest_workload_sampled_parity(ref):
     e.prepare()
     assert int(e.state.list_tiled) == 1
     _check_state(ref, e, L, _sample_ids(n, 1024, 2), 1e-5)
+
+
+def _cell_offset(a, b, n):
+    d = (b - a) % n
+    return np.where(d == n - 1, -1, d)
+
+
+def test_half_list_full_size_sampled_parity(ref):
+    """32,000,000 particles, mixed, half list (each pair once): the rows of
+    sampled keys equal the oracle's neighbour sets cut by the half rule
+    (partners in cells of stencil code above 13, or in the key's cell with a
+    larger slot), in (code, slot) order; the forces on the sampled particles,
+    which collect the atomics of every key, equal the oracle's (1e-5)."""
+    from paper_1012_2677_amd import Engine
+
+    cfg = li.CONFIGS["lj32m"]
+    q, L = li.fcc_lattice(cfg["n_fcc"])
+    v = li.maxwell_boltzmann(q.shape[0], cfg["T"], seed=0)
+    n = q.shape[0]
+    e = Engine(q, v, L, rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], dt=cfg["dt"], precision="mixed",
+               resort_every=1, list_layout="half", device="cuda:0")
+    del q, v
+    e.step(20)
+    e.prepare()
+    assert int(e.state.list.half) == 1 and int(e.state.list_tiled) == 0
+    ids = _sample_ids(n, 2048, 3)
+    q = e.positions()
+    nc, _ = ref.cell_dims(L, e.params.rs)
+    _, count, start, order = ref.bin_cells(q, L, nc)
+    grid = (nc, count, start, order)
+    id_of_slot = e.id.cpu().numpy()
+    slot_of_id = np.empty(n, np.int64)
+    slot_of_id[id_of_slot] = np.arange(n)
+    cxyz = e.grid.cell_xyz.cpu().numpy()
+    slots = slot_of_id[ids]
+    kidx, pslot, codes = G.rows_for_slots(e.plist, slots)
+    ref_rows = ref.neighbors_sample(q, L, ids, rs=e.params.rs, grid=grid)
+    for k in range(len(ids)):
+        sk = slots[k]
+        sj = slot_of_id[ref_rows[k]]
+        a, b = cxyz[sk], cxyz[sj]
+        sx = _cell_offset(a & 1023, b & 1023, nc[0])
+        sy = _cell_offset((a >> 10) & 1023, (b >> 10) & 1023, nc[1])
+        sz = _cell_offset((a >> 20) & 1023, (b >> 20) & 1023, nc[2])
+        code = (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1)
+        keep = (code > 13) | ((code == 13) & (sj > sk))
+        want = np.lexsort((sj[keep], code[keep]))
+        row = kidx == k
+        assert np.array_equal(pslot[row], sj[keep][want]), ids[k]
+        assert np.array_equal(codes[row], code[keep][want]), ids[k]
+    F = e.forces()[ids]
+    Fr, S, _, _, _ = ref.forces_sample(q, L, ids, rc=e.params.rc, rs=e.params.rs, grid=grid)
+    assert G.force_error(F, Fr, S) <= 1e-5
