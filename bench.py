@@ -258,8 +258,8 @@ def main():
                     help="only run a plain 1 GiB device copy (the reference kernel for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how the "
-              "domain decomposition would shard it). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (the domain decomposition that would "
+              "shard the work over GPUs is not built). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
