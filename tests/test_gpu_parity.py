@@ -53,10 +53,27 @@ def _case(name):
     if name == "small_box":
         q, L = li.jittered_fcc(5, amp=0.15, seed=9)  # L = 10: 3 cells per axis
         return q, [L] * 3
+    if name == "clump":
+        # 100 extra particles within 1.2 of one cell's centre: that cell holds
+        # more particles than the build keeps in LDS, so its rows (and those of
+        # its neighbours, whose candidates exceed the register chunks) are
+        # found by the build's re-reading path
+        L = 21.5
+        rng = np.random.default_rng(11)
+        base = li.uniform_box(5003, L, seed=7)
+        c = np.array([3.5, 10.0, 17.9])
+        d = rng.standard_normal((100, 3))
+        d *= (1.2 * rng.random((100, 1)) ** (1.0 / 3.0)) / np.linalg.norm(d, axis=1, keepdims=True)
+        return li.wrap_into_box(np.concatenate([base, c + d]), L), [L] * 3
+    if name == "dense":
+        # rho = 1.6 in a 3-cell box: ~59 particles per cell, every full and
+        # half neighbourhood beyond the build's register chunks
+        L = 10.0
+        return li.uniform_box(1600, L, seed=12), [L] * 3
     raise KeyError(name)
 
 
-CASES = ["fcc10", "jitter12", "uniform_ragged", "aniso", "aniso_jitter", "small_box"]
+CASES = ["fcc10", "jitter12", "uniform_ragged", "aniso", "aniso_jitter", "small_box", "clump", "dense"]
 
 
 @pytest.fixture(autouse=True, scope="module")
@@ -143,7 +160,8 @@ def test_pairlist_overflow_reported(ref):
     assert int(st2[1]) == need
 
 
-@pytest.mark.parametrize("name", ["fcc10", "jitter12", "ragged_jitter", "aniso", "aniso_jitter", "small_box"])
+@pytest.mark.parametrize("name", ["fcc10", "jitter12", "ragged_jitter", "aniso", "aniso_jitter", "small_box", "clump",
+                                  "dense"])
 def test_forces_fp64(ref, name):
     q, L = _case(name)
     s = G.Standalone(q, L)
