@@ -15,7 +15,9 @@ reads partners from LDS.  These tests check:
   * runs with the tiled list match the oracle's run (FP64: energy log to
     1e-10 relative, same rebuilds; mixed: energy per particle to 1e-5) and the
     slot-layout run;
-  * anisotropic boxes with 3-cell axes (3 neighbour columns, one-cell tiles).
+  * anisotropic boxes with 3-cell axes (3 neighbour columns, one-cell tiles);
+  * crowded cells (a clump, a rho = 1.6 box), where the build re-reads its
+    candidates from memory: rows still equal the slot rows and the oracle's.
 """
 
 import numpy as np
@@ -209,3 +211,35 @@ def test_standalone_force_pass_refuses_a_tiled_state_list(precision):
         want = e.force.double().cpu().numpy()
         tol = 1e-12 if precision == "fp64" else 1e-5
         assert np.abs(got - want).max() <= tol * np.abs(want).max()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("name", ["clump", "dense"])
+def test_tiled_rows_in_crowded_cells(ref, precision, name):
+    # cells beyond the build's LDS key buffer and neighbourhoods beyond its
+    # register chunks: the tiled rows come from the path that re-reads the
+    # candidates, and must still equal the slot rows and the oracle's sets
+    from tests.test_gpu_parity import _case
+
+    q, L = _case(name)
+    v = np.zeros_like(q)
+    t = _engine(q, v, L, precision=precision)
+    s = _engine(q, v, L, precision=precision, list_layout="slots")
+    t.prepare()
+    s.prepare()
+    assert int(t.state.list_tiled) == 1 and int(s.state.list_tiled) == 0
+    assert torch.equal(t.id, s.id)
+    n = q.shape[0]
+    slots = np.arange(n)
+    kt, pt = G.rows_for_slots_state(t, slots)
+    ks, ps = G.rows_for_slots_state(s, slots)
+    assert np.array_equal(kt, ks)
+    assert np.array_equal(pt, ps)
+    ids = t.id.cpu().numpy()
+    rows = ref.neighbors_sample(t.positions(), L, ids, rs=2.8)
+    for k in range(n):
+        assert np.array_equal(np.sort(ids[pt[kt == k]]), rows[k])
+    if precision == "fp64":
+        idx = np.arange(n, dtype=np.int64)
+        Fr, S, _, _, _ = ref.forces_sample(t.positions(), L, idx)
+        assert G.force_error(t.forces(), Fr, S) <= 1e-12
