@@ -75,7 +75,8 @@ def test_half_list_adversarial_ulp(ref):
 
 
 @pytest.mark.parametrize("precision,name", [("fp64", n) for n in ("fcc10", "jitter12", "ragged_jitter", "aniso",
-                                                                  "aniso_jitter", "small_box", "clump", "dense")]
+                                                                  "aniso_jitter", "small_box", "clump", "dense",
+                                                                  "slab")]
                          + [("mixed", n) for n in ("jitter12", "ragged_jitter", "aniso_jitter", "small_box")])
 def test_half_forces_match_oracle(ref, precision, name):
     q, L = _case(name)

@@ -70,10 +70,17 @@ def _case(name):
         # half neighbourhood beyond the build's register chunks
         L = 10.0
         return li.uniform_box(1600, L, seed=12), [L] * 3
+    if name == "slab":
+        # particles in x < L/2 only: empty cells, and in the tiled list whole
+        # tiles without keys next to tiles with neighbours to stage
+        L = 21.5
+        q = li.uniform_box(4969, L, seed=13)
+        q[:, 0] *= 0.5
+        return q, [L] * 3
     raise KeyError(name)
 
 
-CASES = ["fcc10", "jitter12", "uniform_ragged", "aniso", "aniso_jitter", "small_box", "clump", "dense"]
+CASES = ["fcc10", "jitter12", "uniform_ragged", "aniso", "aniso_jitter", "small_box", "clump", "dense", "slab"]
 
 
 @pytest.fixture(autouse=True, scope="module")
@@ -161,7 +168,7 @@ def test_pairlist_overflow_reported(ref):
 
 
 @pytest.mark.parametrize("name", ["fcc10", "jitter12", "ragged_jitter", "aniso", "aniso_jitter", "small_box", "clump",
-                                  "dense"])
+                                  "dense", "slab"])
 def test_forces_fp64(ref, name):
     q, L = _case(name)
     s = G.Standalone(q, L)

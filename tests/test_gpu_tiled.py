@@ -17,7 +17,8 @@ reads partners from LDS.  These tests check:
     slot-layout run;
   * anisotropic boxes with 3-cell axes (3 neighbour columns, one-cell tiles);
   * crowded cells (a clump, a rho = 1.6 box), where the build re-reads its
-    candidates from memory: rows still equal the slot rows and the oracle's.
+    candidates from memory, and a half-empty box (tiles without keys): rows
+    still equal the slot rows and the oracle's.
 """
 
 import numpy as np
@@ -214,11 +215,12 @@ def test_standalone_force_pass_refuses_a_tiled_state_list(precision):
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-@pytest.mark.parametrize("name", ["clump", "dense"])
-def test_tiled_rows_in_crowded_cells(ref, precision, name):
+@pytest.mark.parametrize("name", ["clump", "dense", "slab"])
+def test_tiled_rows_in_crowded_or_empty_cells(ref, precision, name):
     # cells beyond the build's LDS key buffer and neighbourhoods beyond its
-    # register chunks: the tiled rows come from the path that re-reads the
-    # candidates, and must still equal the slot rows and the oracle's sets
+    # register chunks (the tiled rows come from the path that re-reads the
+    # candidates), or empty cells and tiles without keys: rows must still
+    # equal the slot rows and the oracle's sets
     from tests.test_gpu_parity import _case
 
     q, L = _case(name)
