@@ -91,7 +91,7 @@ extern "C" {
  *   is 16 times the index of the partner in the tile's neighbourhood (its
  *   byte offset in the copy of the runs of cells around the tile in the 9
  *   columns next to it, which the force pass stages in LDS: 16 bytes per
- *   particle in MD_MIXED, 32 in MD_FP64, where the offset is twice the
+ *   particle in MD_MIXED, 24 in MD_FP64, where the offset is 1.5 times the
  *   entry); otherwise, and always with MD_LIST_SLOTS, entries are
  *   32-bit partner slots as in md_build_pairlist.  Both layouts hold the same
  *   pairs in the same row order.

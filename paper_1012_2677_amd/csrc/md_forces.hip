@@ -706,16 +706,19 @@ __global__ __launch_bounds__(kForceBlock) void k_integrate_half(PairArgs a)
 // Tiled force pass: one block per tile of tc cells along z.  The block first
 // copies the tile's neighbourhood (the runs of cells z0-1 .. z1 of the 9
 // columns around it, in the order of the list build) into LDS; entries are
-// 16-bit byte offsets into that copy (16 bytes per particle) and a row of odd
-// length ends with a stand-in partner beyond the cutoff.
+// 16 x the partner's index in that copy (its byte offset at 16 bytes per
+// particle) and a row of odd length ends with a stand-in partner beyond the
+// cutoff.
 //   Mixed: each particle is staged from its local coordinates as
 //   (x + sx cs_x, y + sy cs_y, z, j) with (sx, sy) its column offset and j its
 //   position in the run.  With the key's (x, y, z) local and its own run
 //   position jk, d = (x_j - x_i, y_j - y_i, (z_j - z_i) + (j - jk) cs_z), the
 //   last term exact ((j - jk) is -1, 0 or 1).
-//   FP64: particles are staged as their FP64 positions (32 bytes, the entry
-//   doubled), and displacements take the minimum image in tiles that touch
-//   the box boundary (a no-op for pairs that do not wrap), as in k_pairs_fp64.
+//   FP64: particles are staged as their FP64 positions (24 bytes, so the
+//   byte offset is 1.5 x the entry: a copy of ~1600 particles leaves room for
+//   4 blocks per CU, which 32-byte records would cut to 3), and
+//   displacements take the minimum image in tiles that touch the box
+//   boundary (a no-op for pairs that do not wrap), as in k_pairs_fp64.
 // The tile's keys are split evenly over the waves.  In each 64-key chunk the
 // rows are walked in rounds of 8 keys grouped by row length, the first
 // kPrefetch entries of all 8 rounds loaded up front, two per 32-bit load.  Key
@@ -732,17 +735,24 @@ constexpr int kPrefetch = MD_TILE_PREFETCH;     // row entries per key loaded up
 
 template <bool MIXED>
 struct TileT;
+// A staged FP64 particle is its position alone (24 bytes, no padding), so a
+// tile's neighbourhood takes three quarters of the LDS a double4 copy would.
+struct D3 {
+    double x, y, z;
+};
 template <>
 struct TileT<true> {
     using R = float;
     using V4 = float4;
-    static constexpr int kScale = 1;   // entry -> byte offset
+    using S = float4;                   // staged particle: 16 bytes, byte offset = entry
+    __device__ static uint32_t off(uint32_t e) { return e; }
 };
 template <>
 struct TileT<false> {
     using R = double;
     using V4 = double4;
-    static constexpr int kScale = 2;
+    using S = D3;                       // 24 bytes: byte offset = 1.5 x entry
+    __device__ static uint32_t off(uint32_t e) { return e + (e >> 1); }
 };
 
 template <int U, bool ENERGY, int MODE, bool VMAX, bool MIXED>
@@ -750,10 +760,10 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
 {
     using R = typename TileT<MIXED>::R;
     using V4 = typename TileT<MIXED>::V4;
-    constexpr int SC = TileT<MIXED>::kScale;
+    using S = typename TileT<MIXED>::S;
     constexpr int NW = kTileBlock / 64;
     extern __shared__ float4 s_lds[];     // staged neighbourhood, then one stand-in
-    V4* s_nb = (V4*)s_lds;
+    S* s_nb = (S*)s_lds;
     __shared__ uint8_t s_perm[NW][64];
     __shared__ int32_t s_run[9][4];
     __shared__ int32_t s_base[10];
@@ -798,7 +808,7 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         } else {
             double x = ((double)cx + 0.5) * a.cs[0] + 0.5 * a.L[0];
             x -= x >= a.L[0] ? a.L[0] : 0.0;
-            s_nb[b] = make_double4(x, ((double)cy + 0.5) * a.cs[1], ((double)z0 + 0.5) * a.cs[2], 0.0);
+            s_nb[b] = D3{x, ((double)cy + 0.5) * a.cs[1], ((double)z0 + 0.5) * a.cs[2]};
         }
     }
     __syncthreads();
@@ -829,7 +839,7 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
                 s_nb[s_base[col] + i] = make_float4(q.x + (float)(col / 3 - 1) * csx, q.y + (float)(col % 3 - 1) * csy,
                                                     q.z, (float)j);
             } else {
-                s_nb[s_base[col] + i] = q;
+                s_nb[s_base[col] + i] = D3{q.x, q.y, q.z};
             }
         };
 #pragma unroll
@@ -864,8 +874,8 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     const int wave = tid >> 6, lane = tid & 63, sub = lane & 7, grp = lane >> 3;
     const R rc2 = (R)a.lj.rc2, A = (R)a.lj.A, B = (R)a.lj.B, C8 = (R)a.lj.C8;
     double pe = 0.0, w = 0.0, ke = 0.0, d2 = 0.0, v2 = 0.0;
-    auto nb = [&](uint32_t e) { return *(const V4*)((const char*)s_nb + SC * e); };
-    auto pair = [&](const V4& pj, const V4& li, R& fx, R& fy, R& fz) {
+    auto nb = [&](uint32_t e) { return *(const S*)((const char*)s_nb + TileT<MIXED>::off(e)); };
+    auto pair = [&](const auto& pj, const V4& li, R& fx, R& fy, R& fz) {
         R dx = pj.x - li.x;
         R dy = pj.y - li.y;
         R dz;
@@ -975,7 +985,7 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
             if (16 * u < cmax) {
-                const V4 p0 = nb(E[r][u] & 0xFFFFu), p1 = nb(E[r][u] >> 16);
+                const S p0 = nb(E[r][u] & 0xFFFFu), p1 = nb(E[r][u] >> 16);
                 pair(p0, li, fx, fy, fz);
                 pair(p1, li, fx, fy, fz);
             }
@@ -1070,7 +1080,7 @@ static void launch_pairs_mode(const Geo& g, int precision, const PairArgs& a, hi
                                dim3(kTileBlock), sizeof(float4) * (size_t)(stage + 1), s, a);
         else
             hipLaunchKernelGGL((k_pairs_tiled<kForceUnroll64, ENERGY, MODE, VMAX, false>), dim3((unsigned)g.ntile),
-                               dim3(kTileBlock), sizeof(double4) * (size_t)(stage + 1), s, a);
+                               dim3(kTileBlock), sizeof(D3) * (size_t)(stage + 1), s, a);
         return;
     }
     const dim3 grid((unsigned)pair_blocks(g)), block(kForceBlock);
