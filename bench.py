@@ -210,6 +210,81 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
     return out
 
 
+def adjoint_bytes_per_key(mean_entries: float) -> float:
+    """Algorithmic HBM bytes of one key in md_adjoint_kick (the fused adjoint
+    kick of the reverse sweep, out accumulated and u_out written): row offset
+    (8) + row length (4) + 4 per slot entry + own position (32) + packed cell
+    (4) + u (24) + out read and written (48) + u_out written (24).  Partner
+    positions and u are re-reads of arrays counted once as keys."""
+    return 8 + 4 + 4 * mean_entries + 32 + 4 + 24 + 48 + 24
+
+
+def grad_mode(cfg, steps, ckpt, seed, reps=50):
+    """Gradient of the trajectory observable O = (1/K) sum_k U(q_k) with
+    respect to q0, eps and sigma (TrajectoryMeanPE: forward run storing a
+    checkpoint every ckpt steps, then the checkpointed reverse sweep), timed
+    end to end after an untimed short one; then md_adjoint_kick alone at the
+    starting positions, timed with HIP events on the stream it runs on."""
+    import torch
+
+    import lj_inputs as li
+    from paper_1012_2677_amd import TrajectoryMeanPE
+    from paper_1012_2677_amd.autograd import Field
+
+    dev = torch.device("cuda", 0)
+    q, L = li.fcc_lattice(cfg["n_fcc"], cfg["rho"])
+    v = li.initial_velocities(cfg, q.shape[0], seed=seed)
+    n = q.shape[0]
+    rs, dt = cfg["rc"] + cfg["skin"], cfg["dt"]
+    qt = torch.tensor(q, dtype=torch.float64, device=dev, requires_grad=True)
+    vt = torch.tensor(v, dtype=torch.float64, device=dev)
+    eps = torch.tensor(1.0, dtype=torch.float64, device=dev, requires_grad=True)
+    sig = torch.tensor(1.0, dtype=torch.float64, device=dev, requires_grad=True)
+    TrajectoryMeanPE.apply(qt, vt, eps, sig, L, ckpt, ckpt, dt, cfg["rc"], rs).backward()
+    qt.grad = eps.grad = sig.grad = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    O = TrajectoryMeanPE.apply(qt, vt, eps, sig, L, steps, ckpt, dt, cfg["rc"], rs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    O.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(f"[bench] gradients: N={n}, {steps} steps, checkpoint every {ckpt}: forward {t1 - t0:.3f}s, "
+        f"reverse sweep {t2 - t1:.3f}s, dO/deps {eps.grad.item():.6f}, dO/dsigma {sig.grad.item():.6f}")
+    f = Field(n, L, 1.0, 1.0, cfg["rc"], rs, dev)
+    f.params.dt = dt
+    f.set_positions(qt.detach())
+    g = torch.Generator(device=dev).manual_seed(seed)
+    u = torch.randn((3, n), dtype=torch.float64, device=dev, generator=g)
+    out = torch.zeros_like(u)
+    u_out = torch.empty_like(u)
+    acc = torch.zeros(2, dtype=torch.float64, device=dev)
+    coef = (1.0, -0.5 * dt, -1.0 / steps, 0.5 * dt, 1.0 / steps)
+    f.adjoint_kick(u, out, u_out, coef, acc)
+    stream = torch.cuda.current_stream(dev)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        f.adjoint_kick(u, out, u_out, coef, acc)
+    end.record(stream)
+    torch.cuda.synchronize()
+    avg_ms = start.elapsed_time(end) / reps
+    entries = int(f.plist.status[0].item())
+    per_call = n * adjoint_bytes_per_key(entries / n)
+    gbs = per_call / (avg_ms * 1e-3) / 1e9
+    log(f"[bench] md_adjoint_kick: {avg_ms:.3f} ms per call, {gbs:.0f} GB/s algorithmic")
+    return {
+        "n": n, "steps": steps, "checkpoint_every": ckpt,
+        "forward_s": t1 - t0, "reverse_s": t2 - t1,
+        "value": n * steps / (t2 - t0), "unit": "particle-steps/s (forward + reverse sweep)",
+        "dO_deps": eps.grad.item(), "dO_dsigma": sig.grad.item(),
+        "adjoint_kernel": {"kernel": "k_adjoint (md_adjoint_kick)", "bound": "hbm", "avg_call_ms": avg_ms,
+                           "algorithmic_bytes_per_call": int(per_call), "achieved": round(gbs, 1),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)},
+    }
+
+
 def cpu_baseline(cfg, seconds_target=20.0):
     """The oracle as it is (plain C, one thread) on a bounded sample of the same
     workload: the same density, initial velocities, dt and skin on a
@@ -251,6 +326,9 @@ def main():
                          "or each pair once with atomic partner forces (half)")
     ap.add_argument("--tile-cells", type=int, default=0, help="tile length along z in cells (0 = automatic)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--gradients", action="store_true",
+                    help="also time the gradient of the trajectory mean PE (on by default for lj256k)")
+    ap.add_argument("--ckpt", type=int, default=20, help="checkpoint interval of the gradient run")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--modes", default=None, help="comma list of precisions to run (default mixed,fp64)")
@@ -313,6 +391,9 @@ def main():
                     "algorithmic_bytes_per_launch": int(fk["algorithmic_bytes_per_launch"]),
                     "achievable_copy_GBs": round(copy["GBs"], 1),
                     "frac_of_achievable": round(fk["achieved_GBs"] / copy["GBs"], 4)}
+    grads = None
+    if args.gradients or args.config == "lj256k":
+        grads = grad_mode(cfg, cfg.get("steps", 200), args.ckpt, args.seed)
     cpu = None if args.no_cpu else cpu_baseline(cfg)
     vel_desc = (f"|v|={cfg['speed']} in random directions" if "speed" in cfg
                 else f"T={cfg['T']} Maxwell-Boltzmann")
@@ -342,6 +423,7 @@ def main():
         "cpu_baseline": cpu,
         "modes": results,
         "ablation": ablation,
+        "gradients": grads,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)

@@ -185,6 +185,11 @@ class TrajectoryMeanPE(torch.autograd.Function):
         av = torch.zeros_like(aq)
         av_next = torch.empty_like(aq)
         acc = torch.zeros(2, dtype=torch.float64, device=dev)
+        # pair lists: the recomputation of a segment rebuilds its list by the
+        # rule of every run (some particle moved more than (rs - rc)/2 since the
+        # last build), so a list built at one of the states it rebuilt at holds
+        # every pair within rc up to the next such state; the reverse sweep
+        # builds its lists at those states only
         k_end = K
         for si in range(len(ctx.ckpts) - 1, -1, -1):
             qc, vc = ctx.ckpts[si]
@@ -193,19 +198,36 @@ class TrajectoryMeanPE(torch.autograd.Function):
             # recompute the segment's states q_k0 .. q_k0+m from its checkpoint
             eng = Engine(qc.cpu().numpy(), vc.cpu().numpy(), cfg["box"], eps=cfg["eps"], sigma=cfg["sigma"],
                          rc=cfg["rc"], rs=cfg["rs"], dt=dt, precision="fp64", resort_every=0, device=dev)
+            eng.prepare()                 # the list of state 0
             states = [qc]
-            for _ in range(m):
+            builds = [0]                  # states of the segment its lists were built at
+            for t in range(m):
+                before = eng.rebuilds
                 eng.step(1)
+                if eng.rebuilds > before:
+                    builds.append(t + 1)
                 states.append(eng.pos[:, :3].clone())
             del eng
+            current = placed = None      # state of the field's list; state of its positions
+
+            def place(t):
+                nonlocal current, placed
+                b = max(x for x in builds if x <= t)
+                if b != current:
+                    f.set_positions(states[b])
+                    current = placed = b
+                if t != placed:
+                    f.set_positions(states[t], rebuild=False)
+                    placed = t
+
             for j in range(m - 1, -1, -1):
                 # step q_j -> q_{j+1}: observable term and second kick at q_{j+1},
                 # with the drift of the velocity adjoint fused in
-                f.set_positions(states[j + 1])
+                place(j + 1)
                 f.adjoint_kick(av, aq, av_next, (1.0, -h, -w, h, w), acc)
                 av, av_next = av_next, av
-                # first kick at q_j (the list built at q_{j+1} is still valid)
-                f.set_positions(states[j], rebuild=False)
+                # first kick at q_j
+                place(j)
                 f.adjoint_kick(av, aq, None, (1.0, -h, 0.0, h, 0.0), acc)
             k_end = k0
         ge = acc[0].to(ctx.eps_like) if ctx.eps_like is not None else None
