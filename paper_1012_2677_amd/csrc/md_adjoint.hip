@@ -29,6 +29,7 @@ struct AdjArgs {
     double* u_out;
     double* part;
     double alpha, beta, gamma, cu, cU, dt;
+    double inv_eps, inv_sigma;   // 1/eps and 1/sigma, computed on the host
     int64_t n;
     double L[3], invL[3];
     int32_t nc[3];
@@ -77,7 +78,7 @@ __device__ __forceinline__ void block_partial2_a(double a, double b, double* par
 // then out_i = alpha out_i + beta Hu_i + gamma F_i (when out != nullptr),
 // u_out_i = u_i + dt out_i (when u_out != nullptr), and the block partials
 // (cu t_e + cU v_e, cu t_s + cU v_s) / 2 (each pair is visited twice).
-template <int G, bool HAS_U>
+template <int G, int U, bool HAS_U>
 __global__ __launch_bounds__(kForceBlock) void k_adjoint(AdjArgs a)
 {
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -106,41 +107,65 @@ __global__ __launch_bounds__(kForceBlock) void k_adjoint(AdjArgs a)
     const LJ& lj = a.lj;
     double hx = 0.0, hy = 0.0, hz = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
     double te = 0.0, ts = 0.0, ve = 0.0, vs = 0.0;
-    for (int t = sub; t < cnt; t += G) {
-        const uint32_t e = a.nbr[off + t];
-        const int64_t j = e & kSlotMask;
-        const double4 pj = a.pos[j];
-        double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
-        if (minimg) {
-            dx -= a.L[0] * rint(dx * a.invL[0]);
-            dy -= a.L[1] * rint(dy * a.invL[1]);
-            dz -= a.L[2] * rint(dz * a.invL[2]);
+    // U row entries per lane at a time: their loads, then the partners'
+    // positions and u, then the pair terms, so that several gathers are in
+    // flight per lane (slots past the row's end read the key itself and are
+    // skipped)
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    for (int t0 = sub; t0 < cnt; t0 += G * U) {
+        uint32_t e[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int t = t0 + q * G;
+            e[q] = t < cnt ? a.nbr[off + t] : kNone;
         }
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (!(r2 < lj.rc2)) continue;
-        const double r2i = 1.0 / r2;
-        const double r6i = r2i * r2i * r2i;
-        const double g = r2i * r6i * (lj.A * r6i - lj.B) - lj.C8;
-        fx -= g * dx;
-        fy -= g * dy;
-        fz -= g * dz;
-        if (HAS_U) {
-            const double gp = r2i * r2i * r6i * (-7.0 * lj.A * r6i + 4.0 * lj.B);
-            const double dux = a.u[j] - uxi, duy = a.u[n + j] - uyi, duz = a.u[2 * n + j] - uzi;
-            const double ddu = dx * dux + dy * duy + dz * duz;
-            const double c = 2.0 * gp * ddu;
-            hx += c * dx + g * dux;
-            hy += c * dy + g * duy;
-            hz += c * dz + g * duz;
-            // dg/deps = g/eps;  dg/dsigma = (12 A s^-7 - 6 B s^-4 - Cs) / sigma
-            te += (g / lj.eps) * ddu;
-            ts += ((12.0 * lj.A * r6i - 6.0 * lj.B) * r6i * r2i - lj.Cs) / lj.sigma * ddu;
+        double4 pj[U];
+        double ujx[U], ujy[U], ujz[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t j = e[q] != kNone ? (int64_t)(e[q] & kSlotMask) : key;
+            pj[q] = a.pos[j];
+            if (HAS_U) {
+                ujx[q] = a.u[j];
+                ujy[q] = a.u[n + j];
+                ujz[q] = a.u[2 * n + j];
+            }
         }
-        const double V = r6i * (lj.A4 * r6i - lj.B4) + lj.C2 * r2 + lj.C0;
-        const double sa = r6i * r6i + 6.0 * r2 * lj.rc14i - 7.0 * lj.rc12i;
-        const double sb = r6i + 3.0 * r2 * lj.rc8i - 4.0 * lj.rc6i;
-        ve += V / lj.eps;
-        vs += (12.0 * lj.A4 * sa - 6.0 * lj.B4 * sb) / lj.sigma;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (e[q] == kNone) continue;
+            double dx = pj[q].x - xi, dy = pj[q].y - yi, dz = pj[q].z - zi;
+            if (minimg) {
+                dx -= a.L[0] * rint(dx * a.invL[0]);
+                dy -= a.L[1] * rint(dy * a.invL[1]);
+                dz -= a.L[2] * rint(dz * a.invL[2]);
+            }
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (!(r2 < lj.rc2)) continue;
+            const double r2i = rcp64(r2);
+            const double r6i = r2i * r2i * r2i;
+            const double g = r2i * r6i * (lj.A * r6i - lj.B) - lj.C8;
+            fx -= g * dx;
+            fy -= g * dy;
+            fz -= g * dz;
+            if (HAS_U) {
+                const double gp = r2i * r2i * r6i * (-7.0 * lj.A * r6i + 4.0 * lj.B);
+                const double dux = ujx[q] - uxi, duy = ujy[q] - uyi, duz = ujz[q] - uzi;
+                const double ddu = dx * dux + dy * duy + dz * duz;
+                const double c = 2.0 * gp * ddu;
+                hx += c * dx + g * dux;
+                hy += c * dy + g * duy;
+                hz += c * dz + g * duz;
+                // dg/deps = g/eps;  dg/dsigma = (12 A s^-7 - 6 B s^-4 - Cs) / sigma
+                te += g * a.inv_eps * ddu;
+                ts += ((12.0 * lj.A * r6i - 6.0 * lj.B) * r6i * r2i - lj.Cs) * a.inv_sigma * ddu;
+            }
+            const double V = r6i * (lj.A4 * r6i - lj.B4) + lj.C2 * r2 + lj.C0;
+            const double sa = r6i * r6i + 6.0 * r2 * lj.rc14i - 7.0 * lj.rc12i;
+            const double sb = r6i + 3.0 * r2 * lj.rc8i - 4.0 * lj.rc6i;
+            ve += V * a.inv_eps;
+            vs += (12.0 * lj.A4 * sa - 6.0 * lj.B4 * sb) * a.inv_sigma;
+        }
     }
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) {
@@ -175,6 +200,11 @@ __global__ __launch_bounds__(kForceBlock) void k_adjoint(AdjArgs a)
         block_partial2_a<kForceBlock>(0.5 * (a.cu * te + a.cU * ve), 0.5 * (a.cu * ts + a.cU * vs), a.part, blk);
 }
 
+#ifndef MD_ADJ_UNROLL
+#define MD_ADJ_UNROLL 2
+#endif
+constexpr int kAdjUnroll = MD_ADJ_UNROLL;   // row entries in flight per lane
+
 static AdjArgs make_args(const Geo& g, const LJ& lj, const double* pos, const int32_t* cell_xyz,
                          const md_pairlist& list)
 {
@@ -197,6 +227,8 @@ static AdjArgs make_args(const Geo& g, const LJ& lj, const double* pos, const in
     }
     a.exact_all = g.exact_all;
     a.lj = lj;
+    a.inv_eps = 1.0 / lj.eps;
+    a.inv_sigma = 1.0 / lj.sigma;
     return a;
 }
 
@@ -204,9 +236,9 @@ static void launch_adj(const Geo& g, const AdjArgs& a, hipStream_t s)
 {
     const dim3 grid((unsigned)ceil_div(g.n, kKeysPerBlock)), block(kForceBlock);
     if (a.u)
-        hipLaunchKernelGGL((k_adjoint<kLanesPerKey, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_adjoint<kLanesPerKey, kAdjUnroll, true>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((k_adjoint<kLanesPerKey, false>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_adjoint<kLanesPerKey, kAdjUnroll, false>), grid, block, 0, s, a);
 }
 
 hipError_t launch_hvp(const Geo& g, const LJ& lj, const double* pos, const int32_t* cell_xyz,
