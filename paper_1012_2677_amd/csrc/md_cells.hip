@@ -47,20 +47,27 @@ __global__ __launch_bounds__(kStreamBlock) void k_label(Geo g, const double4* __
     cell_of[i] = c;
     cell_xyz[i] = cx | (cy << 10) | (cz << 20);
     // Slots in cell order (after a re-sort) put runs of equal cells in one
-    // wave: one atomic per distinct cell of the wave, ranks by lane order.
+    // wave: the lanes are grouped by cell first, then the first lane of each
+    // group adds the group's size with one atomic, all groups' atomics issued
+    // together; ranks follow lane order inside a group (the order within a
+    // cell is made stable afterwards by k_sort_cells).
     uint64_t todo = __ballot(1);
-    int32_t r = 0;
+    int leader_of = 0;
+    uint64_t group = 0;
     while (todo) {
         const int leader = __ffsll((unsigned long long)todo) - 1;
         const int32_t cl = __shfl(c, leader, 64);
         const uint64_t same = __ballot(c == cl);
-        int32_t base = 0;
-        if ((int)lane_id() == leader) base = atomicAdd(&count[cl], (int32_t)__popcll(same));
-        base = __shfl(base, leader, 64);
-        if (c == cl) r = base + (int32_t)mbcnt64(same);
+        if (c == cl) {
+            leader_of = leader;
+            group = same;
+        }
         todo &= ~same;
     }
-    rank[i] = r;
+    int32_t base = 0;
+    if ((int)lane_id() == leader_of) base = atomicAdd(&count[c], (int32_t)__popcll(group));
+    base = __shfl(base, leader_of, 64);
+    rank[i] = base + (int32_t)mbcnt64(group);
 }
 
 // ---- three-phase exclusive scan of int32 (block: 256 threads x 4 items) -----
