@@ -163,20 +163,42 @@ __global__ __launch_bounds__(kStreamBlock) void k_scatter(int64_t n, const int32
 
 // Insertion sort of each cell's segment by slot (segments hold ~11 slots at
 // rho = 0.5; any length is handled).
+// Insertion sort of each cell's slots (the scatter leaves the groups of
+// different waves in atomic order).  A block's cells are contiguous in
+// `order`: when their slots fit, they are loaded into LDS with coalesced
+// loads, sorted there (one thread per cell) and written back; otherwise each
+// thread sorts its cell in place in global memory.
+constexpr int kSortLds = 4096;   // slots of one block's cells sorted in LDS
+
+__device__ __forceinline__ void insertion_sort(int32_t* v, int32_t len)
+{
+    for (int32_t k = 1; k < len; ++k) {
+        const int32_t x = v[k];
+        int32_t p = k - 1;
+        while (p >= 0 && v[p] > x) {
+            v[p + 1] = v[p];
+            --p;
+        }
+        v[p + 1] = x;
+    }
+}
+
 __global__ __launch_bounds__(kStreamBlock) void k_sort_cells(int64_t ncell, const int32_t* __restrict__ start,
                                                              int32_t* __restrict__ order)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    const int32_t s = start[c], e = start[c + 1];
-    for (int32_t k = s + 1; k < e; ++k) {
-        const int32_t v = order[k];
-        int32_t p = k - 1;
-        while (p >= s && order[p] > v) {
-            order[p + 1] = order[p];
-            --p;
-        }
-        order[p + 1] = v;
+    __shared__ int32_t s_o[kSortLds];
+    const int64_t c0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t c1 = c0 + blockDim.x < ncell ? c0 + blockDim.x : ncell;
+    const int64_t c = c0 + threadIdx.x;
+    const int32_t b0 = start[c0], b1 = start[c1];
+    if (b1 - b0 <= kSortLds) {
+        for (int32_t t = threadIdx.x; t < b1 - b0; t += blockDim.x) s_o[t] = order[b0 + t];
+        __syncthreads();
+        if (c < c1) insertion_sort(s_o + (start[c] - b0), start[c + 1] - start[c]);
+        __syncthreads();
+        for (int32_t t = threadIdx.x; t < b1 - b0; t += blockDim.x) order[b0 + t] = s_o[t];
+    } else if (c < c1) {
+        insertion_sort(order + start[c], start[c + 1] - start[c]);
     }
 }
 
