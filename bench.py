@@ -14,6 +14,16 @@ is reported beside it.  A step is one full pass of the hot path: half kick +
 drift, rebuild check (and bin / re-sort / pair-list build when due), forces,
 second half kick.
 
+After the timed steps of each mode, an untimed leg runs the paper's own
+protocol on the same state (150 steps, then 1000 steps with the energy sampled
+every 10): its rate and the energy drift per 1000 steps fitted to its samples
+are reported for every mode whatever --steps is, so that the FP64 and mixed
+rates always stand beside their drifts.
+
+The CPU baseline (the oracle, plain C) runs first, in child processes that
+touch no GPU: one thread, then one process per core of the job's CPU share,
+each on its own 256,000-particle box of the same fluid.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 
@@ -24,6 +34,7 @@ import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -61,6 +72,17 @@ def force_bytes_per_key(mean_entries: float, mixed: bool, tiled: bool = False, h
     if mixed:
         return idx + 16 + 32 + 4 + 48 + 24 + 32 + 16 + fbytes
     return idx + 32 + (0 if tiled else 4) + 48 + 24 + 32 + fbytes
+
+
+def survey_bytes_per_key(mean_entries: float) -> float:
+    """Algorithmic bytes per particle of the fused force + integrator pass as
+    the hot path's measurement plan counts them, whatever the list layout:
+    the force row reads 4 bytes per list entry, an 8-byte row offset and the
+    24-byte FP64 position; the integrator adds the position written (24), the
+    velocity read and written (48) and the reference position (24), its force
+    store and load and its position read vanishing in the fusion:
+    4 m + 128."""
+    return 4.0 * mean_entries + 8 + 24 + 24 + 48 + 24
 
 
 def force_sources_sha256() -> str:
@@ -111,6 +133,37 @@ def copy_bandwidth(nbytes: int = 4 << 30, reps: int = 10):
     return {"bytes_per_copy": 2 * nbytes, "ms": ms, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def hbm_probe(nbytes: int = 4 << 30, reps: int = 10):
+    """Achievable HBM bandwidth from the library's streaming probes (read,
+    copy, triad; plain and non-temporal accesses) on arrays of nbytes each,
+    the best of reps launches of each; bytes moved per launch: read nbytes,
+    copy 2 nbytes, triad 3 nbytes."""
+    import torch
+
+    from paper_1012_2677_amd import _abi as A
+
+    dev = torch.device("cuda", 0)
+    a = torch.full((nbytes // 8,), 1.0, dtype=torch.float64, device=dev)
+    b = torch.full_like(a, 2.0)
+    c = torch.empty_like(a)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    out = {}
+    moved = {A.MD_PROBE_READ: 1, A.MD_PROBE_COPY: 2, A.MD_PROBE_TRIAD: 3}
+    names = {A.MD_PROBE_READ: "read", A.MD_PROBE_COPY: "copy", A.MD_PROBE_TRIAD: "triad"}
+    for op in (A.MD_PROBE_READ, A.MD_PROBE_COPY, A.MD_PROBE_TRIAD):
+        for nt in (False, True):
+            kind = op | (A.MD_PROBE_NT if nt else 0)
+            ms = A.md_hbm_probe(kind, a.data_ptr(), b.data_ptr(), c.data_ptr(), nbytes, reps, stream)
+            out[names[op] + ("_nt" if nt else "")] = round(moved[op] * nbytes / (ms * 1e-3) / 1e9, 1)
+    torch.cuda.synchronize()
+    # the copies left b = a = 1 and the triads c = a + 3 b = 4
+    ok = bool(torch.all(b == 1.0).item() and torch.all(c == 4.0).item())
+    del a, b, c
+    torch.cuda.empty_cache()
+    best = max(out.values())
+    return {"array_bytes": nbytes, "reps": reps, "GBs": out, "best_GBs": best, "check": ok}
+
+
 def drift_per_1000(steps_axis, e_per_particle):
     if len(e_per_particle) < 2:
         return None
@@ -120,7 +173,11 @@ def drift_per_1000(steps_axis, e_per_particle):
 
 
 def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, shuffle=False,
-             rebuild_rule="half_skin", ldc_max=8192, list_layout="auto", tile_cells=0):
+             rebuild_rule="half_skin", ldc_max=8192, list_layout="auto", tile_cells=0, protocol=(150, 1000, 10)):
+    """One precision mode: prepare, warmup, the timed steps, then (protocol =
+    (lead, steps, sample_every), lead > 0 or steps > 0) the paper's protocol
+    leg on the same state: lead untimed steps, then steps timed ones with the
+    energy sampled every sample_every steps, whose samples give the drift."""
     import torch
 
     import lj_inputs as li
@@ -151,17 +208,9 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
         e.timers.launches[k] = 0
     reb0 = e.rebuilds
     ldc0 = e.ldc_stats
-    # the paper's own protocol also reports the rate after its first 150 steps
-    split = 150 if steps >= 300 and steps % sample_every == 0 and 150 % sample_every == 0 else 0
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    if split:
-        elog0 = e.step(split, sample_every=sample_every)
-        torch.cuda.synchronize()
-        t_split = time.perf_counter()
-        elog = np.concatenate([elog0, e.step(steps - split, sample_every=sample_every)])
-    else:
-        elog = e.step(steps, sample_every=sample_every)
+    elog = e.step(steps, sample_every=sample_every)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     dt = t2 - t1
@@ -171,9 +220,6 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
     tim = e.timer_dict()
     rebuilds = e.rebuilds - reb0
     log(f"[bench] {precision}: {steps} steps in {dt:.3f}s, {rebuilds} rebuilds, timers {tim}")
-    # rows are written at step numbers (counted from the start) divisible by sample_every
-    first = (warmup // sample_every + 1) * sample_every
-    axis = np.arange(first, first + sample_every * len(elog), sample_every, dtype=np.float64)[: len(elog)]
     e_pp = elog[:, 3] / n if len(elog) else np.zeros(0)
     out = {
         "n": n,
@@ -188,22 +234,54 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
         "list_tiled": tiled,
         "list_half": half,
         "tile_cells": int(e.state.tile_cells),
+        "list_cell_stride": int(e.plist.cell_stride),
+        "list_largest_cell_block": int(e.plist.status[1].item()),
         "timers_ms": {k: [round(m, 3), c] for k, (m, c) in tim.items()},
         "energy_per_particle_start": float(e0[3] / n),
         "energy_per_particle_samples": [float(x) for x in e_pp],
-        "drift_per_1000_steps": drift_per_1000(axis, e_pp),
-        "max_abs_energy_change": float(np.abs(e_pp - e0[3] / n).max()) if len(e_pp) else None,
         "temperature_end": float(2.0 * elog[-1, 0] / (3.0 * (n - 1))) if len(elog) else None,
-        "value_after_step_150": n * (steps - split) / (t2 - t_split) if split else None,
-        "hbm_footprint_bytes": int(torch.cuda.max_memory_allocated()),
     }
     fm, fl = tim.get("force", (0.0, 0))
     if fl > 0:
         avg_ms = fm / fl
         per_launch = n * force_bytes_per_key(entries / n, precision == "mixed", bool(tiled), bool(half))
-        gbs = per_launch / (avg_ms * 1e-3) / 1e9
-        out["force_kernel"] = {"avg_ms": avg_ms, "launches": fl, "algorithmic_bytes_per_launch": per_launch,
-                               "achieved_GBs": gbs}
+        plan = n * survey_bytes_per_key(entries / n)
+        out["force_kernel"] = {"avg_ms": avg_ms, "launches": fl,
+                               "algorithmic_bytes_per_launch": plan,
+                               "achieved_GBs": plan / (avg_ms * 1e-3) / 1e9,
+                               "layout_bytes_per_launch": per_launch,
+                               "layout_GBs": per_launch / (avg_ms * 1e-3) / 1e9}
+    lead, psteps, pevery = protocol
+    if psteps > 0:
+        if lead > 0:
+            e.step(lead)
+        torch.cuda.synchronize()
+        s0 = e.step_count
+        r0 = e.rebuilds
+        t3 = time.perf_counter()
+        plog = e.step(psteps, sample_every=pevery)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        first = (s0 // pevery + 1) * pevery
+        axis = np.arange(first, first + pevery * len(plog), pevery, dtype=np.float64)[: len(plog)]
+        ep = plog[:, 3] / n
+        out["protocol"] = {
+            "lead_steps": lead, "steps": psteps, "sample_every": pevery,
+            "first_step": s0 + 1,
+            "value": n * psteps / (t4 - t3),
+            "MUPS": n * psteps / (t4 - t3) / 1e6,
+            "ms_per_step": 1e3 * (t4 - t3) / psteps,
+            "rebuilds": e.rebuilds - r0,
+            "drift_per_1000_steps": drift_per_1000(axis, ep),
+            "energy_per_particle_first": float(ep[0]) if len(ep) else None,
+            "energy_per_particle_last": float(ep[-1]) if len(ep) else None,
+            "max_abs_energy_change": float(np.abs(ep - ep[0]).max()) if len(ep) else None,
+            "temperature_end": float(2.0 * plog[-1, 0] / (3.0 * (n - 1))) if len(plog) else None,
+        }
+        out["drift_per_1000_steps"] = out["protocol"]["drift_per_1000_steps"]
+        log(f"[bench] {precision}: protocol {lead} + {psteps} steps: {out['protocol']['ms_per_step']:.3f} ms/step, "
+            f"drift {out['drift_per_1000_steps']:.3e} per particle per 1000 steps")
+    out["hbm_footprint_bytes"] = int(torch.cuda.max_memory_allocated())
     del e
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
@@ -285,28 +363,85 @@ def grad_mode(cfg, steps, ckpt, seed, reps=50):
     }
 
 
-def cpu_baseline(cfg, seconds_target=20.0):
-    """The oracle as it is (plain C, one thread) on a bounded sample of the same
-    workload: the same density, initial velocities, dt and skin on a
-    256,000-particle box (40^3 fcc cells), timed over enough steps for ~10-30 s."""
+def cpu_worker(config: str, seconds_target: float, seed: int):
+    """One oracle process (plain C, one thread): the fluid of `config` at the
+    density, velocity law, dt and skin of the workload, on a 256,000-particle
+    box (40^3 fcc cells), for enough velocity-Verlet steps (rebuilds included)
+    to take about seconds_target.  Prints one JSON line."""
     import oracle
     import lj_inputs as li
 
+    cfg = {**li.CONFIGS, **li.PAPER_CONFIGS}[config]
     q, L = li.fcc_lattice(40, cfg["rho"])
-    v = li.initial_velocities(cfg, q.shape[0], seed=0)
+    v = li.initial_velocities(cfg, q.shape[0], seed=seed)
     n = q.shape[0]
+    kw = dict(dt=cfg["dt"], rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], sample_every=0)
     t0 = time.perf_counter()
-    oracle.run(q, v, L, 2, dt=cfg["dt"], rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], sample_every=0)
+    oracle.run(q, v, L, 2, **kw)
     per_step = (time.perf_counter() - t0) / 2.0
-    k = max(2, min(200, int(seconds_target / max(per_step, 1e-3))))
+    k = max(2, min(400, int(seconds_target / max(per_step, 1e-3))))
     t0 = time.perf_counter()
-    oracle.run(q, v, L, k, dt=cfg["dt"], rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], sample_every=0)
+    oracle.run(q, v, L, k, **kw)
     dt = time.perf_counter() - t0
+    print(json.dumps({"n": n, "steps": k, "seconds": dt, "value": n * k / dt}), flush=True)
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(config: str, cfg, seconds_target=10.0):
+    """The oracle as it is, timed on this job's host cores in child processes
+    that use no GPU: one process alone (one thread), then one process per core
+    of the job's CPU share at once, each on its own 256,000-particle box of the
+    same fluid (a bounded sample of the workload).  The all-core aggregate is
+    the sum of the processes' rates."""
+    affinity = len(os.sched_getaffinity(0))
+    # at most 16 workers: the CPU share of one GPU of the job
+    procs = max(1, min(affinity, 16))
+
+    def launch(seed):
+        return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", "--config", config,
+                                 "--cpu-seconds", str(seconds_target), "--seed", str(seed)],
+                                stdout=subprocess.PIPE, text=True, cwd=ROOT)
+
+    def collect(ps):
+        res = []
+        for p in ps:
+            out, _ = p.communicate()
+            if p.returncode != 0:
+                raise RuntimeError(f"cpu worker failed with status {p.returncode}")
+            res.append(json.loads(out.strip().splitlines()[-1]))
+        return res
+
+    single = collect([launch(0)])[0]
+    log(f"[bench] cpu oracle, one thread: {single['value']:.3e} particle-steps/s")
+    t0 = time.perf_counter()
+    many = collect([launch(k) for k in range(procs)])
+    wall = time.perf_counter() - t0
+    agg = sum(r["value"] for r in many)
+    log(f"[bench] cpu oracle, {procs} processes: {agg:.3e} particle-steps/s in {wall:.1f} s")
     vel = f"|v|={cfg['speed']}" if "speed" in cfg else f"T={cfg['T']}"
-    return {"value": n * k / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"N={n} (40^3 fcc cells, rho={cfg['rho']}, {vel}, dt={cfg['dt']}, rc={cfg['rc']}, "
-                      f"skin={cfg['skin']}, FP64), {k} velocity-Verlet steps incl. rebuilds, single thread, "
-                      f"{dt:.1f} s"}
+    n = single["n"]
+    return {"value": agg, "unit": "particle-steps/s", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} oracle processes at once (one thread each, plain C), each on its own N={n} box "
+                      f"(40^3 fcc cells, rho={cfg['rho']}, {vel}, dt={cfg['dt']}, rc={cfg['rc']}, "
+                      f"skin={cfg['skin']}, FP64) for {min(r['steps'] for r in many)}-"
+                      f"{max(r['steps'] for r in many)} velocity-Verlet steps incl. rebuilds; "
+                      f"rates summed; {wall:.1f} s wall",
+            "cpu_model": _cpu_model(), "affinity_cores": affinity,
+            "single_thread": {"value": single["value"], "steps": single["steps"], "seconds": single["seconds"],
+                              "MUPS": single["value"] / 1e6},
+            "MUPS_per_core": agg / procs / 1e6,
+            "paper_MUPS_per_process_context": {"Xeon X5570 core (2.93 GHz)": 2.730,
+                                               "POWER6 SMT process (4.7 GHz)": 1.652}}
 
 
 def main():
@@ -334,43 +469,67 @@ def main():
     ap.add_argument("--modes", default=None, help="comma list of precisions to run (default mixed,fp64)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference kernel for HBM counter scaling)")
+    ap.add_argument("--protocol-lead", type=int, default=150,
+                    help="untimed steps before the protocol leg (the paper's 150)")
+    ap.add_argument("--protocol-steps", type=int, default=1000,
+                    help="steps of the protocol leg after the timed steps (0 = none); its energy samples give "
+                         "the drift per 1000 steps")
+    ap.add_argument("--protocol-every", type=int, default=10, help="energy sampling interval of the protocol leg")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target seconds per CPU oracle process")
+    ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:
+        # a child of cpu_baseline: the oracle only, no GPU
+        cpu_worker(args.config, args.cpu_seconds, args.seed)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: there is no multi-GPU path (the domain decomposition that would "
               "shard the work over GPUs is not built). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-
     import lj_inputs as li
+
+    cfg = dict({**li.CONFIGS, **li.PAPER_CONFIGS}[args.config])
+    # the CPU baseline first, while this process has not touched the GPU
+    cpu = None if (args.no_cpu or args.calibrate_copy) else cpu_baseline(args.config, cfg, args.cpu_seconds)
+
+    import torch
 
     if args.calibrate_copy:
         print(json.dumps({"calibrate_copy": copy_bandwidth(1 << 30, 3)}), flush=True)
         return
-    cfg = dict({**li.CONFIGS, **li.PAPER_CONFIGS}[args.config])
     if args.warmup is None:
         args.warmup = cfg.get("warmup", 10)
     headline = cfg["precision"]
     modes = args.modes.split(",") if args.modes else ([headline] + ([] if args.no_fp64 else
                                                                     (["fp64"] if headline != "fp64" else [])))
     sample_every = min(args.sample_every, max(1, args.steps))
+    protocol = (args.protocol_lead, args.protocol_steps, args.protocol_every)
     results = {}
     for m in modes:
         results[m] = run_mode(cfg, m, args.steps, args.warmup, sample_every, args.seed,
                               rebuild_rule=args.rebuild_rule, ldc_max=args.ldc_max, list_layout=args.list_layout,
-                              tile_cells=args.tile_cells)
+                              tile_cells=args.tile_cells, protocol=protocol)
     head = results[modes[0]]
     n = head["n"]
+    drift = {m: results[m].get("drift_per_1000_steps") for m in modes}
+    if "mixed" in drift and "fp64" in drift and drift["mixed"] is not None and drift["fp64"] is not None:
+        fluct = results["fp64"]["protocol"]["max_abs_energy_change"]
+        drift["matched"] = bool(abs(drift["mixed"]) <= 2.0 * abs(drift["fp64"]) or
+                                max(abs(drift["mixed"]), abs(drift["fp64"])) <= fluct)
+        drift["criterion"] = ("|drift mixed| <= 2 |drift FP64|, or both below the FP64 run's largest energy "
+                              "change over the leg")
     ablation = None
     if args.ablation:
-        ab = run_mode(cfg, modes[0], args.steps, args.warmup, sample_every, args.seed, resort_every=0, shuffle=True)
+        ab = run_mode(cfg, modes[0], args.steps, args.warmup, sample_every, args.seed, resort_every=0, shuffle=True,
+                      protocol=(0, 0, 0))
         ablation = {"no_resort_shuffled": {k: ab[k] for k in ("value", "ms_per_step", "rebuilds", "timers_ms")},
                     "resort_every_rebuild_over_no_resort": head["value"] / ab["value"]}
         log(f"[bench] ablation: no re-sort, shuffled labels: {ab['ms_per_step']:.3f} ms/step "
             f"(re-sort at every rebuild is {ablation['resort_every_rebuild_over_no_resort']:.2f}x faster)")
     fk = head.get("force_kernel")
-    copy = copy_bandwidth()
-    log(f"[bench] plain copy: {copy['GBs']:.0f} GB/s")
+    probe = hbm_probe()
+    log(f"[bench] streaming probes (GB/s): {probe['GBs']}")
     roofline = None
     if fk:
         if head.get("list_half"):
@@ -389,12 +548,16 @@ def main():
                     "kernel": kname,
                     "avg_launch_ms": round(fk["avg_ms"], 4),
                     "algorithmic_bytes_per_launch": int(fk["algorithmic_bytes_per_launch"]),
-                    "achievable_copy_GBs": round(copy["GBs"], 1),
-                    "frac_of_achievable": round(fk["achieved_GBs"] / copy["GBs"], 4)}
+                    "algorithmic_bytes_per_particle": round(fk["algorithmic_bytes_per_launch"] / n, 2),
+                    "layout_bytes_per_launch": int(fk["layout_bytes_per_launch"]),
+                    "layout_GBs": round(fk["layout_GBs"], 1),
+                    "layout_frac": round(fk["layout_GBs"] / HBM_PEAK_GBS, 4),
+                    "achievable_GBs": probe["best_GBs"],
+                    "achievable_probe": probe,
+                    "frac_of_achievable": round(fk["achieved_GBs"] / probe["best_GBs"], 4)}
     grads = None
     if args.gradients or args.config == "lj256k":
         grads = grad_mode(cfg, cfg.get("steps", 200), args.ckpt, args.seed)
-    cpu = None if args.no_cpu else cpu_baseline(cfg)
     vel_desc = (f"|v|={cfg['speed']} in random directions" if "speed" in cfg
                 else f"T={cfg['T']} Maxwell-Boltzmann")
     # The paper's own number exists only for its own workload: 64 cubes of
@@ -420,6 +583,7 @@ def main():
                                f"{args.rebuild_rule} rebuild rule",
                    "n": n, "box": head["L"], "precision": modes[0], "sample_every": sample_every},
         "roofline": roofline,
+        "drift_per_1000_steps": drift,
         "cpu_baseline": cpu,
         "modes": results,
         "ablation": ablation,

@@ -150,8 +150,13 @@ typedef struct md_cells {
  * the block nbr[c*cell_stride .. (c+1)*cell_stride).
  *   offsets   device int64[n]
  *   counts    device int32[n]
- *   nbr       device uint32[capacity], capacity >= nc * cell_stride,
- *             1 <= cell_stride <= 2^29
+ *   nbr       device uint32[capacity], 1 <= cell_stride <= 2^29;
+ *             capacity >= nc * cell_stride for slot entries (every call
+ *             but md_prepare / md_step / md_energy), and for a simulation
+ *             state whose list is tiled (16-bit entries, see md_state)
+ *             capacity >= nc * cell_stride / 2 (rounded up) is enough; should
+ *             such a state need slot entries, md_prepare / md_step return
+ *             MD_ERR_CAPACITY with status[2] clear (grow nbr and call again)
  *   status    device int64[4]: [0] total entries, [1] largest per-cell block,
  *             [2] 1 if some cell block overflowed cell_stride (list invalid),
  *             [3] reserved.

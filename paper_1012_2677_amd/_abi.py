@@ -37,7 +37,9 @@ TIMER_NAMES = ["force", "integrate", "bin", "resort", "build", "reduce", "check"
 
 EXPORTED = ["md_cell_dims", "md_workspace_bytes", "md_pack_positions", "md_bin_cells", "md_resort", "md_build_pairlist",
             "md_forces", "md_prepare", "md_step", "md_energy", "md_hvp", "md_adjoint_kick", "md_param_grad",
-            "md_ldc_check", "md_last_error"]
+            "md_ldc_check", "md_last_error", "md_hbm_probe"]
+
+MD_PROBE_READ, MD_PROBE_COPY, MD_PROBE_TRIAD, MD_PROBE_NT = 0, 1, 2, 4
 
 
 class MdError(RuntimeError):
@@ -113,6 +115,7 @@ def lib():
         "md_ldc_check": (C.c_int, [P(MdParams), vp, vp, P(C.c_int32), P(C.c_int64), P(C.c_double), vp,
                                    C.c_size_t, vp]),
         "md_last_error": (C.c_char_p, []),
+        "md_hbm_probe": (C.c_int, [C.c_int32, vp, vp, vp, C.c_size_t, C.c_int32, P(C.c_float), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -202,3 +205,10 @@ def md_ldc_check(params, pos, pos_ref, ws, ws_bytes, stream):
     _check(lib().md_ldc_check(C.byref(params), pos, pos_ref, C.byref(valid), C.byref(members), C.byref(dmax2),
                               ws, ws_bytes, stream), "md_ldc_check")
     return bool(valid.value), int(members.value), float(dmax2.value)
+
+
+def md_hbm_probe(kind, a, b, c, nbytes, reps, stream) -> float:
+    """Shortest of reps launches of a streaming probe kernel, in ms (md_probe.h)."""
+    ms = C.c_float(0.0)
+    _check(lib().md_hbm_probe(int(kind), a, b, c, int(nbytes), int(reps), C.byref(ms), stream), "md_hbm_probe")
+    return float(ms.value)

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmd355.so")
 SOURCES = ["md_api.hip", "md_cells.hip", "md_pairlist.hip", "md_forces.hip", "md_integrate.hip", "md_validity.hip",
-           "md_adjoint.hip"]
+           "md_adjoint.hip", "md_probe.hip"]
 ARCH = "gfx950"
 
 

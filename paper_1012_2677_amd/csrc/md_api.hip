@@ -23,6 +23,8 @@ static int fail(int code, const char* fmt, ...)
     return code;
 }
 
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
 static int hip_fail(hipError_t e, const char* where)
 {
     return fail(MD_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
@@ -74,6 +76,7 @@ Geo make_geo(const md_params& p, const int32_t nc[3])
         g.cs[k] = p.box[k] / (double)nc[k];
         if (nc[k] < 5) g.exact_all = 1;
     }
+    g.force_minimg_all = g.exact_all || p.rebuild_rule == MD_REBUILD_DUTC_LDC;
     // tiles: about kTileKeys keys each at the mean density, at most nz - 2
     // cells long so that a tile's runs wrap at most once
     const int nz = nc[2];
@@ -129,7 +132,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 //   [16..31]  flags gathered for one read-back (layout in k_gather_flags)
 constexpr int kScalOut = 16;
 
-WsLayout ws_layout(const Geo& g, int64_t ldc_max)
+WsLayout ws_layout(const Geo& g, int64_t ldc_max, int precision)
 {
     const int64_t n = g.n, ncell = g.ncell;
     WsLayout L;
@@ -145,7 +148,8 @@ WsLayout ws_layout(const Geo& g, int64_t ldc_max)
     // (one per block or tile)
     L.part_a = off;    off = align256(off + sizeof(double) * 2 * (size_t)std::max(L.nbf, np));
     L.part_b = off;    off = align256(off + sizeof(double) * (size_t)(np > L.nbi ? np : L.nbi));
-    L.pos32 = off;     off = align256(off + 16 * (size_t)n);
+    // local coordinates of md_forces in mixed precision only
+    L.pos32 = off;     off = align256(off + (precision == MD_MIXED ? 16 * (size_t)n : 0));
     L.red = off;       off = align256(off + sizeof(int64_t) * 2 * 1024);
     L.ldc = off;       off = align256(off + sizeof(int32_t) * (size_t)(ldc_max > 0 ? ldc_max : 1));
     L.scal = off;      off = align256(off + sizeof(int64_t) * 32);
@@ -168,7 +172,7 @@ static int setup(const md_params* p, Ctx& c)
     if (rc != MD_OK) return rc;
     c.g = make_geo(*p, c.nc);
     c.lj = make_lj(*p);
-    c.W = ws_layout(c.g, p->ldc_max);
+    c.W = ws_layout(c.g, p->ldc_max, p->precision);
     return MD_OK;
 }
 
@@ -187,15 +191,28 @@ static int check_cells(const Ctx& c, const md_cells* cells)
     return MD_OK;
 }
 
-static int check_list(const Ctx& c, const md_pairlist* list)
+// 32-bit words of nbr that a list of cell_stride entries per cell takes:
+// 32-bit slot entries, or the 16-bit entries of a state's tiled layout.
+static int64_t list_words(const Ctx& c, const md_pairlist* list, bool tiled)
+{
+    const int64_t entries = c.g.ncell * list->cell_stride;
+    return tiled ? (entries + 1) / 2 : entries;
+}
+
+// slot_entries: the call reads or writes 32-bit slot entries, so nbr must
+// hold them all; a state's list only needs the room of its tiled layout here
+// (build_list checks the layout it is about to write).
+static int check_list(const Ctx& c, const md_pairlist* list, bool slot_entries = true)
 {
     if (!list || !list->offsets || !list->counts || !list->nbr || !list->status)
         return fail(MD_ERR_ARG, "pair list has a NULL array");
     if (list->cell_stride <= 0 || list->cell_stride > ((int64_t)1 << 29))
         return fail(MD_ERR_ARG, "cell_stride must be in [1, 2^29]");
-    if (list->capacity < c.g.ncell * list->cell_stride)
-        return fail(MD_ERR_ARG, "capacity %lld < ncell * cell_stride = %lld", (long long)list->capacity,
-                    (long long)(c.g.ncell * list->cell_stride));
+    const int64_t need = list_words(c, list, !slot_entries);
+    if (list->capacity < need)
+        return fail(MD_ERR_ARG, "capacity %lld < %lld words (ncell * cell_stride = %lld entries of %d bits)",
+                    (long long)list->capacity, (long long)need, (long long)(c.g.ncell * list->cell_stride),
+                    slot_entries ? 32 : 16);
     return MD_OK;
 }
 
@@ -290,7 +307,7 @@ size_t md_workspace_bytes(const md_params* p)
 {
     int32_t nc[3];
     if (check_params(p, nc) != MD_OK) return 0;
-    return ws_layout(make_geo(*p, nc), p->ldc_max).total;
+    return ws_layout(make_geo(*p, nc), p->ldc_max, p->precision).total;
 }
 
 int md_pack_positions(const md_params* p, const double* q, double* pos, hipStream_t stream)
@@ -440,7 +457,7 @@ static int check_state(const Ctx& c, const md_params* p, md_state* st)
         return fail(MD_ERR_ARG, "re-sorting needs pos_alt, vel_alt and id_alt");
     int rc = check_cells(c, &st->cells);
     if (rc != MD_OK) return rc;
-    if ((rc = check_list(c, &st->list)) != MD_OK) return rc;
+    if ((rc = check_list(c, &st->list, false)) != MD_OK) return rc;
     return check_ws(c, st->ws, st->ws_bytes);
 }
 
@@ -463,6 +480,13 @@ static hipError_t clear_maxima(const Ctx& c, md_state* st, hipStream_t s)
 // else slot entries.
 static int build_list(const Ctx& c, const md_params* p, md_state* st, bool tiled, Timer& T, hipStream_t s)
 {
+    if (st->list.capacity < list_words(c, &st->list, tiled)) {
+        // the caller gave room for 16-bit entries only; slot entries need twice
+        // as much (the list is left invalid; status[2] stays clear)
+        st->list_valid = 0;
+        return fail(MD_ERR_CAPACITY, "slot entries need %lld words of nbr, capacity is %lld",
+                    (long long)list_words(c, &st->list, tiled), (long long)st->list.capacity);
+    }
     int64_t* tmax = (int64_t*)((char*)st->ws + c.W.tmax);
     if (tiled) MD_HIP(launch_fill_i32((int32_t*)tmax, 0, 2 * kTileMaxSlots, s), "rebuild/tile-max");
     tick(T, MD_T_BUILD, 0, s);

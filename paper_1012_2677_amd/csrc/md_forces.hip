@@ -20,7 +20,10 @@
 // cross-lane permute, so after the rounds lane L holds the force of key base + L.
 //
 // FP64 mode: displacements from absolute FP64 positions, with the minimum
-// image taken only for keys in boundary cells (elsewhere no partner can wrap).
+// image taken only for keys in boundary cells: elsewhere no listed partner can
+// be a wrapped image while no particle has moved more than (cell side - rc)
+// since the build, which the half-skin rule guarantees.  Under the DUTC + LDC
+// rule (no such bound) every key takes minimum images (exact_all).
 // Mixed mode: each slot carries FP32 coordinates relative to its cell corner;
 // d = (l_j - l_i) + s * cs with s the stencil offset stored in the entry, so
 // the FP32 displacement never suffers the cancellation of absolute FP32
@@ -1057,7 +1060,7 @@ static PairArgs make_pair_args(const Geo& g, const LJ& lj, const double* pos, co
         a.cs[k] = g.cs[k];
         a.nc[k] = g.nc[k];
     }
-    a.exact_all = g.exact_all;
+    a.exact_all = g.force_minimg_all;
     a.tc = g.tc;
     a.nt = g.nt;
     a.lj = lj;

@@ -83,6 +83,11 @@ struct Geo {
     double inv[3];    // nc / L   (cell label scale)
     double cs[3];     // L / nc   (cell side)
     int32_t exact_all;  // some axis has fewer than 5 cells: always take minimum images
+    // force passes take minimum images for every pair: under the DUTC + LDC
+    // rule a kept list can outlive displacements of more than (cell side -
+    // rc), after which a partner that crossed the box boundary can come within
+    // rc of a key whose build-time cell is interior
+    int32_t force_minimg_all;
     // tiles of the LDS-staged force pass: runs of tc cells along z in one
     // (x, y) column, nt per column, ntile in all (tc = 0: no tiled layout)
     int32_t tc, nt;
@@ -105,6 +110,8 @@ struct LJ {
 };
 
 Geo make_geo(const md_params& p, const int32_t nc[3]);
+// Records msg as the message of md_last_error() and returns code.
+int set_error(int code, const char* msg);
 LJ make_lj(const md_params& p);
 
 // ---------------------------------------------------------------------------
@@ -116,7 +123,7 @@ struct WsLayout {
     size_t cell_rows;  // int32[ncell]   entries per cell block (pair list)
     size_t part_a;     // double[2*nbf]  per-block partial sums (force kernels)
     size_t part_b;     // double[nbi]    per-block partial sums (streaming kernels)
-    size_t pos32;      // float4[n]      mixed-mode local coordinates (md_forces)
+    size_t pos32;      // float4[n]      mixed-mode local coordinates (md_forces; empty in FP64)
     size_t red;        // int64[2*1024]  partials of the list statistics
     size_t ldc;        // int32[ldc_max] members of the large-displacement check
     size_t scal;       // int64[32]      small device scalars (layout in md_api.hip)
@@ -127,7 +134,7 @@ struct WsLayout {
     int64_t nbf;       // adjoint-kernel blocks (kKeysPerBlock keys each)
     int64_t nbi;       // streaming-kernel blocks
 };
-WsLayout ws_layout(const Geo& g, int64_t ldc_max);
+WsLayout ws_layout(const Geo& g, int64_t ldc_max, int precision);
 
 // ---------------------------------------------------------------------------
 // Small device helpers

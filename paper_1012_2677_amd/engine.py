@@ -94,23 +94,29 @@ def default_cell_stride(params: A.MdParams, ncell) -> int:
 
 
 class PairList:
-    """md_pairlist arrays; the capacity is ncell * cell_stride entries."""
+    """md_pairlist arrays: ncell * cell_stride entries of 32 bits (slot
+    entries), or of 16 bits when entry_bits = 16 (room for the tiled layout of
+    a simulation state only)."""
 
-    def __init__(self, params: A.MdParams, ncell, device, cell_stride: int | None = None):
+    def __init__(self, params: A.MdParams, ncell, device, cell_stride: int | None = None, entry_bits: int = 32):
         n = params.n
         self.ncell = ncell
         self.device = device
+        self.entry_bits = int(entry_bits)
         self.offsets = torch.empty(n, dtype=torch.int64, device=device)
         self.counts = torch.empty(n, dtype=torch.int32, device=device)
         self.status = torch.zeros(4, dtype=torch.int64, device=device)
         self.l = A.MdPairlist()
         self.resize(cell_stride or default_cell_stride(params, ncell))
 
-    def resize(self, cell_stride: int):
+    def resize(self, cell_stride: int, entry_bits: int | None = None):
         self.cell_stride = int(cell_stride)
-        cap = int(np.prod(self.ncell)) * self.cell_stride
+        if entry_bits is not None:
+            self.entry_bits = int(entry_bits)
+        entries = int(np.prod(self.ncell)) * self.cell_stride
+        words = entries if self.entry_bits == 32 else (entries + 1) // 2
         self.nbr = None
-        self.nbr = torch.empty(cap, dtype=torch.int32, device=self.device)
+        self.nbr = torch.empty(words, dtype=torch.int32, device=self.device)
         self.fill(self.l)
 
     def fill(self, l: A.MdPairlist):
@@ -123,6 +129,16 @@ class PairList:
 
     def grow_for(self, needed: int):
         self.resize(int(64 * math.ceil(1.25 * needed / 64.0)))
+
+    def handle_capacity_error(self):
+        """After MD_ERR_CAPACITY from a state call: a cell block overflowed
+        (status[2] set: grow the stride), or the state needs 32-bit slot
+        entries in room made for 16-bit ones (widen)."""
+        status = self.status.cpu()
+        if int(status[2]) != 0:
+            self.grow_for(int(status[1]))
+        else:
+            self.resize(self.cell_stride, 32)
 
     def rows(self):
         """Host copy of the list: (offsets, counts, entries) as numpy arrays."""
@@ -161,7 +177,11 @@ class Engine:
         dev = self.device
         f64 = dict(dtype=torch.float64, device=dev)
         self.grid = Grid(self.params, dev)
-        self.plist = PairList(self.params, self.grid.ncell, dev, cell_stride)
+        # a re-sorted state keeps the tiled layout (16-bit entries) unless a
+        # tile's neighbourhood is too crowded to stage; the list is widened
+        # to slot entries only when the library asks for it
+        tiled = self.params.list_layout == A.MD_LIST_AUTO and resort_every > 0
+        self.plist = PairList(self.params, self.grid.ncell, dev, cell_stride, entry_bits=16 if tiled else 32)
         self.ws = Workspace(self.params, dev)
         p4 = np.zeros((n, 4))
         p4[:, :3] = pos
@@ -218,7 +238,7 @@ class Engine:
                     self._sync_pointers()
                     if e.code != A.MD_ERR_CAPACITY:
                         raise
-                    self.plist.grow_for(int(self.plist.status[1].item()))
+                    self.plist.handle_capacity_error()
                     self.plist.fill(self.state.list)
             self._sync_pointers()
         self.prepared = True
@@ -249,7 +269,7 @@ class Engine:
                 if err is not None:
                     if err.code != A.MD_ERR_CAPACITY:
                         raise err
-                    self.plist.grow_for(int(self.plist.status[1].item()))
+                    self.plist.handle_capacity_error()
                     self.plist.fill(self.state.list)
         return torch.cat(rows).numpy() if rows else np.zeros((0, 4))
 

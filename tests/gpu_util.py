@@ -78,6 +78,20 @@ class Standalone:
         torch.cuda.synchronize()
         return Hu.cpu().numpy().T.copy(), dp.cpu().numpy()
 
+    def adjoint_kick(self, u, out0, coef, with_u_out=True):
+        """md_adjoint_kick with u, out0 given as (n, 3) arrays: returns
+        (out, u_out or None, acc) with acc starting from zero."""
+        ut = torch.from_numpy(np.ascontiguousarray(u.T)).to(device())
+        out = torch.from_numpy(np.ascontiguousarray(out0.T)).to(device())
+        u_out = torch.empty_like(ut) if with_u_out else None
+        acc = torch.zeros(2, dtype=torch.float64, device=device())
+        self.A.md_adjoint_kick(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, ut.data_ptr(),
+                               out.data_ptr(), None if u_out is None else u_out.data_ptr(), tuple(coef),
+                               acc.data_ptr(), self.ws.ptr, self.ws.nbytes, self.stream)
+        torch.cuda.synchronize()
+        uo = None if u_out is None else u_out.cpu().numpy().T.copy()
+        return out.cpu().numpy().T.copy(), uo, acc.cpu().numpy()
+
     def param_grad(self):
         dU = torch.zeros(2, dtype=torch.float64, device=device())
         self.A.md_param_grad(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, dU.data_ptr(),
@@ -117,6 +131,34 @@ def force_error(F, Fref, S):
     """max_i |F_i - Fref_i| / S_i with S_i the sum of pair-force magnitudes on i."""
     err = np.linalg.norm(F - Fref, axis=1)
     return float(np.max(err / np.maximum(S, 1e-300)))
+
+
+def hvp_scale(q, L, u, pairs, eps=1.0, sigma=1.0):
+    """Per-particle scale of (H u)_i for an element-wise tolerance:
+    sum over the pairs within rc of h_ij |u_j - u_i|, with h_ij an upper bound
+    on the norm of the pair's 3x3 Hessian block (max(|V''|, |g|) <= |V''| + |g|,
+    bounded by the magnitudes of the r^-14 and r^-8 terms of the plain LJ
+    derivatives plus a margin for the small truncation terms).  A tolerance
+    scale, not a result: it only normalises the error."""
+    q = np.asarray(q, np.float64)
+    L = np.broadcast_to(np.asarray(L, np.float64), (3,))
+    i, j = pairs[:, 0].astype(np.int64), pairs[:, 1].astype(np.int64)
+    d = q[j] - q[i]
+    d -= L * np.rint(d / L)
+    r2 = np.einsum("ij,ij->i", d, d)
+    s6 = (sigma * sigma / r2) ** 3
+    h = 4.0 * eps * (168.0 * s6 * s6 + 48.0 * s6) / r2 + 0.1 * eps / (sigma * sigma)
+    du = np.linalg.norm(np.asarray(u)[j] - np.asarray(u)[i], axis=1)
+    out = np.zeros(q.shape[0])
+    np.add.at(out, i, h * du)
+    np.add.at(out, j, h * du)
+    return out
+
+
+def elementwise_error(X, Xref, scale):
+    """max_i |X_i - Xref_i| / scale_i (rows of (n, 3) arrays)."""
+    err = np.linalg.norm(np.asarray(X) - np.asarray(Xref), axis=1)
+    return float(np.max(err / np.maximum(scale, 1e-300)))
 
 
 def rows_for_slots(plist, slots):

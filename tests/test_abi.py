@@ -16,6 +16,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "md.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 @pytest.fixture(scope="module")
@@ -27,7 +29,7 @@ def A():
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(md_\w+)\s*\(", text, re.M)))
 
 
@@ -186,3 +188,17 @@ def test_workspace_too_small(A):
     with pytest.raises(A.MdError) as e:
         A.md_bin_cells(p, fake, cells, fake, 16, None)
     assert e.value.code == A.MD_ERR_WORKSPACE
+
+
+def test_hbm_probe_rejects_bad_arguments(A):
+    # host-side validation: nothing is launched, so fake pointers are never used
+    fake = 1 << 20
+    for kind, a, b, c, nbytes, reps in ((7, fake, fake, fake, 64, 1), (-1, fake, fake, fake, 64, 1),
+                                        (A.MD_PROBE_COPY, fake, None, None, 64, 1),
+                                        (A.MD_PROBE_TRIAD, fake, fake, None, 64, 1),
+                                        (A.MD_PROBE_READ, fake, fake, None, 65, 1),
+                                        (A.MD_PROBE_READ, None, fake, None, 64, 1),
+                                        (A.MD_PROBE_READ, fake, fake, None, 64, 0)):
+        with pytest.raises(A.MdError) as e:
+            A.md_hbm_probe(kind, a, b, c, nbytes, reps, None)
+        assert e.value.code == A.MD_ERR_ARG, (kind, nbytes, reps)

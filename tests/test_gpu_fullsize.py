@@ -14,6 +14,10 @@ The state is first advanced some steps (a disordered fluid with several
 rebuilds and re-sorts behind it), then md_prepare rebuilds the list at the
 current positions.  The half list (each pair once) gets the same row and
 force checks at 32M, its rows cut from the oracle's sets by the half rule.
+
+The adjoint passes (md_hvp, md_param_grad, md_adjoint_kick) are compared with
+the oracle element by element at the gradient workload's full size (256,000
+particles of an equilibrating fluid), one oracle pass each.
 """
 
 import numpy as np
@@ -67,6 +71,7 @@ def _check_state(ref, e, L, ids, tol):
 
 @pytest.mark.parametrize("config,precision,tol,steps", [
     ("lj32m", "mixed", 1e-5, 40),
+    ("lj32m", "fp64", 1e-12, 40),
     ("lj4m", "fp64", 1e-12, 40),
 ])
 def test_full_size_sampled_parity(ref, config, precision, tol, steps):
@@ -155,3 +160,48 @@ def test_half_list_full_size_sampled_parity(ref):
     F = e.forces()[ids]
     Fr, S, _, _, _ = ref.forces_sample(q, L, ids, rc=e.params.rc, rs=e.params.rs, grid=grid)
     assert G.force_error(F, Fr, S) <= 1e-5
+
+
+def test_adjoint_full_size_elementwise(ref):
+    """256,000 particles (the gradient workload), FP64: md_hvp, md_param_grad
+    and md_adjoint_kick against oracle.hvp / oracle.param_grad / oracle.forces
+    on every particle, with the per-particle scales of the pair terms
+    (gradients of one configuration: 1e-10)."""
+    from paper_1012_2677_amd import Engine
+
+    cfg = li.CONFIGS["lj256k"]
+    q, L = li.fcc_lattice(cfg["n_fcc"])
+    v = li.maxwell_boltzmann(q.shape[0], cfg["T"], seed=4)
+    n = q.shape[0]
+    e = Engine(q, v, L, rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], dt=cfg["dt"], precision="fp64",
+               resort_every=1, device="cuda:0")
+    e.step(40)
+    assert e.rebuilds > 3
+    q = e.positions()
+    del e
+    eps, sig = 1.05, 0.98
+    s = G.Standalone(q, L, eps=eps, sigma=sig)
+    s.params.dt = cfg["dt"]
+    s.bin()
+    assert s.build()[2] == 0
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(q.shape)
+    out0 = rng.standard_normal(q.shape)
+    pairs = ref.pairs_cells(q, L, cfg["rc"])
+    hs = G.hvp_scale(q, L, u, pairs, eps=eps, sigma=sig)
+    Hr, dpr = ref.hvp(q, L, u, eps=eps, sigma=sig)
+    Hu, dp = s.hvp(u)
+    assert G.elementwise_error(Hu, Hr, hs) <= 1e-10
+    assert dp == pytest.approx(dpr, rel=1e-10)
+    dUr = ref.param_grad(q, L, eps=eps, sigma=sig)
+    assert s.param_grad() == pytest.approx(dUr, rel=1e-10)
+    # the fused kick of the reverse sweep: out = out0 - h H u - w F,
+    # u_out = u + dt out, acc = h u . dF/dtheta + w dU/dtheta
+    h, w = 0.5 * cfg["dt"], 1.0 / 200
+    out, u_out, acc = s.adjoint_kick(u, out0, (1.0, -h, -w, h, w))
+    Fr, S, _, _, _ = ref.forces_sample(q, L, np.arange(n, dtype=np.int64), eps=eps, sigma=sig)
+    want = out0 - h * Hr - w * Fr
+    scale = np.linalg.norm(out0, axis=1) + h * hs + w * S
+    assert G.elementwise_error(out, want, scale) <= 1e-10
+    assert G.elementwise_error(u_out, u + cfg["dt"] * want, np.linalg.norm(u, axis=1) + cfg["dt"] * scale) <= 1e-10
+    assert acc == pytest.approx(h * dpr + w * dUr, rel=1e-10)

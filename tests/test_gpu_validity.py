@@ -17,6 +17,7 @@ import pytest
 import torch
 
 import lj_inputs as li
+from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
 
@@ -109,10 +110,12 @@ def test_dutc_ldc_never_misses_a_pair(ref):
     v = li.maxwell_boltzmann(q.shape[0], T=3.0, seed=12)
     e = _engine(q, v, L, precision="fp64", rebuild_rule="dutc_ldc", resort_every=1)
     e.prepare()
+    ids = np.arange(q.shape[0], dtype=np.int64)
     for _ in range(60):
         e.step(1)
-        Fr, _, _ = ref.forces(e.positions(), L)
-        assert np.abs(e.forces() - Fr).max() <= 1e-11 * max(1.0, np.abs(Fr).max())
+        pos = e.positions()
+        Fr, S, _, _, _ = ref.forces_sample(pos, L, ids)
+        assert G.force_error(e.forces(), Fr, S) <= 1e-12
     checks, kept = e.ldc_stats
     assert kept > 0
 
@@ -125,3 +128,56 @@ def test_mixed_with_dutc_ldc_tracks_fp64(ref):
     _, _, rlog, _ = ref.run(q, v, L, 100, dt=0.005, sample_every=10, rule="dutc_ldc")
     n = q.shape[0]
     assert np.abs(log[:, 3] - rlog[:, 3]).max() / n < 1e-5
+
+
+def _sparse_pair_box():
+    """A sparse box (L = 20, 7 cells of 2.857 per axis, 5 interior) holding a
+    pair A-B listed across the x = 0 face (B in cell 0 at x = 0.3, A in the
+    interior cell 1 at x = 3.0, distance 2.7 < rs), and isolated particles on
+    a cubic lattice of spacing 4 kept more than 5 away from both."""
+    L = 20.0
+    g = np.arange(5) * 4.0 + 2.0
+    lat = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    c = np.array([1.65, 10.0, 10.0])
+    d = lat - c
+    d -= L * np.rint(d / L)
+    lat = lat[np.linalg.norm(d, axis=1) > 5.0]
+    pair = np.array([[3.0, 10.0, 10.0], [0.3, 10.0, 10.0]])
+    return np.concatenate([pair, lat]), L
+
+
+@pytest.mark.parametrize("precision,layout,tile_cells", [
+    ("fp64", "auto", 1), ("fp64", "slots", 0), ("mixed", "auto", 1), ("mixed", "slots", 0)])
+def test_dutc_ldc_kept_list_after_large_moves_uses_minimum_images(ref, precision, layout, tile_cells):
+    # Under DUTC + LDC a kept list can outlive moves larger than (cell side -
+    # rc).  Here B crosses the x = 0 face (it is stored at x = L - 0.05) and A
+    # moves 0.8 towards it, out of its interior build-time cell's margin: their
+    # minimum-image distance is 2.25 < rc.  The check keeps the list (the pair
+    # was listed, nobody else is near), so the force pass must take the minimum
+    # image for the interior key A as well.
+    q, L = _sparse_pair_box()
+    n = q.shape[0]
+    v = np.zeros_like(q)
+    e = _engine(q, v, L, precision=precision, rebuild_rule="dutc_ldc", list_layout=layout,
+                tile_cells=tile_cells, resort_every=1)
+    e.prepare()
+    e.step(1)
+    assert int(e.state.list_tiled) == (1 if layout == "auto" else 0)
+    r0, (c0, k0) = e.rebuilds, e.ldc_stats
+    qold = e.positions()
+    slot_of_id = torch.empty_like(e.id.long())
+    slot_of_id[e.id.long()] = torch.arange(n, device=e.id.device)
+    sa, sb = int(slot_of_id[0]), int(slot_of_id[1])
+    e.pos[sa, 0] = 2.2
+    e.pos[sb, 0] = L - 0.05
+    qnew = e.positions()
+    ok, members, _ = ref.ldc_check(qnew, qold, L)
+    assert ok and members == n
+    e.state.dutc_buffer = 0.0      # the DUTC buffer is used up: the check decides
+    e.step(1)
+    assert e.rebuilds == r0 and e.ldc_stats == (c0 + 1, k0 + 1)
+    pos = e.positions()
+    assert np.allclose(pos, qnew)
+    Fr, S, _, _, _ = ref.forces_sample(pos, L, np.arange(n, dtype=np.int64))
+    assert np.linalg.norm(Fr[0]) > 0.01 and S[0] > 0.01
+    assert G.force_error(e.forces(), Fr, S) <= (1e-12 if precision == "fp64" else 1e-5)
