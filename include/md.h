@@ -315,6 +315,23 @@ int md_forces(const md_params* p, const double* pos, const md_cells* cells,
               const md_pairlist* list, void* force, double* pe_w,
               void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): md_forces
+ * with its workspace taken from a fixed scratch array inside the library
+ * instead of a ws argument, for at most MD_NOALLOC_MAX_N particles (larger n:
+ * MD_ERR_ARG, nothing launched).  The array holds 16 bytes per particle of
+ * local coordinates (mixed precision), the per-block energy partials and a
+ * flag word: 16 MiB + 64 KiB + 256 B on each device the library runs on,
+ * kept until the process ends.  The call allocates and frees nothing; the
+ * caller passes every input and output as for md_forces, whose results it
+ * gives bit for bit.  Every call on one device shares that device's array
+ * (the call clears what must start at zero), so calls on one device that
+ * overlap in time, on different streams or from different threads, race:
+ * order them on one stream. */
+#define MD_NOALLOC_MAX_N ((int64_t)1 << 20)
+int md_forces_noalloc(const md_params* p, const double* pos, const md_cells* cells,
+                      const md_pairlist* list, void* force, double* pe_w, hipStream_t stream);
+
 /* Large-displacement check (Sec. 2.3, Alg. alg_validity_check) of a list
  * built at pos_ref, at positions pos: the particles whose displacement
  * |minimg(q - q_ref)| exceeds t = (rs - rc) - max displacement - 1e-12 are

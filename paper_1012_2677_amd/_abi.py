@@ -37,7 +37,8 @@ TIMER_NAMES = ["force", "integrate", "bin", "resort", "build", "reduce", "check"
 
 EXPORTED = ["md_cell_dims", "md_workspace_bytes", "md_pack_positions", "md_bin_cells", "md_resort", "md_build_pairlist",
             "md_forces", "md_prepare", "md_step", "md_energy", "md_hvp", "md_adjoint_kick", "md_param_grad",
-            "md_ldc_check", "md_last_error", "md_hbm_probe"]
+            "md_ldc_check", "md_last_error", "md_hbm_probe", "md_forces_noalloc"]
+MD_NOALLOC_MAX_N = 1 << 20
 
 MD_PROBE_READ, MD_PROBE_COPY, MD_PROBE_TRIAD, MD_PROBE_NT = 0, 1, 2, 4
 
@@ -116,6 +117,7 @@ def lib():
                                    C.c_size_t, vp]),
         "md_last_error": (C.c_char_p, []),
         "md_hbm_probe": (C.c_int, [C.c_int32, vp, vp, vp, C.c_size_t, C.c_int32, P(C.c_float), vp]),
+        "md_forces_noalloc": (C.c_int, [P(MdParams), vp, P(MdCells), P(MdPairlist), vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -168,6 +170,11 @@ def md_build_pairlist(params, pos, cells, plist, ws, ws_bytes, stream):
 def md_forces(params, pos, cells, plist, force, pe_w, ws, ws_bytes, stream):
     return _check(lib().md_forces(C.byref(params), pos, C.byref(cells), C.byref(plist), force, pe_w, ws,
                                   ws_bytes, stream), "md_forces")
+
+
+def md_forces_noalloc(params, pos, cells, plist, force, pe_w, stream):
+    return _check(lib().md_forces_noalloc(C.byref(params), pos, C.byref(cells), C.byref(plist), force, pe_w,
+                                          stream), "md_forces_noalloc")
 
 
 def md_prepare(params, state, stream):

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <utility>
 
 #include "md_internal.h"
@@ -356,6 +357,29 @@ int md_build_pairlist(const md_params* p, const double* pos, const md_cells* cel
     return MD_OK;
 }
 
+// The force pass of md_forces and md_forces_noalloc, with its scratch given:
+// pos32 (mixed precision: float4 per particle), part (2 doubles per block of
+// the pass) and one flag word (cleared here).
+static int forces_with(const Ctx& c, const md_params* p, const double* pos, const md_cells* cells,
+                       const md_pairlist* list, void* force, double* pe_w, float* pos32, double* part,
+                       int64_t* flags, hipStream_t stream)
+{
+    MD_HIP(launch_fill_i32((int32_t*)flags, 0, 2, stream), "md_forces/flags");
+    if (p->precision == MD_MIXED)
+        MD_HIP(launch_ref_copy(c.g, pos, cells->cell_xyz, nullptr, pos32, stream), "md_forces/pos32");
+    else
+        pos32 = nullptr;
+    ForceOut out;
+    out.force = force;
+    out.part = pe_w ? part : nullptr;
+    out.flags = flags;
+    MD_HIP(launch_forces(c.g, c.lj, p->precision, pos, pos32, cells->cell_xyz, *list, out, stream),
+           "md_forces");
+    if (pe_w)
+        MD_HIP(launch_reduce_pair(out.part, force_blocks(c.g, false), 1.0, 1.0, pe_w, stream), "md_forces/reduce");
+    return MD_OK;
+}
+
 int md_forces(const md_params* p, const double* pos, const md_cells* cells, const md_pairlist* list,
               void* force, double* pe_w, void* ws, size_t ws_bytes, hipStream_t stream)
 {
@@ -367,20 +391,64 @@ int md_forces(const md_params* p, const double* pos, const md_cells* cells, cons
     if ((rc = check_slot_list(c, list, true)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
     char* w = (char*)ws;
-    float* pos32 = nullptr;
-    if (p->precision == MD_MIXED) {
-        pos32 = (float*)(w + c.W.pos32);
-        MD_HIP(launch_ref_copy(c.g, pos, cells->cell_xyz, nullptr, pos32, stream), "md_forces/pos32");
+    return forces_with(c, p, pos, cells, list, force, pe_w, (float*)(w + c.W.pos32), (double*)(w + c.W.part_a),
+                       (int64_t*)(w + c.W.scal) + 2, stream);
+}
+
+// ---------------------------------------------------------------------------
+// md_forces_noalloc: the scratch of md_forces in a file-scope device array.
+// Layout: local coordinates (16 bytes per particle, mixed precision), then
+// the per-block (PE, W) partials, then the flag words.  Host code reaches the
+// array only through the address hipGetSymbolAddress gives on each device.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocMaxN = MD_NOALLOC_MAX_N;
+constexpr size_t kNoAllocPos32 = 16 * (size_t)kNoAllocMaxN;
+constexpr size_t kNoAllocPart = sizeof(double) * 2 * (size_t)((kNoAllocMaxN + kForceBlock - 1) / kForceBlock);
+constexpr size_t kNoAllocFlags = 256;
+constexpr size_t kNoAllocBytes = kNoAllocPos32 + kNoAllocPart + kNoAllocFlags;
+static_assert(kNoAllocPos32 % 256 == 0 && kNoAllocPart % 256 == 0, "scratch regions stay 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kNoAllocDevices] = {};
+
+// Device address of the current device's copy of scratch, looked up once per
+// device (with that device current) and kept.
+static int scratch_address(void** out)
+{
+    int dev = -1;
+    MD_HIP(hipGetDevice(&dev), "md_forces_noalloc/device");
+    if (dev < 0 || dev >= kNoAllocDevices) return fail(MD_ERR_ARG, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        MD_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "md_forces_noalloc/scratch address");
+        if (!ptr) return fail(MD_ERR_HIP, "md_forces_noalloc: no address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
     }
-    ForceOut out;
-    out.force = force;
-    out.part = pe_w ? (double*)(w + c.W.part_a) : nullptr;
-    out.flags = (int64_t*)(w + c.W.scal) + 2;
-    MD_HIP(launch_forces(c.g, c.lj, p->precision, pos, pos32, cells->cell_xyz, *list, out, stream),
-           "md_forces");
-    if (pe_w)
-        MD_HIP(launch_reduce_pair(out.part, force_blocks(c.g, false), 1.0, 1.0, pe_w, stream), "md_forces/reduce");
+    *out = g_scratch_ptr[dev];
     return MD_OK;
+}
+
+int md_forces_noalloc(const md_params* p, const double* pos, const md_cells* cells, const md_pairlist* list,
+                      void* force, double* pe_w, hipStream_t stream)
+{
+    Ctx c;
+    int rc = setup(p, c);
+    if (rc != MD_OK) return rc;
+    if (!pos || !force) return fail(MD_ERR_ARG, "pos or force is NULL");
+    if (p->n > kNoAllocMaxN)
+        return fail(MD_ERR_ARG, "md_forces_noalloc takes at most %lld particles (n = %lld); use md_forces",
+                    (long long)kNoAllocMaxN, (long long)p->n);
+    if ((rc = check_cells(c, cells)) != MD_OK) return rc;
+    if ((rc = check_slot_list(c, list, true)) != MD_OK) return rc;
+    void* base = nullptr;
+    if ((rc = scratch_address(&base)) != MD_OK) return rc;
+    char* w = (char*)base;
+    return forces_with(c, p, pos, cells, list, force, pe_w, (float*)w, (double*)(w + kNoAllocPos32),
+                       (int64_t*)(w + kNoAllocPos32 + kNoAllocPart), stream);
 }
 
 int md_hvp(const md_params* p, const double* pos, const md_cells* cells, const md_pairlist* list,
