@@ -235,7 +235,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
         "list_half": half,
         "tile_cells": int(e.state.tile_cells),
         "list_cell_stride": int(e.plist.cell_stride),
-        "list_largest_cell_block": int(e.plist.status[1].item()),
+        "list_stride_needed": int(e.plist.status[1].item()),
         "timers_ms": {k: [round(m, 3), c] for k, (m, c) in tim.items()},
         "energy_per_particle_start": float(e0[3] / n),
         "energy_per_particle_samples": [float(x) for x in e_pp],

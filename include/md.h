@@ -219,10 +219,16 @@ typedef struct md_timers {
  *   made, and those that kept the list.
  *   list_tiled: 1 when st->list holds the tiled layout (set by the library):
  *   nbr is then read as uint16 entries, offsets count uint16 units, and the
- *   rows of cell c live in ((uint16_t*)nbr)[c*cell_stride ..), each row
- *   starting at an even entry (a row of odd length is followed by one entry
- *   naming the stand-in just past the tile's neighbourhood, counted in the
- *   list status but not in the row's count); tile_stage:
+ *   cells of a tile share one pooled block: ((uint16_t*)nbr)[c0*cell_stride
+ *   .. (c0 + k)*cell_stride) for a tile of k cells whose first cell is c0.
+ *   Each cell's rows lie together in the pool (a cell takes its slice when
+ *   its rows are made, so the order of the slices varies from build to
+ *   build; the rows themselves do not).  status[1] then gives the stride the
+ *   fullest tile needs (its entries over its cells, rounded up) and status[2]
+ *   is set when some tile's pool overflowed.  Each row starts at an even
+ *   entry (a row of odd length is followed by one entry naming the stand-in
+ *   just past the tile's neighbourhood, counted in the list status but not
+ *   in the row's count); tile_stage:
  *   the largest neighbourhood of a tile, in particles; tile_cells: the tile
  *   length along z in cells. */
 typedef struct md_state {

@@ -156,6 +156,7 @@ WsLayout ws_layout(const Geo& g, int64_t ldc_max, int precision)
     L.scal = off;      off = align256(off + sizeof(int64_t) * 32);
     L.tmax = off;      off = align256(off + sizeof(int64_t) * kTileMaxSlots);
     L.mx = off;        off = align256(off + sizeof(int64_t) * 2 * kMaxSlots * kMaxSlotStride);
+    L.tile_used = off; off = align256(off + sizeof(int32_t) * (size_t)(g.ntile > 0 ? g.ntile : 1));
     L.total = off;
     return L;
 }
@@ -679,7 +680,7 @@ static IntArgs int_args(const Ctx& c, const md_params* p, md_state* st, bool ke)
 static int check_status(const int64_t f[16], const md_state* st)
 {
     if (f[2] != 0)
-        return fail(MD_ERR_CAPACITY, "pair list overflow: a cell needs %lld entries, cell_stride is %lld",
+        return fail(MD_ERR_CAPACITY, "pair list overflow: the list needs a cell_stride of %lld, it is %lld",
                     (long long)f[1], (long long)st->list.cell_stride);
     if (f[4] & 2) return fail(MD_ERR_ARG, "positions outside [0, L) given to the cell grid");
     if (f[6] & 1) return fail(MD_ERR_NONFINITE, "non-finite force");

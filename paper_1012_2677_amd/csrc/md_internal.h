@@ -71,6 +71,27 @@ __host__ __device__ inline unsigned long long* max_slot(unsigned long long* base
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Division of 0 <= x < 2^31 by a divisor d >= 1 fixed at launch, by a
+// multiply-high and a shift (division by invariant integers): with
+// s = ceil(log2 d) and m = floor(2^32 (2^s - d) / d) + 1, x / d equals
+// (umulhi(x, m) + x) >> s.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f;
+    f.d = d;
+    f.s = 0;
+    while ((1ull << f.s) < d) ++f.s;
+    f.m = (uint32_t)((((1ull << 32) * ((1ull << f.s) - d)) / d) + 1);
+    return f;
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f)
+{
+    return (__umulhi(x, f.m) + x) >> f.s;
+}
+
 // ---------------------------------------------------------------------------
 // Geometry derived on the host from md_params (FP64, computed once)
 // ---------------------------------------------------------------------------
@@ -129,6 +150,7 @@ struct WsLayout {
     size_t scal;       // int64[32]      small device scalars (layout in md_api.hip)
     size_t tmax;       // int64[kTileMaxSlots]  largest staged tile neighbourhood, spread over slots
     size_t mx;         // int64[2][kMaxSlots * kMaxSlotStride]  block maxima of d2 and v2
+    size_t tile_used;  // int32[ntile]   entries taken in each tile's pooled block (tiled list build)
     size_t total;
     int64_t nbs;       // scan blocks
     int64_t nbf;       // adjoint-kernel blocks (kKeysPerBlock keys each)

@@ -37,6 +37,10 @@ struct BuildArgs {
     int64_t* status;
     int32_t tc;                       // tiled: cells per tile along z
     unsigned long long* tile_max;     // tiled: atomic max of the staged count per tile
+    FastDiv div_nz;                   // division by nz and by kBuildStrip * ny (cell order decode)
+    FastDiv div_strip;
+    int32_t nt;                       // tiled: tiles per column
+    int32_t* tile_used;               // tiled: entries taken so far in each tile's pooled block
 };
 
 // r^2 of the pinned predicate: d = q_j - q_i, optional minimum image,
@@ -58,10 +62,10 @@ __device__ __forceinline__ double pair_r2(const BuildArgs& a, double xj, double 
 // the entries actually stored, so an invalid (overflowed) list still only
 // references written, in-range entries.
 __device__ __forceinline__ void write_row(const BuildArgs& a, int32_t kslot, int64_t base, int64_t used,
-                                          int64_t wpos)
+                                          int64_t wpos, int64_t cap)
 {
-    const int64_t start = used < a.stride ? used : a.stride;
-    const int64_t room = a.stride - start;
+    const int64_t start = used < cap ? used : cap;
+    const int64_t room = cap - start;
     a.offsets[kslot] = base + start;
     a.counts[kslot] = (int32_t)(wpos < room ? wpos : room);
 }
@@ -92,8 +96,10 @@ __device__ __forceinline__ void pad_row(E* blk, uint32_t stride, uint32_t* s_row
     }
 }
 
-// Keys of one cell against candidates held in registers (at most NCH*64).
-// Empty candidate slots carry NaN coordinates, so r2 < rs2 fails for them in
+// Keys of one cell against candidates held in registers: NACT chunks of 64
+// (the cell's neighbourhood rounded up; the key loop is instantiated per
+// chunk count, so the unrolled chunk sequence carries no branch).  Empty
+// candidate slots carry a NaN x coordinate, so r2 < rs2 fails for them in
 // both the plain and the minimum-image form of the test.  The key itself is
 // candidate number self_t.  Output positions come from mbcnt of the row mask,
 // counted on from the row's start.
@@ -105,61 +111,57 @@ __device__ __forceinline__ void pad_row(E* blk, uint32_t stride, uint32_t* s_row
 // Fast form (the key's row surely fits in the LDS row buffer): the row mask is
 // the ballot of the distance test minus the key's own lane; every lane stores,
 // those outside the mask into a spare LDS word, so there is no branch and no
-// exec-mask change per chunk.
-template <bool MINIMG, int NCH, bool HALF>
-__device__ __forceinline__ uint32_t row_chunks_lds(const BuildArgs& a, int T, const double4& kp, int self_t,
+// exec-mask change per chunk.  The drop test is one vector compare of the
+// lane against the key's place in the chunk (a scalar mask built from that
+// place would cost several scalar instructions per chunk, and the scalar unit
+// is as busy as the vector unit here).
+template <bool MINIMG, int NACT, bool HALF>
+__device__ __forceinline__ uint32_t row_chunks_lds(const BuildArgs& a, const double4& kp, int self_t,
                                                    uint32_t w0, const double* cx, const double* cy,
                                                    const double* cz, const uint32_t* meta, uint32_t* s_rows)
 {
     const int lane = (int)lane_id();
     uint32_t wpos = w0;
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-        if (ch * 64 < T) {
-            const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
-            const bool in = r2 < a.rs2;
-            const bool self = HALF ? ch * 64 + lane <= self_t : lane == self_t - ch * 64;
-            const uint64_t m = __builtin_amdgcn_ballot_w64(in) & ~__builtin_amdgcn_ballot_w64(self);
-            const uint32_t wb = (mbcnt64(m) + wpos) << 2;   // byte offset in the row buffer
-            *(uint32_t*)((char*)s_rows + (__builtin_amdgcn_inverse_ballot_w64(m) ? wb : 4u * kRowBuf)) = meta[ch];
-            wpos += (uint32_t)__popcll(m);
-        }
+    for (int ch = 0; ch < NACT; ++ch) {
+        const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
+        const bool in = r2 < a.rs2;
+        const bool drop = HALF ? lane <= self_t - ch * 64 : lane == self_t - ch * 64;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(in) & ~__builtin_amdgcn_ballot_w64(drop);
+        const uint32_t wb = (mbcnt64(m) + wpos) << 2;   // byte offset in the row buffer
+        *(uint32_t*)((char*)s_rows + (__builtin_amdgcn_inverse_ballot_w64(m) ? wb : 4u * kRowBuf)) = meta[ch];
+        wpos += (uint32_t)__popcll(m);
     }
     return wpos;
 }
 
 // General form: entries go to the LDS row buffer while they fit in it, past
 // that straight to the cell block with a capacity test.
-template <bool MINIMG, int NCH, typename E, bool HALF>
-__device__ __forceinline__ uint32_t row_chunks(const BuildArgs& a, E* blk, uint32_t stride, int T,
-                                               const double4& kp, int self_t, uint32_t w0, const double* cx,
-                                               const double* cy, const double* cz, const uint32_t* meta,
-                                               uint32_t* s_rows)
+template <bool MINIMG, int NACT, typename E, bool HALF>
+__device__ __forceinline__ uint32_t row_chunks(const BuildArgs& a, E* blk, uint32_t stride, const double4& kp,
+                                               int self_t, uint32_t w0, const double* cx, const double* cy,
+                                               const double* cz, const uint32_t* meta, uint32_t* s_rows)
 {
     const int lane = (int)lane_id();
     uint32_t wpos = w0;
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) {
-        if (ch * 64 < T) {
-            const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
-            const bool in = r2 < a.rs2;
-            uint64_t m = __builtin_amdgcn_ballot_w64(in);
-            const int sl = self_t - ch * 64;          // the key's own lane in this chunk, if any
-            const bool drop = HALF ? lane <= sl : lane == sl;
-            if (HALF) m &= ~__builtin_amdgcn_ballot_w64(drop);
-            else if (sl >= 0 && sl < 64) m &= ~(1ull << sl);
-            const uint32_t w = mbcnt64(m) + wpos;
-            if (in && !drop) {
-                if (w < (uint32_t)kRowBuf) s_rows[w] = meta[ch];
-                else if (w < stride) blk[w] = (E)meta[ch];
-            }
-            wpos += (uint32_t)__popcll(m);
+    for (int ch = 0; ch < NACT; ++ch) {
+        const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
+        const bool in = r2 < a.rs2;
+        const int sl = self_t - ch * 64;          // the key's own lane in this chunk, if any
+        const bool drop = HALF ? lane <= sl : lane == sl;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(in) & ~__builtin_amdgcn_ballot_w64(drop);
+        const uint32_t w = mbcnt64(m) + wpos;
+        if (in && !drop) {
+            if (w < (uint32_t)kRowBuf) s_rows[w] = meta[ch];
+            else if (w < stride) blk[w] = (E)meta[ch];
         }
+        wpos += (uint32_t)__popcll(m);
     }
     return wpos;
 }
 
-template <bool MINIMG, int NCH, typename E, bool HALF>
+template <bool MINIMG, int NACT, typename E, bool HALF>
 __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* blk, uint32_t stride,
                                                        int T, int own_pref, int own_cnt, const double4* s_key,
                                                        const double* cx, const double* cy, const double* cz,
@@ -169,11 +171,10 @@ __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* b
     uint32_t used = 0;
     for (int kk = 0; kk < own_cnt; ++kk) {
         if (used + (uint32_t)T <= (uint32_t)kRowBuf)
-            used = row_chunks_lds<MINIMG, NCH, HALF>(a, T, s_key[kk], own_pref + kk, used, cx, cy, cz, meta,
-                                                     s_rows);
+            used = row_chunks_lds<MINIMG, NACT, HALF>(a, s_key[kk], own_pref + kk, used, cx, cy, cz, meta, s_rows);
         else
-            used = row_chunks<MINIMG, NCH, E, HALF>(a, blk, stride, T, s_key[kk], own_pref + kk, used, cx, cy, cz,
-                                                    meta, s_rows);
+            used = row_chunks<MINIMG, NACT, E, HALF>(a, blk, stride, s_key[kk], own_pref + kk, used, cx, cy, cz,
+                                                     meta, s_rows);
         if (lane_id() == 0) s_rowend[kk] = used;
         pad_row<E>(blk, stride, s_rows, used, pad);
         used = row_start<E>(used);
@@ -195,15 +196,180 @@ __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* b
     const int kk = (int)lane_id();
     if (kk < own_cnt) {
         const uint32_t end = s_rowend[kk], beg = kk > 0 ? row_start<E>(s_rowend[kk - 1]) : 0u;
-        write_row(a, (int32_t)__double_as_longlong(s_key[kk].w), (int64_t)(blk - (E*)a.nbr), beg, end - beg);
+        write_row(a, (int32_t)__double_as_longlong(s_key[kk].w), (int64_t)(blk - (E*)a.nbr), beg, end - beg,
+                  a.stride);
     }
     return used;
+}
+
+// Tiled rows.  The cells of a tile share one pooled block of tile_cells *
+// cell_stride 16-bit entries (the first cell's block and those after it): a
+// cell stages its rows in LDS as 16-bit entries, then takes its slice of the
+// pool with one atomic add and writes it with full-wave 32-bit stores, so the
+// pool has to hold the tile's total rather than every cell the largest cell's
+// rows.  The order of the slices inside a pool follows the order in which the
+// cells finish.  A cell whose rows outgrow the LDS buffer counts the rest,
+// takes its slice, and computes those rows again straight into it.
+constexpr int kRowBuf16 = 2048;   // 16-bit entries of one tiled cell staged in LDS (the row buffer's 4 KB)
+
+template <bool MINIMG, int NACT>
+__device__ __forceinline__ uint32_t tiled_row_lds(const BuildArgs& a, const double4& kp, int self_t, uint32_t w0,
+                                                  const double* cx, const double* cy, const double* cz,
+                                                  const uint32_t* meta, uint16_t* s_rows16)
+{
+    const int lane = (int)lane_id();
+    uint32_t wpos = w0;
+#pragma unroll
+    for (int ch = 0; ch < NACT; ++ch) {
+        const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
+        const bool in = r2 < a.rs2;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(in) & ~__builtin_amdgcn_ballot_w64(lane == self_t - ch * 64);
+        const uint32_t wb = (mbcnt64(m) + wpos) << 1;   // byte offset in the row buffer
+        *(uint16_t*)((char*)s_rows16 + (__builtin_amdgcn_inverse_ballot_w64(m) ? wb : 2u * kRowBuf16)) =
+            (uint16_t)meta[ch];
+        wpos += (uint32_t)__popcll(m);
+    }
+    return wpos;
+}
+
+// the same row, counted only (STORE = false) or written to dst[w0 ..]
+template <bool MINIMG, int NACT, bool STORE>
+__device__ __forceinline__ uint32_t tiled_row_direct(const BuildArgs& a, const double4& kp, int self_t, uint32_t w0,
+                                                     const double* cx, const double* cy, const double* cz,
+                                                     const uint32_t* meta, uint16_t* dst)
+{
+    const int lane = (int)lane_id();
+    uint32_t wpos = w0;
+#pragma unroll
+    for (int ch = 0; ch < NACT; ++ch) {
+        const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
+        const bool in = r2 < a.rs2 && lane != self_t - ch * 64;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(in);
+        if (STORE && in) dst[mbcnt64(m) + wpos] = (uint16_t)meta[ch];
+        wpos += (uint32_t)__popcll(m);
+    }
+    return wpos;
+}
+
+// One tiled cell: rows, its slice of the tile's pool and the row headers.
+// Returns the entries the cell takes (even).
+template <bool MINIMG, int NACT>
+__device__ __forceinline__ uint32_t tiled_rows_from_registers(const BuildArgs& a, uint16_t* tblk, uint64_t tcap,
+                                                             int32_t* tile_used, int T, int own_pref, int own_cnt,
+                                                             const double4* s_key, const double* cx,
+                                                             const double* cy, const double* cz,
+                                                             const uint32_t* meta, uint16_t* s_rows16,
+                                                             uint32_t* s_rowend, uint32_t pad)
+{
+    const int lane = (int)lane_id();
+    uint32_t used = 0;
+    int kk = 0;
+    // rows staged while they surely fit: a row adds at most T - 1 entries
+    for (; kk < own_cnt && used + (uint32_t)T <= (uint32_t)kRowBuf16; ++kk) {
+        used = tiled_row_lds<MINIMG, NACT>(a, s_key[kk], own_pref + kk, used, cx, cy, cz, meta, s_rows16);
+        if (lane == 0) {
+            s_rowend[kk] = used;
+            if (used & 1u) s_rows16[used] = (uint16_t)pad;
+        }
+        used = (used + 1u) & ~1u;
+    }
+    const int ks = kk;
+    const uint32_t staged = used;
+    // the rest counted, then computed again into the slice below
+    for (int k2 = ks; k2 < own_cnt; ++k2) {
+        used = tiled_row_direct<MINIMG, NACT, false>(a, s_key[k2], own_pref + k2, used, cx, cy, cz, meta, nullptr);
+        if (lane == 0) s_rowend[k2] = used;
+        used = (used + 1u) & ~1u;
+    }
+    uint32_t base = 0;
+    if (lane == 0) base = (uint32_t)atomicAdd(tile_used, (int32_t)used);
+    base = __builtin_amdgcn_readfirstlane(base);
+    const bool fits = (uint64_t)base + used <= tcap;
+    if (!fits && lane == 0) atomicOr((unsigned long long*)&a.status[2], 1ull);
+    __syncthreads();
+    uint16_t* dst = tblk + base;
+    if (fits) {
+        // base and staged are even and the pool starts 4-byte aligned
+        uint32_t* dst2 = (uint32_t*)dst;
+        const uint32_t* src2 = (const uint32_t*)s_rows16;
+        for (uint32_t t = lane; 2 * t < staged; t += 64) dst2[t] = src2[t];
+        uint32_t w = staged;
+        for (int k2 = ks; k2 < own_cnt; ++k2) {
+            w = tiled_row_direct<MINIMG, NACT, true>(a, s_key[k2], own_pref + k2, w, cx, cy, cz, meta, dst);
+            if (lane == 0 && (w & 1u)) dst[w] = (uint16_t)pad;
+            w = (w + 1u) & ~1u;
+        }
+    }
+    if (lane < own_cnt) {
+        const uint32_t end = s_rowend[lane], beg = lane > 0 ? (s_rowend[lane - 1] + 1u) & ~1u : 0u;
+        const int32_t kslot = (int32_t)__double_as_longlong(s_key[lane].w);
+        // an overflowed cell (list invalid) keeps in-range, empty rows
+        a.offsets[kslot] = (int64_t)((fits ? dst : tblk) - (uint16_t*)a.nbr) + (fits ? beg : 0u);
+        a.counts[kslot] = fits ? (int32_t)(end - beg) : 0;
+    }
+    return used;
+}
+
+template <bool MINIMG, int NCH>
+__device__ __forceinline__ uint32_t tiled_rows_for_chunks(int nact, const BuildArgs& a, uint16_t* tblk, uint64_t tcap,
+                                                         int32_t* tile_used, int T, int own_pref, int own_cnt,
+                                                         const double4* s_key, const double* cx, const double* cy,
+                                                         const double* cz, const uint32_t* meta, uint16_t* s_rows16,
+                                                         uint32_t* s_rowend, uint32_t pad)
+{
+    static_assert(NCH == 8, "one case per chunk count");
+#define MD_TROWS_CASE(N) \
+    case N:              \
+        return tiled_rows_from_registers<MINIMG, N>(a, tblk, tcap, tile_used, T, own_pref, own_cnt, s_key, cx, cy, \
+                                                    cz, meta, s_rows16, s_rowend, pad);
+    switch (nact) {
+        MD_TROWS_CASE(1)
+        MD_TROWS_CASE(2)
+        MD_TROWS_CASE(3)
+        MD_TROWS_CASE(4)
+        MD_TROWS_CASE(5)
+        MD_TROWS_CASE(6)
+        MD_TROWS_CASE(7)
+        default:
+            return tiled_rows_from_registers<MINIMG, 8>(a, tblk, tcap, tile_used, T, own_pref, own_cnt, s_key, cx,
+                                                        cy, cz, meta, s_rows16, s_rowend, pad);
+    }
+#undef MD_TROWS_CASE
+}
+
+// The key loop for the cell's chunk count nact in [1, NCH].
+template <bool MINIMG, int NCH, typename E, bool HALF>
+__device__ __forceinline__ uint32_t rows_for_chunks(int nact, const BuildArgs& a, E* blk, uint32_t stride, int T,
+                                                   int own_pref, int own_cnt, const double4* s_key, const double* cx,
+                                                   const double* cy, const double* cz, const uint32_t* meta,
+                                                   uint32_t* s_rows, uint32_t* s_rowend, uint32_t pad)
+{
+    static_assert(NCH == 8, "one case per chunk count");
+#define MD_ROWS_CASE(N) \
+    case N:             \
+        return rows_from_registers<MINIMG, N, E, HALF>(a, blk, stride, T, own_pref, own_cnt, s_key, cx, cy, cz, meta, \
+                                                        s_rows, s_rowend, pad);
+    switch (nact) {
+        MD_ROWS_CASE(1)
+        MD_ROWS_CASE(2)
+        MD_ROWS_CASE(3)
+        MD_ROWS_CASE(4)
+        MD_ROWS_CASE(5)
+        MD_ROWS_CASE(6)
+        MD_ROWS_CASE(7)
+        default:
+            return rows_from_registers<MINIMG, 8, E, HALF>(a, blk, stride, T, own_pref, own_cnt, s_key, cx, cy, cz,
+                                                           meta, s_rows, s_rowend, pad);
+    }
+#undef MD_ROWS_CASE
 }
 
 // Same rows, candidates re-read from memory for every key (neighbourhoods with
 // more than NCH*64 particles or cells with more than 64 particles: never at
 // liquid densities, kept for generality).
-template <bool MINIMG, typename E, bool HALF>
+// COUNT: only the rows' total (with the even starts of 16-bit rows) is
+// returned, nothing is written.
+template <bool MINIMG, typename E, bool HALF, bool COUNT = false>
 __device__ uint32_t rows_from_memory(const BuildArgs& a, E* blk, uint32_t stride, int T, int own_start,
                                      int own_cnt, const int* s_pref, const int* s_nstart, const int* s_lbase,
                                      uint32_t pad)
@@ -231,11 +397,11 @@ __device__ uint32_t rows_from_memory(const BuildArgs& a, E* blk, uint32_t stride
             }
             const uint64_t m = __ballot(pass);
             const uint32_t w = used + wpos + mbcnt64(m);
-            if (pass && w < stride) blk[w] = (E)meta;
+            if (!COUNT && pass && w < stride) blk[w] = (E)meta;
             wpos += (uint32_t)__popcll(m);
         }
-        if (lane_id() == 0) {
-            write_row(a, kslot, (int64_t)(blk - (E*)a.nbr), used, wpos);
+        if (!COUNT && lane_id() == 0) {
+            write_row(a, kslot, (int64_t)(blk - (E*)a.nbr), used, wpos, stride);
             if (sizeof(E) == 2 && ((used + wpos) & 1u) && used + wpos < stride) blk[used + wpos] = (E)pad;
         }
         used = row_start<E>(used + wpos);
@@ -247,25 +413,32 @@ template <int NCH, bool TILED, bool HALF>
 __global__ __launch_bounds__(64) void k_build(BuildArgs a)
 {
     using E = typename std::conditional<TILED, uint16_t, uint32_t>::type;
-    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    if (t >= a.ncell) return;
+    const int64_t tb = xcd_remap(blockIdx.x, gridDim.x);
+    if (tb >= a.ncell) return;
     const int lane = (int)threadIdx.x;
     const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
     // cells in strips of kBuildStrip x-columns walked along y (a column's
     // cells consecutive), so that cells built close in time share their
-    // neighbour cells in L2
-    const int cz = (int)(t % nz);
-    const int64_t seq = t / nz;
-    const int64_t strip = seq / ((int64_t)kBuildStrip * ny);
-    const int sw = (int)min((int64_t)kBuildStrip, (int64_t)nx - strip * kBuildStrip);
-    const int64_t in = seq - strip * kBuildStrip * ny;
-    const int cy = (int)(in / sw), cx = (int)(strip * kBuildStrip + in % sw);
+    // neighbour cells in L2 (cell ids < 2^31: 32-bit arithmetic, divisions by
+    // the launch's multiply-shift divisors)
+    const uint32_t t = (uint32_t)tb;
+    const uint32_t seq = fdiv(t, a.div_nz);
+    const int cz = (int)(t - seq * (uint32_t)nz);
+    const uint32_t strip = fdiv(seq, a.div_strip);
+    const uint32_t in = seq - strip * (uint32_t)(kBuildStrip * ny);
+    const int sw = min(kBuildStrip, nx - (int)strip * kBuildStrip);
+    uint32_t cyu;
+    if (sw == kBuildStrip) cyu = in / (uint32_t)kBuildStrip;   // a power of two
+    else cyu = in / (uint32_t)sw;                              // the last, narrower strip
+    const int cy = (int)cyu, cx = (int)(strip * kBuildStrip + (in - cyu * (uint32_t)sw));
     const int64_t c = ((int64_t)cx * ny + cy) * nz + cz;
 
     __shared__ int s_nstart[27];
     __shared__ int s_pref[28];
     __shared__ double4 s_key[kMaxOwn];
-    __shared__ __align__(8) uint32_t s_rows[kRowBuf + 2];   // + a spare word for lanes that store nothing
+    // rows of the cell's keys before the block is written (+ a spare word for
+    // lanes that store nothing); before that, the candidate table
+    __shared__ __align__(8) uint32_t s_rows[kRowBuf + 2];
     __shared__ uint32_t s_rowend[kMaxOwn];
     __shared__ int s_lbase[27];
     __shared__ uint32_t s_pad;
@@ -280,14 +453,9 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     // only: the other 13 cells count as empty
     int cnt = 0, st = 0;
     if (lane < 27 && (!HALF || lane >= 13)) {
-        int ax = cx + lane / 9 - 1, ay = cy + (lane / 3) % 3 - 1, az = cz + lane % 3 - 1;
-        ax += ax < 0 ? nx : 0;
-        ax -= ax >= nx ? nx : 0;
-        ay += ay < 0 ? ny : 0;
-        ay -= ay >= ny ? ny : 0;
-        az += az < 0 ? nz : 0;
-        az -= az >= nz ? nz : 0;
-        const int64_t nb = ((int64_t)ax * ny + ay) * nz + az;
+        const int ax = wrap_cell(cx + lane / 9 - 1, nx), ay = wrap_cell(cy + (lane / 3) % 3 - 1, ny);
+        const int az = wrap_cell(cz + lane % 3 - 1, nz);
+        const int nb = (ax * ny + ay) * nz + az;
         st = a.start[nb];
         cnt = a.count[nb];
     }
@@ -302,6 +470,7 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
         s_pref[lane + 1] = incl;
     }
     if (lane == 0) s_pref[0] = 0;
+    int lb = 0;   // tiled: staged index of the first particle of this lane's cell
     if (TILED) {
         // the tile's staged layout: the bases of the 9 column runs (exclusive
         // prefix of the run lengths), then the staged index of
@@ -321,7 +490,8 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
         const int sA = __shfl(run.sA, col, 64), lenA = __shfl(run.lenA, col, 64), sB = __shfl(run.sB, col, 64);
         if (lane < 27) {
             const int j = cz + lane % 3 - 1 - z0 + 1;
-            s_lbase[lane] = cbase + (j < jw ? st - sA : lenA + st - sB);
+            lb = cbase + (j < jw ? st - sA : lenA + st - sB);
+            s_lbase[lane] = lb;
         }
         if (lane == 0) {
             s_pad = (uint32_t)total << 4;   // the stand-in partner of the force pass
@@ -344,8 +514,31 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     // capped so that byte offsets (entries << 2) fit in 32 bits
     const uint32_t stride = (uint32_t)(a.stride < (1 << 29) ? a.stride : (1 << 29));
     uint32_t used = 0;
+    // tiled: the pooled block of the tile (its first cell's block and the
+    // blocks after it) and the tile's count of entries taken
+    uint16_t* tblk = nullptr;
+    uint64_t tcap = 0;
+    int32_t* tused = nullptr;
+    if (TILED) {
+        const int64_t colc = (int64_t)cx * ny + cy;
+        tblk = (uint16_t*)a.nbr + (colc * nz + z0) * a.stride;
+        tcap = (uint64_t)(z1 - z0) * (uint64_t)a.stride;
+        tused = a.tile_used + colc * a.nt + cz / a.tc;
+    }
 
     if (own_cnt > 0 && T <= NCH * 64 && own_cnt <= kMaxOwn) {
+        // candidate table: entry t = (the candidate's position in the cell
+        // order, its list entry bits), written by the lane of its cell; it
+        // lives in the row buffer, which is free until the rows are made
+        static_assert(NCH * 64 * sizeof(uint2) <= sizeof(uint32_t) * (kRowBuf + 2), "table fits the row buffer");
+        uint2* s_tab = reinterpret_cast<uint2*>(s_rows);
+        if (lane < 27) {
+            const int t0 = incl - cnt;
+            const uint32_t mb = TILED ? (uint32_t)lb << 4 : (uint32_t)lane << kCodeShift;
+            for (int i = 0; i < cnt; ++i)
+                s_tab[t0 + i] = make_uint2((uint32_t)(st + i), TILED ? mb + ((uint32_t)i << 4) : mb);
+        }
+        __syncthreads();
         double px[NCH], py[NCH], pz[NCH];
         uint32_t meta[NCH];
         const double qnan = __longlong_as_double(0x7FF8000000000000LL);
@@ -354,44 +547,91 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
             px[ch] = py[ch] = pz[ch] = qnan;
             meta[ch] = 0;
             if (ch * 64 >= T) continue;          // uniform: chunk beyond the neighbourhood
-            const int t = ch * 64 + lane;
-            const int tt = t < T ? t : T - 1;   // in-range index; the result is discarded if t >= T
-            // neighbour cell holding candidate tt: binary search in the prefix
-            int lo = 0, hi = 27;
-#pragma unroll
-            for (int it = 0; it < 5; ++it) {
-                const int mid = (lo + hi) >> 1;
-                const bool le = s_pref[mid] <= tt;
-                lo = le ? mid : lo;
-                hi = le ? hi : mid;
-            }
-            const int idx = s_nstart[lo] + (tt - s_pref[lo]);
-            const int32_t slot = a.order ? a.order[idx] : idx;
+            const int tq = ch * 64 + lane;
+            const bool ok = tq < T;
+            const uint2 e = s_tab[ok ? tq : T - 1];   // in-range entry; discarded if tq >= T
+            const int32_t slot = a.order ? a.order[e.x] : (int32_t)e.x;
             const double4 p = a.pos[slot];
-            const bool ok = t < T;
+            // a NaN x alone fails the distance test in both forms of it
             px[ch] = ok ? p.x : qnan;
-            py[ch] = ok ? p.y : qnan;
-            pz[ch] = ok ? p.z : qnan;
-            meta[ch] = TILED ? (uint32_t)(s_lbase[lo] + (tt - s_pref[lo])) << 4
-                             : (uint32_t)slot | ((uint32_t)lo << kCodeShift);
-            const int k = t - own_pref;
+            py[ch] = p.y;
+            pz[ch] = p.z;
+            meta[ch] = TILED ? e.y : ((uint32_t)slot | e.y);
+            const int k = tq - own_pref;
             if (ok && k >= 0 && k < own_cnt) s_key[k] = make_double4(p.x, p.y, p.z, __longlong_as_double((long long)slot));
         }
         __syncthreads();
-        used = minimg ? rows_from_registers<true, NCH, E, HALF>(a, blk, stride, T, own_pref, own_cnt, s_key, px,
-                                                                py, pz, meta, s_rows, s_rowend, pad)
-                      : rows_from_registers<false, NCH, E, HALF>(a, blk, stride, T, own_pref, own_cnt, s_key, px,
-                                                                 py, pz, meta, s_rows, s_rowend, pad);
+        const int nact = (T + 63) >> 6;
+        if constexpr (TILED) {
+            uint16_t* s_rows16 = reinterpret_cast<uint16_t*>(s_rows);
+            used = minimg ? tiled_rows_for_chunks<true, NCH>(nact, a, tblk, tcap, tused, T, own_pref, own_cnt, s_key,
+                                                             px, py, pz, meta, s_rows16, s_rowend, pad)
+                          : tiled_rows_for_chunks<false, NCH>(nact, a, tblk, tcap, tused, T, own_pref, own_cnt,
+                                                              s_key, px, py, pz, meta, s_rows16, s_rowend, pad);
+        } else {
+            used = minimg ? rows_for_chunks<true, NCH, E, HALF>(nact, a, blk, stride, T, own_pref, own_cnt, s_key,
+                                                                px, py, pz, meta, s_rows, s_rowend, pad)
+                          : rows_for_chunks<false, NCH, E, HALF>(nact, a, blk, stride, T, own_pref, own_cnt, s_key,
+                                                                 px, py, pz, meta, s_rows, s_rowend, pad);
+        }
     } else if (own_cnt > 0) {
-        const int* lb = TILED ? s_lbase : nullptr;
-        used = minimg ? rows_from_memory<true, E, HALF>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart,
-                                                        lb, pad)
-                      : rows_from_memory<false, E, HALF>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart,
-                                                         lb, pad);
+        if constexpr (TILED) {
+            // count the rows, take the cell's slice of the tile's pool, write
+            const uint32_t total =
+                minimg ? rows_from_memory<true, E, false, true>(a, nullptr, 0, T, own_start, own_cnt, s_pref,
+                                                                s_nstart, s_lbase, pad)
+                       : rows_from_memory<false, E, false, true>(a, nullptr, 0, T, own_start, own_cnt, s_pref,
+                                                                 s_nstart, s_lbase, pad);
+            uint32_t base = 0;
+            if (lane == 0) base = (uint32_t)atomicAdd(tused, (int32_t)total);
+            base = __builtin_amdgcn_readfirstlane(base);
+            const bool fits = (uint64_t)base + total <= tcap;
+            if (!fits && lane == 0) atomicOr((unsigned long long*)&a.status[2], 1ull);
+            // an overflowed cell writes empty rows (capacity 0)
+            E* cblk = (E*)(fits ? tblk + base : tblk);
+            const uint32_t cap = fits ? total : 0u;
+            if (minimg)
+                rows_from_memory<true, E, false>(a, cblk, cap, T, own_start, own_cnt, s_pref, s_nstart, s_lbase, pad);
+            else
+                rows_from_memory<false, E, false>(a, cblk, cap, T, own_start, own_cnt, s_pref, s_nstart, s_lbase, pad);
+            used = total;
+        } else {
+            used = minimg ? rows_from_memory<true, E, HALF>(a, blk, stride, T, own_start, own_cnt, s_pref, s_nstart,
+                                                            nullptr, pad)
+                          : rows_from_memory<false, E, HALF>(a, blk, stride, T, own_start, own_cnt, s_pref,
+                                                             s_nstart, nullptr, pad);
+        }
     }
     if (lane == 0) {
         a.cell_rows[c] = used > 0x7FFFFFFFu ? 0x7FFFFFFF : (int32_t)used;
-        if (used > stride) atomicOr((unsigned long long*)&a.status[2], 1ull);
+        if (!TILED && used > stride) atomicOr((unsigned long long*)&a.status[2], 1ull);
+    }
+}
+
+// Stride a tiled list needs: the largest ceil(tile total / cells of the tile)
+// over the tiles, into status[1].
+__global__ __launch_bounds__(1024) void k_tile_need(const int32_t* __restrict__ tile_used, int64_t ntile, int32_t nt,
+                                                    int32_t tc, int32_t nz, int64_t* __restrict__ status)
+{
+    __shared__ long long s_m[16];
+    long long m = 0;
+    for (int64_t t = threadIdx.x; t < ntile; t += 1024) {
+        const int tz = (int)(t % nt);
+        const int cells = min(tc, nz - tz * tc);
+        const long long need = ((long long)tile_used[t] + cells - 1) / cells;
+        m = need > m ? need : m;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long y = __shfl_xor(m, o, 64);
+        m = y > m ? y : m;
+    }
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long r = 0;
+        for (int w = 0; w < 16; ++w) r = s_m[w] > r ? s_m[w] : r;
+        status[1] = r;
     }
 }
 
@@ -399,6 +639,7 @@ hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cel
                         const md_pairlist& list, void* ws, const WsLayout& L, bool tiled, bool half,
                         unsigned long long* tile_max, hipStream_t s)
 {
+    int32_t* tile_used = (int32_t*)((char*)ws + L.tile_used);
     BuildArgs a;
     a.pos = (const double4*)pos;
     a.start = cells.start;
@@ -420,18 +661,26 @@ hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cel
     a.status = list.status;
     a.tc = g.tc;
     a.tile_max = tile_max;
+    a.div_nz = make_fastdiv((uint32_t)g.nc[2]);
+    a.div_strip = make_fastdiv((uint32_t)(kBuildStrip * g.nc[1]));
+    a.nt = g.nt;
+    a.tile_used = tile_used;
     if (tiled && (half || !cells.sorted || g.tc <= 0 || !tile_max)) return hipErrorInvalidValue;
     // status[2] (overflow) is cleared by the statistics kernel of the previous
     // build or by the caller; clear it here on the stream before the build.
     hipError_t e = launch_fill_i32((int32_t*)list.status, 0, 8, s);
     if (e != hipSuccess) return e;
+    if (tiled && (e = launch_fill_i32(tile_used, 0, g.ntile, s)) != hipSuccess) return e;
     const dim3 grid((unsigned)g.ncell);
     if (tiled) hipLaunchKernelGGL((k_build<kBuildChunks, true, false>), grid, dim3(64), 0, s, a);
     else if (half) hipLaunchKernelGGL((k_build<kBuildChunks, false, true>), grid, dim3(64), 0, s, a);
     else hipLaunchKernelGGL((k_build<kBuildChunks, false, false>), grid, dim3(64), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_list_stats(a.cell_rows, g.ncell, list.status, (long long*)((char*)ws + L.red), s);
+    e = launch_list_stats(a.cell_rows, g.ncell, list.status, (long long*)((char*)ws + L.red), s);
+    if (e != hipSuccess || !tiled) return e;
+    hipLaunchKernelGGL(k_tile_need, dim3(1), dim3(1024), 0, s, tile_used, g.ntile, g.nt, g.tc, g.nc[2], list.status);
+    return hipGetLastError();
 }
 
 }  // namespace md

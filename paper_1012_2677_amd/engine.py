@@ -83,14 +83,18 @@ class Grid:
         c.order = self.order.data_ptr()
 
 
-def default_cell_stride(params: A.MdParams, ncell) -> int:
-    """Entries reserved per cell: twice the mean (cell occupancy times the mean
-    number of partners within rs) plus 64, rounded up to 64."""
+def default_cell_stride(params: A.MdParams, ncell, pooled: bool = False) -> int:
+    """Entries reserved per cell: the mean (cell occupancy times the mean
+    number of partners within rs) times a margin, plus 64, rounded up to 64.
+    Cell blocks of their own (slot entries) must hold the fullest cell of a
+    fluctuating fluid: twice the mean.  The tiled layout pools the blocks of a
+    tile's cells, so its stride only has to hold the fullest tile's average:
+    1.35 times the mean.  Either grows on MD_ERR_CAPACITY."""
     vol = params.box[0] * params.box[1] * params.box[2]
     rho = params.n / vol
     per_cell = params.n / float(np.prod(ncell))
     mean = per_cell * rho * (4.0 / 3.0) * math.pi * params.rs ** 3
-    return int(64 * math.ceil((2.0 * mean + 64.0) / 64.0))
+    return int(64 * math.ceil(((1.35 if pooled else 2.0) * mean + 64.0) / 64.0))
 
 
 class PairList:
@@ -107,7 +111,7 @@ class PairList:
         self.counts = torch.empty(n, dtype=torch.int32, device=device)
         self.status = torch.zeros(4, dtype=torch.int64, device=device)
         self.l = A.MdPairlist()
-        self.resize(cell_stride or default_cell_stride(params, ncell))
+        self.resize(cell_stride or default_cell_stride(params, ncell, pooled=self.entry_bits == 16))
 
     def resize(self, cell_stride: int, entry_bits: int | None = None):
         self.cell_stride = int(cell_stride)
