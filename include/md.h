@@ -370,6 +370,22 @@ int md_prepare(const md_params* p, md_state* st, hipStream_t stream);
 int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_every,
             double* energy_log, hipStream_t stream);
 
+/* md_step that also keeps the trajectory, for the checkpointed reverse sweep
+ * of trajectory gradients (which recomputes a segment of steps from its
+ * checkpoint and needs every state of it and the states its pair lists were
+ * built at).  For step k of the call (k = 0 .. nsteps-1):
+ *   traj + 4*n*k: device double[n][4], the positions at which step k
+ *     evaluates its forces (after its drift), in the particles' original
+ *     order (row id holds particle id), as (x, y, z, 0): the layout of pos,
+ *     so a frame can be given to md_bin_cells / md_hvp / md_adjoint_kick as
+ *     it is;
+ *   built[k]: host int32, 1 when step k rebuilt the pair list (at those
+ *     positions), else 0.
+ * Rows k at or past the step where the call stops with an error are not
+ * written.  Otherwise as md_step. */
+int md_step_record(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_every,
+                   double* energy_log, double* traj, int32_t* built, hipStream_t stream);
+
 /* Kinetic, potential, virial and total energy at the current state:
  * out: device double[4] = (KE, PE, W, KE + PE).  Recomputes the forces. */
 int md_energy(const md_params* p, md_state* st, double* out, hipStream_t stream);

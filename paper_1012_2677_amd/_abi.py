@@ -37,7 +37,7 @@ TIMER_NAMES = ["force", "integrate", "bin", "resort", "build", "reduce", "check"
 
 EXPORTED = ["md_cell_dims", "md_workspace_bytes", "md_pack_positions", "md_bin_cells", "md_resort", "md_build_pairlist",
             "md_forces", "md_prepare", "md_step", "md_energy", "md_hvp", "md_adjoint_kick", "md_param_grad",
-            "md_ldc_check", "md_last_error", "md_hbm_probe", "md_forces_noalloc"]
+            "md_ldc_check", "md_last_error", "md_hbm_probe", "md_forces_noalloc", "md_step_record"]
 MD_NOALLOC_MAX_N = 1 << 20
 
 MD_PROBE_READ, MD_PROBE_COPY, MD_PROBE_TRIAD, MD_PROBE_NT = 0, 1, 2, 4
@@ -108,6 +108,7 @@ def lib():
         "md_forces": (C.c_int, [P(MdParams), vp, P(MdCells), P(MdPairlist), vp, vp, vp, C.c_size_t, vp]),
         "md_prepare": (C.c_int, [P(MdParams), P(MdState), vp]),
         "md_step": (C.c_int, [P(MdParams), P(MdState), C.c_int64, C.c_int64, vp, vp]),
+        "md_step_record": (C.c_int, [P(MdParams), P(MdState), C.c_int64, C.c_int64, vp, vp, P(C.c_int32), vp]),
         "md_energy": (C.c_int, [P(MdParams), P(MdState), vp, vp]),
         "md_hvp": (C.c_int, [P(MdParams), vp, P(MdCells), P(MdPairlist), vp, vp, vp, vp, C.c_size_t, vp]),
         "md_adjoint_kick": (C.c_int, [P(MdParams), vp, P(MdCells), P(MdPairlist), vp, vp, vp,
@@ -184,6 +185,12 @@ def md_prepare(params, state, stream):
 def md_step(params, state, nsteps, sample_every, energy_log, stream):
     return _check(lib().md_step(C.byref(params), C.byref(state), nsteps, sample_every, energy_log, stream),
                   "md_step")
+
+
+def md_step_record(params, state, nsteps, sample_every, energy_log, traj, built, stream):
+    """built: a ctypes int32 array of nsteps (host)."""
+    return _check(lib().md_step_record(C.byref(params), C.byref(state), nsteps, sample_every, energy_log, traj,
+                                       built, stream), "md_step_record")
 
 
 def md_energy(params, state, out, stream):

@@ -41,7 +41,8 @@ class Field:
         self.grid = Grid(self.params, self.device)
         self.plist = PairList(self.params, self.grid.ncell, self.device)
         self.ws = Workspace(self.params, self.device)
-        self.pos = torch.empty((self.n, 4), dtype=torch.float64, device=self.device)
+        self._own_pos = torch.empty((self.n, 4), dtype=torch.float64, device=self.device)
+        self.pos = self._own_pos
         self.out2 = torch.empty(2, dtype=torch.float64, device=self.device)
 
     def set_params(self, eps, sigma):
@@ -54,9 +55,22 @@ class Field:
         valid while no particle has moved more than (rs - rc)/2 since)."""
         q = q.detach().to(self.device, torch.float64).contiguous()
         st = stream_handle(self.device)
+        self.pos = self._own_pos
         A.md_pack_positions(self.params, q.data_ptr(), self.pos.data_ptr(), st)
-        if not rebuild:
-            return
+        if rebuild:
+            self._build()
+
+    def use_frame(self, frame: torch.Tensor, rebuild: bool = True):
+        """Take a frame of positions already in the library's layout (N, 4),
+        inside the box (a frame of md_step_record), without a copy; rebuild
+        the pair list there unless rebuild is False."""
+        assert frame.dtype == torch.float64 and frame.is_contiguous() and tuple(frame.shape) == (self.n, 4)
+        self.pos = frame
+        if rebuild:
+            self._build()
+
+    def _build(self):
+        st = stream_handle(self.device)
         A.md_bin_cells(self.params, self.pos.data_ptr(), self.grid.c, self.ws.ptr, self.ws.nbytes, st)
         for _ in range(4):
             A.md_build_pairlist(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, self.ws.ptr,
@@ -144,7 +158,9 @@ class TrajectoryMeanPE(torch.autograd.Function):
         a_q  += -h H(q) a_v           (first kick)
     and the observable adds (1/K) grad U(q') = -(1/K) F(q') to a_q at every
     step; the parameter adjoint gathers h a_v . dF/dtheta at both kicks and
-    (1/K) dU/dtheta at every sampled state.
+    (1/K) dU/dtheta at every sampled state.  The first kick of step k and the
+    second kick of step k - 1 both act at q_k with the same a_v, so every
+    state but q_0 and q_K takes one fused adjoint pass (coefficient 2h).
     """
 
     @staticmethod
@@ -191,44 +207,51 @@ class TrajectoryMeanPE(torch.autograd.Function):
         # every pair within rc up to the next such state; the reverse sweep
         # builds its lists at those states only
         k_end = K
+        # one engine recomputes every segment, reset from each checkpoint
+        eng = Engine(np.zeros((n, 3)), np.zeros((n, 3)), cfg["box"], eps=cfg["eps"], sigma=cfg["sigma"],
+                     rc=cfg["rc"], rs=cfg["rs"], dt=dt, precision="fp64", resort_every=0, device=dev)
         for si in range(len(ctx.ckpts) - 1, -1, -1):
             qc, vc = ctx.ckpts[si]
             k0 = si * cfg["ckpt"]
             m = k_end - k0
             # recompute the segment's states q_k0 .. q_k0+m from its checkpoint
-            eng = Engine(qc.cpu().numpy(), vc.cpu().numpy(), cfg["box"], eps=cfg["eps"], sigma=cfg["sigma"],
-                         rc=cfg["rc"], rs=cfg["rs"], dt=dt, precision="fp64", resort_every=0, device=dev)
+            # in one run that records them (state t >= 1 is frame t - 1)
+            eng.reset(qc, vc)
             eng.prepare()                 # the list of state 0
-            states = [qc]
-            builds = [0]                  # states of the segment its lists were built at
-            for t in range(m):
-                before = eng.rebuilds
-                eng.step(1)
-                if eng.rebuilds > before:
-                    builds.append(t + 1)
-                states.append(eng.pos[:, :3].clone())
-            del eng
-            current = placed = None      # state of the field's list; state of its positions
+            frame0 = eng.pos.clone()      # state 0 in the library's layout (the prepared positions)
+            _, frames, built = eng.step_record(m)
+            builds = [0] + [t + 1 for t in range(m) if built[t]]   # states the segment's lists were built at
+            current = None                # state of the field's list
 
             def place(t):
-                nonlocal current, placed
+                nonlocal current
                 b = max(x for x in builds if x <= t)
+                fb = frame0 if b == 0 else frames[b - 1]
                 if b != current:
-                    f.set_positions(states[b])
-                    current = placed = b
-                if t != placed:
-                    f.set_positions(states[t], rebuild=False)
-                    placed = t
+                    f.use_frame(fb)
+                    current = b
+                f.use_frame(frame0 if t == 0 else frames[t - 1], rebuild=False)
 
-            for j in range(m - 1, -1, -1):
-                # step q_j -> q_{j+1}: observable term and second kick at q_{j+1},
-                # with the drift of the velocity adjoint fused in
-                place(j + 1)
-                f.adjoint_kick(av, aq, av_next, (1.0, -h, -w, h, w), acc)
-                av, av_next = av_next, av
-                # first kick at q_j
-                place(j)
-                f.adjoint_kick(av, aq, None, (1.0, -h, 0.0, h, 0.0), acc)
+            # states k = k0 + t, from the segment's top down to k0 (the top
+            # state k_end was taken by the later segment unless it is q_K)
+            t_top = m if k_end == K else m - 1
+            for t in range(t_top, -1, -1):
+                k = k0 + t
+                place(t)
+                if k == K:
+                    # second kick of the last step and the observable term at q_K,
+                    # with the drift of the velocity adjoint fused in
+                    f.adjoint_kick(av, aq, av_next, (1.0, -h, -w, h, w), acc)
+                    av, av_next = av_next, av
+                elif k > 0:
+                    # the first kick of step k and the second kick of step k - 1
+                    # act at the same q_k with the same velocity adjoint: one
+                    # pass with both (2h), the observable term, and the drift
+                    f.adjoint_kick(av, aq, av_next, (1.0, -2.0 * h, -w, 2.0 * h, w), acc)
+                    av, av_next = av_next, av
+                else:
+                    # first kick of step 0 at q_0
+                    f.adjoint_kick(av, aq, None, (1.0, -h, 0.0, h, 0.0), acc)
             k_end = k0
         ge = acc[0].to(ctx.eps_like) if ctx.eps_like is not None else None
         gs = acc[1].to(ctx.sig_like) if ctx.sig_like is not None else None

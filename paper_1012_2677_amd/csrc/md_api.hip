@@ -830,8 +830,9 @@ int md_energy(const md_params* p, md_state* st, double* out, hipStream_t s)
     return MD_OK;
 }
 
-int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_every, double* energy_log,
-            hipStream_t s)
+// The step loop of md_step and md_step_record (traj / built may be NULL).
+static int step_loop(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_every, double* energy_log,
+                     double* traj, int32_t* built, hipStream_t s)
 {
     Ctx c;
     int rc = setup(p, c);
@@ -896,6 +897,9 @@ int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_eve
             }
             st->list_valid = 1;
         }
+        if (built) built[done] = expired ? 1 : 0;
+        if (traj)
+            MD_HIP(launch_record(c.g, st->pos, st->id, traj + 4 * c.g.n * done, s), "step/record");
         // force pass with the second half kick of this step, fused with the
         // next step's first half kick and drift unless this is the last step
         // of the call (then the force is stored for the next call)
@@ -950,6 +954,19 @@ int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_eve
         }
     }
     return MD_OK;
+}
+
+int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_every, double* energy_log,
+            hipStream_t s)
+{
+    return step_loop(p, st, nsteps, sample_every, energy_log, nullptr, nullptr, s);
+}
+
+int md_step_record(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_every, double* energy_log,
+                   double* traj, int32_t* built, hipStream_t s)
+{
+    if (!traj || !built) return fail(MD_ERR_ARG, "traj or built is NULL");
+    return step_loop(p, st, nsteps, sample_every, energy_log, traj, built, s);
 }
 
 }  // extern "C"

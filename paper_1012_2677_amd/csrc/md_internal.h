@@ -254,6 +254,8 @@ hipError_t launch_resort(const Geo& g, const int32_t* order, const double* pos, 
                          double* pos_ref, float* pos32, int32_t* cell_of, int32_t* cell_xyz,
                          hipStream_t s);
 hipError_t launch_pack(const Geo& g, const double* q, double* pos, hipStream_t s);
+// frame[id[slot]] = pos[slot] (double4, w = 0): positions in the original order
+hipError_t launch_record(const Geo& g, const double* pos, const int32_t* id, double* frame, hipStream_t s);
 hipError_t launch_ref_copy(const Geo& g, const double* pos, const int32_t* cell_xyz, double* pos_ref,
                            float* pos32, hipStream_t s);
 

@@ -220,6 +220,26 @@ class Engine:
         self.state = s
         self.prepared = False
 
+    def reset(self, pos: torch.Tensor, vel: torch.Tensor):
+        """Start again from device positions (N, 3) (or (N, 4)) and velocities
+        (N, 3), in the original particle order, keeping every buffer: the
+        arrays are copied in on the device and the next step prepares the
+        state from scratch."""
+        with torch.no_grad():
+            self.pos[:, :3].copy_(pos[:, :3])
+            self.pos[:, 3].zero_()
+            self.vel.copy_(vel.t())
+            self.id.copy_(torch.arange(self.n, dtype=torch.int32, device=self.device))
+        s = self.state
+        s.step = 0
+        s.rebuilds = 0
+        s.resorts = 0
+        s.phase = 0
+        s.list_valid = 0
+        s.ldc_checks = 0
+        s.ldc_kept = 0
+        self.prepared = False
+
     # -- pointer bookkeeping after the library swapped buffers ------------------
     def _sync_pointers(self):
         s = self.state
@@ -276,6 +296,45 @@ class Engine:
                     self.plist.handle_capacity_error()
                     self.plist.fill(self.state.list)
         return torch.cat(rows).numpy() if rows else np.zeros((0, 4))
+
+    def step_record(self, nsteps: int, sample_every: int = 0):
+        """step() that also keeps the trajectory (md_step_record): returns
+        (energy log, frames, built) with frames a (nsteps, N, 4) float64 device
+        tensor, frame k the positions (x, y, z, 0) at which step k evaluated
+        its forces, rows in the original particle order, and built a numpy
+        bool array, True where step k rebuilt the pair list."""
+        import ctypes
+
+        if not self.prepared:
+            self.prepare()
+        se = int(sample_every)
+        log = torch.zeros((nsteps // se + 2 if se > 0 else 1, 4), dtype=torch.float64, device=self.device)
+        frames = torch.empty((nsteps, self.n, 4), dtype=torch.float64, device=self.device)
+        built = (ctypes.c_int32 * max(nsteps, 1))()
+        rows = []
+        done = 0
+        with torch.cuda.device(self.device):
+            while done < nsteps:
+                before = int(self.state.step)
+                err = None
+                sub = ctypes.cast(ctypes.byref(built, 4 * done), ctypes.POINTER(ctypes.c_int32))
+                try:
+                    A.md_step_record(self.params, self.state, nsteps - done, se, log.data_ptr(),
+                                     frames[done:].data_ptr(), sub, self.stream())
+                except A.MdError as e:
+                    err = e
+                self._sync_pointers()
+                after = int(self.state.step)
+                if se > 0:
+                    rows.append(log[: after // se - before // se].cpu())
+                done += after - before
+                if err is not None:
+                    if err.code != A.MD_ERR_CAPACITY:
+                        raise err
+                    self.plist.handle_capacity_error()
+                    self.plist.fill(self.state.list)
+        elog = torch.cat(rows).numpy() if rows else np.zeros((0, 4))
+        return elog, frames, np.array(built[:nsteps], dtype=bool)
 
     def energies(self):
         """(KE, PE, W, E) at the current state (recomputes forces)."""

@@ -254,3 +254,29 @@ def test_overflow_mid_run_resumes(ref, precision):
     _, _, rlog, _ = ref.run(q, v, L, 60, sample_every=10)
     assert log.shape == rlog.shape
     assert _close_logs(log, rlog, precision, q.shape[0])
+
+
+@pytest.mark.parametrize("precision,resort_every", [("fp64", 0), ("fp64", 1), ("mixed", 1)])
+def test_step_record_matches_single_steps(precision, resort_every):
+    # md_step_record's frame k is the positions at which step k evaluated its
+    # forces, in the original particle order, and built[k] marks the steps
+    # that rebuilt the list; the same run taken one md_step at a time (whose
+    # kicks run in separate passes, so roundings may differ in the last bits)
+    # gives the same positions and the same rebuilds
+    q, L = li.fcc_lattice(10)
+    v = li.maxwell_boltzmann(q.shape[0], T=1.0, seed=14)
+    a = _engine(q, v, L, precision=precision, resort_every=resort_every)
+    b = _engine(q, v, L, precision=precision, resort_every=resort_every)
+    a.prepare()
+    b.prepare()
+    _, frames, built = a.step_record(30)
+    assert frames.shape == (30, q.shape[0], 4)
+    fr = frames.cpu().numpy()
+    assert np.all(fr[:, :, 3] == 0.0)
+    for k in range(30):
+        r0 = b.rebuilds
+        b.step(1)
+        assert built[k] == (b.rebuilds > r0), k
+        d = fr[k, :, :3] - b.positions()
+        assert np.abs(d - L * np.rint(d / L)).max() < 1e-9, k
+    assert built.any() and not built.all()
