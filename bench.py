@@ -113,26 +113,6 @@ def counter_traffic(kernel: str, workload: str):
     return b, path
 
 
-def copy_bandwidth(nbytes: int = 4 << 30, reps: int = 10):
-    """Achievable HBM bandwidth: a plain device-to-device copy of nbytes (reads
-    nbytes, writes nbytes), timed with events on the current stream."""
-    import torch
-
-    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
-    b = torch.empty_like(a)
-    b.copy_(a)
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / reps
-    del a, b
-    torch.cuda.empty_cache()
-    return {"bytes_per_copy": 2 * nbytes, "ms": ms, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
-
-
 def hbm_probe(nbytes: int = 4 << 30, reps: int = 10):
     """Achievable HBM bandwidth from the library's streaming probes (read,
     copy, triad; plain and non-temporal accesses) on arrays of nbytes each,
@@ -468,7 +448,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--modes", default=None, help="comma list of precisions to run (default mixed,fp64)")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain 1 GiB device copy (the reference kernel for HBM counter scaling)")
+                    help="only run the plain 1 GiB copy probe (the reference kernel for HBM counter scaling)")
     ap.add_argument("--protocol-lead", type=int, default=150,
                     help="untimed steps before the protocol leg (the paper's 150)")
     ap.add_argument("--protocol-steps", type=int, default=1000,
@@ -496,7 +476,16 @@ def main():
     import torch
 
     if args.calibrate_copy:
-        print(json.dumps({"calibrate_copy": copy_bandwidth(1 << 30, 3)}), flush=True)
+        # the reference kernel of the HBM counter scaling: the library's plain
+        # copy probe over 1 GiB (reads 1 GiB, writes 1 GiB per launch)
+        from paper_1012_2677_amd import _abi as A
+
+        a = torch.full(((1 << 30) // 8,), 1.0, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        ms = A.md_hbm_probe(A.MD_PROBE_COPY, a.data_ptr(), b.data_ptr(), None, 1 << 30, 3,
+                            torch.cuda.current_stream().cuda_stream)
+        print(json.dumps({"calibrate_copy": {"kernel": "md::k_probe<1, false>", "bytes_read": 1 << 30,
+                                             "bytes_written": 1 << 30, "best_ms": ms}}), flush=True)
         return
     if args.warmup is None:
         args.warmup = cfg.get("warmup", 10)
