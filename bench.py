@@ -153,7 +153,8 @@ def drift_per_1000(steps_axis, e_per_particle):
 
 
 def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, shuffle=False,
-             rebuild_rule="half_skin", ldc_max=8192, list_layout="auto", tile_cells=0, protocol=(150, 1000, 10)):
+             rebuild_rule="half_skin", ldc_max=8192, list_layout="auto", tile_cells=0, protocol=(150, 1000, 10),
+             step_run=0):
     """One precision mode: prepare, warmup, the timed steps, then (protocol =
     (lead, steps, sample_every), lead > 0 or steps > 0) the paper's protocol
     leg on the same state: lead untimed steps, then steps timed ones with the
@@ -173,7 +174,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
     n = q.shape[0]
     e = Engine(q, v, L, rc=cfg["rc"], rs=cfg["rc"] + cfg["skin"], dt=cfg["dt"], precision=precision,
                resort_every=resort_every, rebuild_rule=rebuild_rule, ldc_max=ldc_max, list_layout=list_layout,
-               tile_cells=tile_cells, device="cuda:0", timers=True)
+               tile_cells=tile_cells, step_run=step_run, device="cuda:0", timers=True)
     del q, v
     e.prepare()
     e0 = e.energies()
@@ -214,6 +215,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
         "list_tiled": tiled,
         "list_half": half,
         "tile_cells": int(e.state.tile_cells),
+        "step_run": int(step_run),
         "list_cell_stride": int(e.plist.cell_stride),
         "list_stride_needed": int(e.plist.status[1].item()),
         "timers_ms": {k: [round(m, 3), c] for k, (m, c) in tim.items()},
@@ -441,6 +443,8 @@ def main():
                          "or each pair once with atomic partner forces (half)")
     ap.add_argument("--tile-cells", type=int, default=0, help="tile length along z in cells (0 = automatic)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--step-run", type=int, default=0,
+                    help="steps queued per wait for the device (0 = automatic, 1 = a wait after every step)")
     ap.add_argument("--gradients", action="store_true",
                     help="also time the gradient of the trajectory mean PE (on by default for lj256k)")
     ap.add_argument("--ckpt", type=int, default=20, help="checkpoint interval of the gradient run")
@@ -498,7 +502,7 @@ def main():
     for m in modes:
         results[m] = run_mode(cfg, m, args.steps, args.warmup, sample_every, args.seed,
                               rebuild_rule=args.rebuild_rule, ldc_max=args.ldc_max, list_layout=args.list_layout,
-                              tile_cells=args.tile_cells, protocol=protocol)
+                              tile_cells=args.tile_cells, protocol=protocol, step_run=args.step_run)
     head = results[modes[0]]
     n = head["n"]
     drift = {m: results[m].get("drift_per_1000_steps") for m in modes}

@@ -68,6 +68,8 @@ extern "C" {
 #define MD_REBUILD_HALF_SKIN 0   /* rebuild once some particle moved more than (rs - rc)/2         */
 #define MD_REBUILD_DUTC_LDC  1   /* DUTC, then the large-displacement check (Alg. alg_validity_check) */
 
+#define MD_STEP_RUN_MAX 64       /* most steps md_step queues per host wait (md_params.step_run) */
+
 /* Model and run parameters.
  *   V(r) = 4 eps [ (sigma/r)^12 - (sigma/r)^6 + c2 (r/sigma)^2 + c0 ] for r < rc,
  *   with c2, c0 fixed by V(rc) = V'(rc) = 0 (Sec. 2.1, eq. lj_cutoff); rc and rs
@@ -104,7 +106,12 @@ extern "C" {
  *   rounding of a force sum depends on the order of the atomics; in a
  *   simulation state the integrator then runs as a pass of its own.
  *   tile_cells: cells per tile along z (0 = about 200 keys per tile at the
- *   mean density in MD_MIXED, 135 in MD_FP64); clipped to [1, nz - 2]. */
+ *   mean density in MD_MIXED, 135 in MD_FP64); clipped to [1, nz - 2].
+ *   step_run: with MD_REBUILD_HALF_SKIN and a full list, the steps md_step
+ *   queues before it waits for the device (0 = automatic: the steps the list
+ *   is expected to last, from its age and the growth of the largest
+ *   displacement, plus one, at most MD_STEP_RUN_MAX; 1 = a wait after every
+ *   step).  The results do not depend on it. */
 typedef struct md_params {
     int64_t n;
     double  box[3];
@@ -117,6 +124,7 @@ typedef struct md_params {
     int32_t ldc_max;
     int32_t list_layout;   /* MD_LIST_AUTO, MD_LIST_SLOTS or MD_LIST_HALF */
     int32_t tile_cells;    /* 0 = automatic, else 1 .. 1023 */
+    int32_t step_run;      /* 0 = automatic, else 1 .. MD_STEP_RUN_MAX steps per wait */
 } md_params;
 
 /* Cell grid (Sec. 2.2): GridParticleNumber = count, GridPointer = start,
@@ -363,8 +371,13 @@ int md_prepare(const md_params* p, md_state* st, hipStream_t stream);
  * drift run in the force pass (two separate roundings for the two kicks).
  * Every sample_every steps (counted from st->step) the row
  * energy_log[k][0..3] = (KE, PE, W, KE + PE) is written (device double
- * array; NULL to skip; sample_every <= 0 samples nothing).  Synchronises once
- * per step to read the rebuild flag.  On MD_ERR_CAPACITY the state stops in
+ * array; NULL to skip; sample_every <= 0 samples nothing).
+ * With MD_REBUILD_HALF_SKIN and a full list the rebuild decision is taken on
+ * the device: steps are queued in runs (md_params.step_run), a small pass
+ * after each step sets a device flag once the next step must rebuild, the
+ * passes of the run's later steps then do nothing, and the host waits once
+ * per run and once per rebuild, resuming where the run stopped.  With
+ * MD_REBUILD_DUTC_LDC or a half list it waits once per step.  On MD_ERR_CAPACITY the state stops in
  * phase 1 with st->step steps done; grow the list and call md_step again.
  * MD_ERR_NONFINITE stops after the step that produced a non-finite force. */
 int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_every,

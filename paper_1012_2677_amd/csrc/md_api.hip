@@ -53,6 +53,8 @@ static int check_params(const md_params* p, int32_t nc[3])
     if (p->list_layout != MD_LIST_AUTO && p->list_layout != MD_LIST_SLOTS && p->list_layout != MD_LIST_HALF)
         return fail(MD_ERR_ARG, "list_layout must be 0, 1 or 2");
     if (p->tile_cells < 0 || p->tile_cells > 1023) return fail(MD_ERR_ARG, "tile_cells must be in [0, 1023]");
+    if (p->step_run < 0 || p->step_run > MD_STEP_RUN_MAX)
+        return fail(MD_ERR_ARG, "step_run must be in [0, %d]", MD_STEP_RUN_MAX);
     for (int k = 0; k < 3; ++k) {
         const double m = std::floor(p->box[k] / p->rs);
         if (m < 3.0) return fail(MD_ERR_BOX, "axis %d has %.0f cells (< 3): box too small for rs", k, m);
@@ -130,6 +132,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 //   [0], [1]  cell-grid error flags         [2]  md_forces non-finite flag
 //   [4]       large-displacement members    [5]  large-displacement violation
 //   [6]       largest squared displacement (md_ldc_check)
+//   [8]       gate of a run of queued steps (int32; md_step)
 //   [16..31]  flags gathered for one read-back (layout in k_gather_flags)
 constexpr int kScalOut = 16;
 
@@ -235,15 +238,18 @@ static int check_slot_list(const Ctx& c, const md_pairlist* list, bool allow_hal
 // ---------------------------------------------------------------------------
 // timers
 // ---------------------------------------------------------------------------
-// Up to two launches of each kernel class are timed between two host waits
-// (md_step waits once or twice per step, so every launch is covered).
+// Up to kTimerSlots launches of each kernel class are timed between two host
+// waits (md_step waits at least once per run of steps, and a run is at most
+// kTimerSlots steps long, so every launch is covered).
+constexpr int kTimerSlots = 64;
+
 struct Timer {
     md_timers* t;
     bool ok;
     int n[MD_T_COUNT];
 };
 
-static hipEvent_t g_ev[MD_T_COUNT][2][2];
+static hipEvent_t g_ev[MD_T_COUNT][kTimerSlots][2];
 static bool g_ev_made = false;
 
 static void timer_begin(Timer& T, md_timers* t)
@@ -253,7 +259,7 @@ static void timer_begin(Timer& T, md_timers* t)
     for (int k = 0; k < MD_T_COUNT; ++k) T.n[k] = 0;
     if (!T.ok || g_ev_made) return;
     for (int a = 0; a < MD_T_COUNT; ++a)
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < kTimerSlots; ++b)
             for (int e = 0; e < 2; ++e)
                 if (hipEventCreate(&g_ev[a][b][e]) != hipSuccess) {
                     T.ok = false;
@@ -266,9 +272,16 @@ static void tick(Timer& T, int cls, int which, hipStream_t s)
 {
     if (!T.ok) return;
     const int k = T.n[cls];
-    if (k >= 2) return;
+    if (k >= kTimerSlots) return;
     (void)hipEventRecord(g_ev[cls][k][which], s);
     if (which == 1) T.n[cls] = k + 1;
+}
+
+// drop all but the first keep timed launches of a class (launches that a
+// gate turned into no-ops)
+static void timer_keep(Timer& T, int cls, int64_t keep)
+{
+    if (T.ok && keep < T.n[cls]) T.n[cls] = (int)keep;
 }
 
 // call after the stream has been synchronised
@@ -830,6 +843,171 @@ int md_energy(const md_params* p, md_state* st, double* out, hipStream_t s)
     return MD_OK;
 }
 
+// Steps of the half-skin rule with a full list, queued in runs without a host
+// wait per step.  The gather after each step decides on the device whether
+// the next one must rebuild first (Sec. 2.3: largest displacement since the
+// build beyond half the skin); once one must, it sets the gate and the passes
+// of the rest of the run do nothing.  The host waits once per run, learns how
+// many steps ran, rebuilds when the run stopped for it, and resumes there: the
+// steps taken, the lists and the results are those of one wait per step.
+static_assert(MD_STEP_RUN_MAX <= kTimerSlots, "a run's launches must fit the timer slots");
+constexpr int64_t kRunFirst = 4;   // run length while the list's age is unknown
+
+static int step_runs(const Ctx& c, const md_params* p, md_state* st, int64_t nsteps, int64_t sample_every,
+                     double* energy_log, double* traj, int32_t* built, Timer& T, hipStream_t s)
+{
+    const double half_skin = 0.5 * (p->rs - p->rc);
+    const double thr2 = half_skin * half_skin;
+    const bool mixed = p->precision == MD_MIXED;
+    int64_t* scal = (int64_t*)((char*)st->ws + c.W.scal);
+    int32_t* gate = (int32_t*)(scal + 8);
+    double* part_pw = (double*)((char*)st->ws + c.W.part_a);
+    double* part_ke = (double*)((char*)st->ws + c.W.part_b);
+    int rc;
+    int64_t f[16];
+    if (st->phase == 0) {
+        // first half kick and drift of the first step
+        MD_HIP(clear_maxima(c, st, s), "step/maxd2");
+        tick(T, MD_T_INTEGRATE, 0, s);
+        MD_HIP(launch_integrate(c.g, INT_KD, int_args(c, p, st, false), s), "step/kd");
+        tick(T, MD_T_INTEGRATE, 1, s);
+        st->phase = 1;
+    }
+    if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
+    timer_collect(T);
+    double maxd2;
+    std::memcpy(&maxd2, &f[7], sizeof(double));
+    bool expired = !st->list_valid || maxd2 > thr2;
+    bool dirty = true;        // slots may hold maxima no gather of a run cleared
+    int64_t age = -1;         // steps since the last build (-1: built before this call)
+    int64_t cycle = 0;        // steps between the last two builds of this call
+    double rate = 0.0;        // growth of the largest displacement per step (age unknown)
+    int64_t done = 0, k_log = 0;
+    while (done < nsteps) {
+        const bool rebuilt = expired;
+        if (expired) {
+            if ((rc = rebuild(c, p, st, true, T, s, f)) != MD_OK) return rc;
+            st->rebuilds += 1;
+            st->dutc_buffer = p->rs - p->rc;
+            timer_collect(T);
+            if (f[2] != 0) {
+                st->list_valid = 0;
+                return check_status(f, st);
+            }
+            st->list_valid = 1;
+            if (age > 0) cycle = age;
+            age = 0;
+        }
+        if (dirty) {
+            MD_HIP(clear_maxima(c, st, s), "step/maxd2");
+            dirty = false;
+        }
+        // run length: the steps left until the largest displacement, growing
+        // in proportion to the list's age (or as it did over the last run),
+        // passes half the skin, and one more
+        const double d0 = rebuilt ? 0.0 : std::sqrt(maxd2);
+        double left = (double)kRunFirst;
+        if (age > 0 && d0 > 0.0) left = (double)age * (half_skin / d0 - 1.0);
+        else if (age == 0 && cycle > 0) left = (double)cycle;
+        else if (age < 0 && rate > 0.0) left = (half_skin - d0) / rate;
+        int64_t run = p->step_run;
+        if (run == 0) run = (int64_t)std::ceil(std::min(std::max(left, 0.0), (double)MD_STEP_RUN_MAX)) + 1;
+        run = std::min(std::min(run, (int64_t)MD_STEP_RUN_MAX), nsteps - done);
+        // queue the run; the first step needs no gate
+        double* P = st->pos;
+        double* Palt = st->pos_alt;
+        float* P32 = st->pos32;
+        float* P32alt = st->pos32_alt;
+        const int64_t nfb = force_blocks(c.g, st->list_tiled);
+        int64_t k_run = k_log;
+        for (int64_t b = 0; b < run; ++b) {
+            const int64_t step_no = st->step + 1 + b;
+            const bool sample = sample_every > 0 && (step_no % sample_every) == 0;
+            const bool last = done + b + 1 == nsteps;
+            const int32_t* g = b > 0 ? gate : nullptr;
+            if (traj)
+                MD_HIP(launch_record(c.g, P, st->id, traj + 4 * c.g.n * (done + b), s, g), "step/record");
+            StepIo io;
+            io.pos = P;
+            io.pos32 = mixed ? P32 : nullptr;
+            io.cell_xyz = st->cells.cell_xyz;
+            io.list = st->list;
+            io.force = st->force;
+            io.part_pw = sample ? part_pw : nullptr;
+            io.part_ke = sample ? part_ke : nullptr;
+            io.flags = st->flags;
+            io.vel = st->vel;
+            io.pos_ref = st->pos_ref;
+            io.pos_out = mixed ? P : Palt;
+            io.pos32_out = mixed ? P32alt : nullptr;
+            io.max_d2 = mx_slots(c, st, 0);
+            io.max_v2 = mx_slots(c, st, 1);
+            io.dt = p->dt;
+            io.drift = !last;
+            io.track_speed = false;
+            io.tile = tile_io(st);
+            io.gate = g;
+            tick(T, MD_T_FORCE, 0, s);
+            MD_HIP(launch_force_step(c.g, c.lj, p->precision, io, s), "step/force");
+            tick(T, MD_T_FORCE, 1, s);
+            if (!last) {
+                if (mixed) std::swap(P32, P32alt);
+                else std::swap(P, Palt);
+            }
+            if (sample) {
+                tick(T, MD_T_REDUCE, 0, s);
+                MD_HIP(launch_reduce_energy(part_pw, nfb, part_ke, nfb, st->energy,
+                                            energy_log ? energy_log + 4 * k_run : nullptr, s, g),
+                       "step/reduce");
+                tick(T, MD_T_REDUCE, 1, s);
+                ++k_run;
+            }
+            FlagGate fg;
+            fg.gate = gate;
+            fg.thr2 = thr2;
+            fg.idx = (int32_t)(b + 1);
+            fg.fold = !last;     // the last step of a call has no drift
+            fg.clear = !last;
+            MD_HIP(launch_gather_flags(st->list.status, scal, st->flags, st->energy,
+                                       (const int64_t*)((char*)st->ws + c.W.tmax), mx_slots(c, st, 0),
+                                       scal + kScalOut, s, fg),
+                   "step/gather");
+        }
+        int64_t* dst = st->host_scratch ? st->host_scratch : f;
+        MD_HIP(hipMemcpyAsync(dst, scal + kScalOut, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, s), "step/copy");
+        MD_HIP(hipStreamSynchronize(s), "step/sync");
+        if (dst != f)
+            for (int k = 0; k < 16; ++k) f[k] = dst[k];
+        const int64_t ran = f[12];
+        if (ran < 1 || ran > run) return fail(MD_ERR_HIP, "step run: gather reported %lld of %lld steps",
+                                              (long long)ran, (long long)run);
+        // the state after the steps that ran
+        int64_t samples = 0;
+        for (int64_t b = 0; b < ran; ++b) {
+            const int64_t step_no = st->step + 1 + b;
+            if (sample_every > 0 && (step_no % sample_every) == 0) ++samples;
+            if (built) built[done + b] = (b == 0 && expired) ? 1 : 0;
+            if (done + b + 1 != nsteps) {
+                if (mixed) std::swap(st->pos32, st->pos32_alt);
+                else std::swap(st->pos, st->pos_alt);
+            }
+        }
+        timer_keep(T, MD_T_FORCE, ran);
+        timer_keep(T, MD_T_REDUCE, samples);
+        timer_collect(T);
+        k_log += samples;
+        st->step += ran;
+        done += ran;
+        if (age >= 0) age += ran;
+        st->phase = done == nsteps ? 0 : 1;
+        std::memcpy(&maxd2, &f[7], sizeof(double));
+        if (age < 0 && std::sqrt(maxd2) > d0) rate = (std::sqrt(maxd2) - d0) / (double)ran;
+        if (f[6] & 1) return check_status(f, st);
+        expired = f[13] != 0;
+    }
+    return check_status(f, st);
+}
+
 // The step loop of md_step and md_step_record (traj / built may be NULL).
 static int step_loop(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_every, double* energy_log,
                      double* traj, int32_t* built, hipStream_t s)
@@ -849,6 +1027,8 @@ static int step_loop(const md_params* p, md_state* st, int64_t nsteps, int64_t s
     const double thr2 = half_skin * half_skin;
     Timer T;
     timer_begin(T, st->timers);
+    if (p->rebuild_rule == MD_REBUILD_HALF_SKIN && p->list_layout != MD_LIST_HALF)
+        return step_runs(c, p, st, nsteps, sample_every, energy_log, traj, built, T, s);
     double* part_pw = (double*)((char*)st->ws + c.W.part_a);
     double* part_ke = (double*)((char*)st->ws + c.W.part_b);
     int64_t k_log = 0;

@@ -337,18 +337,20 @@ __global__ __launch_bounds__(kStreamBlock) void k_ref_copy(Geo g, const double4*
 // Positions of the current slots into a trajectory frame in the particles'
 // original order: frame[id[s]] = pos[s] (x, y, z, 0).
 __global__ __launch_bounds__(kStreamBlock) void k_record(int64_t n, const double4* __restrict__ pos,
-                                                         const int32_t* __restrict__ id, double4* __restrict__ frame)
+                                                         const int32_t* __restrict__ id, double4* __restrict__ frame,
+                                                         const int32_t* __restrict__ gate)
 {
     const int64_t s = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x;
-    if (s >= n) return;
+    if (s >= n || (gate && gate[0])) return;
     const double4 p = pos[s];
     frame[id[s]] = make_double4(p.x, p.y, p.z, 0.0);
 }
 
-hipError_t launch_record(const Geo& g, const double* pos, const int32_t* id, double* frame, hipStream_t s)
+hipError_t launch_record(const Geo& g, const double* pos, const int32_t* id, double* frame, hipStream_t s,
+                         const int32_t* gate)
 {
     hipLaunchKernelGGL(k_record, dim3((unsigned)ceil_div(g.n, kStreamBlock)), dim3(kStreamBlock), 0, s, g.n,
-                       (const double4*)pos, id, (double4*)frame);
+                       (const double4*)pos, id, (double4*)frame, gate);
     return hipGetLastError();
 }
 

@@ -68,6 +68,7 @@ struct PairArgs {
     const int32_t* start;      // tiled: cell starts and counts (slots in cell order)
     const int32_t* count;
     int32_t tc, nt;            // tiled: cells per tile along z, tiles per column
+    const int32_t* gate;       // step passes: nothing to do when *gate != 0
 };
 
 // Keys [kb, ke) of logical block b: a chunk of kForceBlock consecutive slots.
@@ -281,6 +282,7 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_fp64(
     __shared__ double4 s_p[NW][64];     // own position, .w = 1 if the key needs minimum images
     __shared__ int64_t s_off[NW][64];
     __shared__ int32_t s_cnt[NW][64];
+    if (a.gate && a.gate[0]) return;
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, sub = lane & 7, grp = lane >> 3;
     int64_t kb, kend;
@@ -395,6 +397,7 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_mixed
     __shared__ float4 s_l[NW][64];
     __shared__ int64_t s_off[NW][64];
     __shared__ int32_t s_cnt[NW][64];
+    if (a.gate && a.gate[0]) return;
     if (threadIdx.x < 32) {
         // code 27 never occurs in an entry: it is the stand-in used for
         // masked slots, displaced far beyond the cutoff
@@ -770,6 +773,7 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     __shared__ uint8_t s_perm[NW][64];
     __shared__ int32_t s_run[9][4];
     __shared__ int32_t s_base[10];
+    if (a.gate && a.gate[0]) return;
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
     const int tz = (int)(blk % a.nt);
@@ -1165,6 +1169,7 @@ hipError_t launch_force_step(const Geo& g, const LJ& lj, int precision, const St
     a.dt = io.dt;
     const bool energy = io.part_pw != nullptr;
     if (io.list.half) {
+        if (io.gate) return hipErrorInvalidValue;   // the half-list passes take no gate
         // pair pass into the cleared force array, then the integrator
         if (io.tile.stage > 0 || !io.force) return hipErrorInvalidValue;
         hipError_t e = energy ? launch_pairs_half<true>(g, precision, a, s)
@@ -1182,6 +1187,7 @@ hipError_t launch_force_step(const Geo& g, const LJ& lj, int precision, const St
         }
         return hipGetLastError();
     }
+    a.gate = io.gate;
     if (io.drift && io.track_speed) {
         // the largest drift speed is needed by the DUTC rule only
         if (energy) launch_pairs_mode<true, MODE_KKD, true>(g, precision, a, s, io.tile.stage);

@@ -171,8 +171,10 @@ __device__ __forceinline__ double block_sum_1024(double v)
 __global__ __launch_bounds__(kReduceBlock) void k_reduce_energy(const double* __restrict__ part_pw, int64_t nbf,
                                                                 const double* __restrict__ part_ke, int64_t nbi,
                                                                 double* __restrict__ energy,
-                                                                double* __restrict__ log_row)
+                                                                double* __restrict__ log_row,
+                                                                const int32_t* __restrict__ gate)
 {
+    if (gate && gate[0]) return;
     double pe = 0.0, w = 0.0, ke = 0.0;
     for (int64_t b = threadIdx.x; b < nbf; b += kReduceBlock) {
         pe += part_pw[2 * b];
@@ -197,10 +199,10 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce_energy(const double* __
 }
 
 hipError_t launch_reduce_energy(const double* part_pw, int64_t nbf, const double* part_ke, int64_t nbi,
-                                double* energy, double* log_row, hipStream_t s)
+                                double* energy, double* log_row, hipStream_t s, const int32_t* gate)
 {
     hipLaunchKernelGGL(k_reduce_energy, dim3(1), dim3(kReduceBlock), 0, s, part_pw, nbf, part_ke, nbi,
-                       energy, log_row);
+                       energy, log_row, gate);
     return hipGetLastError();
 }
 
@@ -310,18 +312,26 @@ hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t* s
 
 __global__ void k_gather_flags(const int64_t* __restrict__ status, const int64_t* __restrict__ err,
                                const int64_t* __restrict__ flags, double* __restrict__ energy,
-                               const int64_t* __restrict__ tmax, const unsigned long long* __restrict__ mx,
-                               int64_t* __restrict__ out)
+                               const int64_t* __restrict__ tmax, unsigned long long* __restrict__ mx,
+                               int64_t* __restrict__ out, FlagGate g)
 {
+    // a run already stopped: leave out (and the slots) as the stopping gather left them
+    if (g.gate && g.gate[0] && g.idx > 1) return;
     // wave-wide maxima over the slots: largest staged tile neighbourhood,
     // largest squared displacement and drift speed (bit patterns of
     // non-negative doubles order like the values)
     int64_t m = 0;
     unsigned long long md = 0, mv = 0;
     for (int k = threadIdx.x; k < kTileMaxSlots; k += 64) m = max(m, tmax[k]);
-    for (int k = threadIdx.x; k < kMaxSlots; k += 64) {
-        md = max(md, mx[k * kMaxSlotStride]);
-        mv = max(mv, mx[(kMaxSlots + k) * kMaxSlotStride]);
+    if (g.fold) {
+        for (int k = threadIdx.x; k < kMaxSlots; k += 64) {
+            md = max(md, mx[k * kMaxSlotStride]);
+            mv = max(mv, mx[(kMaxSlots + k) * kMaxSlotStride]);
+            if (g.clear) {
+                mx[k * kMaxSlotStride] = 0;
+                mx[(kMaxSlots + k) * kMaxSlotStride] = 0;
+            }
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -330,8 +340,10 @@ __global__ void k_gather_flags(const int64_t* __restrict__ status, const int64_t
         mv = max(mv, (unsigned long long)__shfl_xor((long long)mv, o, 64));
     }
     if (threadIdx.x != 0) return;
-    energy[4] = __longlong_as_double((long long)md);
-    energy[5] = __longlong_as_double((long long)mv);
+    if (g.fold) {
+        energy[4] = __longlong_as_double((long long)md);
+        energy[5] = __longlong_as_double((long long)mv);
+    }
     out[0] = status[0];
     out[1] = status[1];
     out[2] = status[2];
@@ -344,12 +356,20 @@ __global__ void k_gather_flags(const int64_t* __restrict__ status, const int64_t
     out[9] = err[4];    // large-displacement check: member count
     out[10] = err[5];   // large-displacement check: violation flag
     out[11] = m;        // tiled list: largest staged neighbourhood of a tile
+    int32_t stop = 0;
+    if (g.gate) {
+        stop = ((flags[0] & 1) != 0 || (g.fold && energy[4] > g.thr2)) ? 1 : 0;
+        g.gate[0] = stop;
+    }
+    out[12] = g.idx;
+    out[13] = stop;
 }
 
 hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags, double* energy,
-                               const int64_t* tmax, const unsigned long long* mx, int64_t* out, hipStream_t s)
+                               const int64_t* tmax, unsigned long long* mx, int64_t* out, hipStream_t s,
+                               const FlagGate& gate)
 {
-    hipLaunchKernelGGL(k_gather_flags, dim3(1), dim3(64), 0, s, status, err, flags, energy, tmax, mx, out);
+    hipLaunchKernelGGL(k_gather_flags, dim3(1), dim3(64), 0, s, status, err, flags, energy, tmax, mx, out, gate);
     return hipGetLastError();
 }
 

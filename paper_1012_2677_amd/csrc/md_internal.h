@@ -255,7 +255,9 @@ hipError_t launch_resort(const Geo& g, const int32_t* order, const double* pos, 
                          hipStream_t s);
 hipError_t launch_pack(const Geo& g, const double* q, double* pos, hipStream_t s);
 // frame[id[slot]] = pos[slot] (double4, w = 0): positions in the original order
-hipError_t launch_record(const Geo& g, const double* pos, const int32_t* id, double* frame, hipStream_t s);
+// (nothing when gate is given and *gate != 0)
+hipError_t launch_record(const Geo& g, const double* pos, const int32_t* id, double* frame, hipStream_t s,
+                         const int32_t* gate = nullptr);
 hipError_t launch_ref_copy(const Geo& g, const double* pos, const int32_t* cell_xyz, double* pos_ref,
                            float* pos32, hipStream_t s);
 
@@ -307,6 +309,7 @@ struct StepIo {
     bool drift;
     bool track_speed;             // also record the largest squared drift speed
     TileIo tile;                  // tiled list (tile.stage > 0)
+    const int32_t* gate = nullptr;  // full list: the pass does nothing when *gate != 0
 };
 hipError_t launch_force_step(const Geo& g, const LJ& lj, int precision, const StepIo& io, hipStream_t s);
 int64_t pair_blocks(const Geo& g);   // blocks (and energy partials) of one pair-kernel launch
@@ -335,12 +338,27 @@ __device__ __forceinline__ double pinned_len2(double x, double y, double z)
 }
 hipError_t launch_integrate(const Geo& g, IntMode mode, const IntArgs& a, hipStream_t s);
 hipError_t launch_reduce_energy(const double* part_pw, int64_t nbf, const double* part_ke,
-                                int64_t nbi, double* energy, double* log_row, hipStream_t s);
+                                int64_t nbi, double* energy, double* log_row, hipStream_t s,
+                                const int32_t* gate = nullptr);
 hipError_t launch_reduce_pair(const double* part, int64_t nb, double scale0, double scale1,
                               double* out2, hipStream_t s, bool accumulate = false);
+// The step decision of a run of steps queued without reading flags back
+// (half-skin rule): the gather that follows step idx - 1 of the run sets *gate
+// when step idx must rebuild first (largest squared displacement > thr2) or a
+// non-finite force was seen; the passes of later steps, given the gate, then
+// do nothing, and the gathers after it keep out as the stopping one wrote it.
+// out[12] = idx and out[13] = 1 when it stopped the run.
+struct FlagGate {
+    int32_t* gate = nullptr;      // nullptr: a plain gather
+    double thr2 = 0.0;
+    int32_t idx = 0;
+    bool fold = true;             // fold the slot maxima into energy[4], energy[5]
+    bool clear = false;           // and clear the slots after reading them
+};
 // Also folds the slot maxima of d2 and v2 (mx) into energy[4] and energy[5].
 hipError_t launch_gather_flags(const int64_t* status, const int64_t* err, const int64_t* flags, double* energy,
-                               const int64_t* tmax, const unsigned long long* mx, int64_t* out, hipStream_t s);
+                               const int64_t* tmax, unsigned long long* mx, int64_t* out, hipStream_t s,
+                               const FlagGate& gate = FlagGate());
 hipError_t launch_list_stats(const int32_t* cell_rows, int64_t ncell, int64_t* status, long long* part,
                              hipStream_t s);
 

@@ -27,7 +27,7 @@ LIST_LAYOUTS = {"auto": A.MD_LIST_AUTO, "slots": A.MD_LIST_SLOTS, "half": A.MD_L
 
 def make_params(n, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precision="fp64",
                 resort_every=1, rebuild_rule="half_skin", ldc_max=8192, list_layout="auto",
-                tile_cells=0) -> A.MdParams:
+                tile_cells=0, step_run=0) -> A.MdParams:
     p = A.MdParams()
     p.n = int(n)
     b = np.broadcast_to(np.asarray(box, dtype=np.float64), (3,))
@@ -40,6 +40,7 @@ def make_params(n, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precisi
     p.ldc_max = int(ldc_max)
     p.list_layout = LIST_LAYOUTS[list_layout] if isinstance(list_layout, str) else int(list_layout)
     p.tile_cells = int(tile_cells)
+    p.step_run = int(step_run)
     return p
 
 
@@ -161,12 +162,13 @@ class Engine:
     slots are in cell order), "slots", or "half" (each pair once, Sec. 2.4:
     the partner's force added by device atomics, the integrator in a pass of
     its own; much slower on this GPU, kept for comparison); tile_cells: tile
-    length along z in cells (0 = automatic).
+    length along z in cells (0 = automatic); step_run: steps queued per wait
+    for the device (0 = automatic, 1 = a wait after every step).
     """
 
     def __init__(self, pos, vel, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precision="fp64",
                  resort_every=1, rebuild_rule="half_skin", ldc_max=8192, list_layout="auto", tile_cells=0,
-                 device="cuda", cell_stride=None, timers=False):
+                 step_run=0, device="cuda", cell_stride=None, timers=False):
         pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64))
         vel = np.ascontiguousarray(np.asarray(vel, dtype=np.float64))
         n = pos.shape[0]
@@ -175,7 +177,7 @@ class Engine:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.params = make_params(n, box, eps=eps, sigma=sigma, rc=rc, rs=rs, dt=dt, precision=precision,
                                   resort_every=resort_every, rebuild_rule=rebuild_rule, ldc_max=ldc_max,
-                                  list_layout=list_layout, tile_cells=tile_cells)
+                                  list_layout=list_layout, tile_cells=tile_cells, step_run=step_run)
         self.n = n
         self.mixed = self.params.precision == A.MD_MIXED
         dev = self.device

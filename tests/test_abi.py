@@ -33,6 +33,21 @@ def declared_functions():
     return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(md_\w+)\s*\(", text, re.M)))
 
 
+def test_constants_match_headers(A):
+    # every integer #define of the headers that the binding mirrors has the
+    # header's value
+    text = "".join(open(h).read() for h in HEADERS)
+    seen = 0
+    for name, expr in re.findall(r"^#define\s+(MD_\w+)\s+(\S[^/\n]*?)\s*(?:/\*.*)?$", text, re.M):
+        expr = re.sub(r"\((?:u?int\d+_t|size_t)\)", "", expr)
+        if not re.fullmatch(r"[-()\d\s<]+", expr):
+            continue
+        if hasattr(A, name):
+            assert getattr(A, name) == eval(expr), name
+            seen += 1
+    assert seen >= 15
+
+
 def test_exports_every_declared_symbol(A):
     names = declared_functions()
     assert len(names) >= 12
@@ -59,7 +74,7 @@ int main() {
   OFF(md_state, cells); OFF(md_state, list); OFF(md_state, energy); OFF(md_state, ws_bytes);
   OFF(md_state, timers); OFF(md_state, step); OFF(md_state, phase); OFF(md_state, list_valid);
   OFF(md_params, list_layout); OFF(md_params, tile_cells); OFF(md_state, list_tiled); OFF(md_state, tile_stage);
-  OFF(md_state, tile_cells);
+  OFF(md_state, tile_cells); OFF(md_params, step_run);
   return 0;
 }
 """
@@ -106,12 +121,13 @@ def test_cell_dims_and_workspace(A):
     (dict(n=0), -1), (dict(n=1 << 27), -1), (dict(L=8.0), -2), (dict(L=3000.0), -2),
     (dict(rc=3.0, rs=2.8), -1), (dict(eps=-1.0), -1), (dict(precision=7), -1),
     (dict(list_layout=3), -1), (dict(tile_cells=-1), -1), (dict(tile_cells=1024), -1),
+    (dict(step_run=-1), -1), (dict(step_run=65), -1),
 ])
 def test_validation_codes(A, kw, code):
-    p = _params(A, **{k: v for k, v in kw.items() if k not in ("precision", "list_layout", "tile_cells")})
+    p = _params(A, **{k: v for k, v in kw.items() if k not in ("precision", "list_layout", "tile_cells", "step_run")})
     if kw.get("precision") == 7:
         p.precision = 7
-    for f in ("list_layout", "tile_cells"):
+    for f in ("list_layout", "tile_cells", "step_run"):
         if f in kw:
             setattr(p, f, kw[f])
     with pytest.raises(A.MdError) as e:

@@ -13,7 +13,9 @@
   * runs are bitwise deterministic;
   * the re-sort is an exact permutation;
   * error paths: non-finite force, positions outside the box, list overflow
-    with resumption.
+    with resumption;
+  * steps queued in runs with the rebuild decision on the device give bitwise
+    the run of one wait per step, and a non-finite force stops a run.
 """
 
 import numpy as np
@@ -280,3 +282,55 @@ def test_step_record_matches_single_steps(precision, resort_every):
         d = fr[k, :, :3] - b.positions()
         assert np.abs(d - L * np.rint(d / L)).max() < 1e-9, k
     assert built.any() and not built.all()
+
+
+@pytest.mark.parametrize("precision,layout,resort_every", [("fp64", "auto", 1), ("mixed", "auto", 1),
+                                                           ("fp64", "slots", 0), ("mixed", "slots", 1)])
+def test_queued_runs_equal_a_wait_per_step(precision, layout, resort_every):
+    # md_step queues the steps in runs and takes the rebuild decision on the
+    # device; runs of one step (a wait after each), of 16 steps (the passes
+    # after each stop run gated), and of the automatic length give bitwise the
+    # same run: energy log, positions, velocities, forces and rebuild count,
+    # and every force pass that ran is timed once
+    q, L = li.fcc_lattice(10)
+    v = li.maxwell_boltzmann(q.shape[0], T=1.0, seed=21)
+    out = {}
+    for run in (1, 16, 0):
+        e = _engine(q, v, L, precision=precision, list_layout=layout, resort_every=resort_every, step_run=run,
+                    timers=True)
+        log = e.step(120, sample_every=3)
+        e.step(7, sample_every=1)     # a second call resumes the first's state
+        out[run] = (log, e.positions(), e.velocities(), e.forces(), e.rebuilds, e.timer_dict())
+    ref = out[1]
+    assert ref[4] > 10
+    for run in (16, 0):
+        got = out[run]
+        assert np.array_equal(got[0], ref[0]), run
+        for k in (1, 2, 3):
+            assert np.array_equal(got[k], ref[k]), (run, k)
+        assert got[4] == ref[4], run
+        for name in ("force", "reduce", "build"):
+            assert got[5][name][1] == ref[5][name][1], (run, name)
+    assert ref[5]["force"][1] == 127          # one per step (md_prepare is not timed)
+
+
+def test_queued_runs_stop_on_a_nonfinite_force():
+    # a particle placed on top of another, with the same velocity and force,
+    # from the host: the next step rebuilds (the move is beyond half the skin), its
+    # force is not finite, the run of 16 stops there and its later passes do
+    # nothing; the step count says which step it was
+    from paper_1012_2677_amd import MdError, _abi as A
+
+    q, L = li.fcc_lattice(8)
+    v = li.maxwell_boltzmann(q.shape[0], seed=3)
+    e = _engine(q, v, L, step_run=16)
+    e.step(5)
+    r0 = e.rebuilds
+    e.pos[1, :3] = e.pos[0, :3]
+    e.vel[:, 1] = e.vel[:, 0]
+    e.force[:, 1] = e.force[:, 0]     # so that the first half kick and drift keep them together
+    with pytest.raises(MdError) as err:
+        e.step(20)
+    assert err.value.code == A.MD_ERR_NONFINITE
+    assert e.step_count == 6
+    assert e.rebuilds == r0 + 1
