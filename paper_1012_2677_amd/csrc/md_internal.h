@@ -33,7 +33,11 @@ constexpr int kLanesPerKey = MD_LANES_PER_KEY;   // lanes cooperating on one key
 constexpr int kForceUnroll = MD_FORCE_UNROLL;    // row entries in flight per lane (FP32 pair terms)
 constexpr int kForceUnroll64 = MD_FORCE_UNROLL_FP64;  // same for FP64 pair terms (register bound)
 constexpr int kKeysPerBlock = kForceBlock / kLanesPerKey;
-constexpr int kBuildChunks = 8;          // candidates held in registers: 8 x 64
+#ifndef MD_BUILD_NCH
+#define MD_BUILD_NCH 8
+#endif
+constexpr int kBuildChunks = MD_BUILD_NCH;   // candidates held in registers: kBuildChunks x 64
+constexpr int kBuildChunksSmall = 6;          // the same where neighbourhoods are small (fewer registers)
 constexpr int kReduceBlock = 1024;
 
 constexpr uint32_t kSlotMask = (1u << 27) - 1u;
@@ -205,6 +209,41 @@ __device__ __forceinline__ int tile_jw(int z0, int z1, int nz)
 {
     const int R = z1 - z0 + 2;
     return z0 == 0 ? 1 : (z1 == nz ? R - 1 : R);
+}
+
+// The same run in two steps, so that a caller can issue its loads together with
+// others: the cells whose start / count give the run's ends (cell 0 where
+// `use` is false or there is no second segment), then the loads.
+struct TileCells {
+    int64_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+    bool two = false;
+};
+__device__ __forceinline__ TileCells tile_run_cells(int X, int Y, int ny, int nz, int z0, int z1, bool use)
+{
+    const int R = z1 - z0 + 2, jw = tile_jw(z0, z1, nz);
+    const int64_t col = ((int64_t)X * ny + Y) * nz;
+    TileCells t;
+    t.two = use && jw < R;
+    if (use) {
+        t.a0 = col + wrap_cell(z0 - 1, nz);
+        t.a1 = col + wrap_cell(z0 - 2 + jw, nz);
+    }
+    if (t.two) {
+        t.b0 = col + wrap_cell(z0 - 1 + jw, nz);
+        t.b1 = col + wrap_cell(z1, nz);
+    }
+    return t;
+}
+__device__ __forceinline__ TileRun tile_run_load(const int32_t* start, const int32_t* count, const TileCells& t)
+{
+    const int sa = start[t.a0], ea = start[t.a1], ca = count[t.a1];
+    const int sb = start[t.b0], eb = start[t.b1], cb = count[t.b1];
+    TileRun r;
+    r.sA = sa;
+    r.lenA = ea + ca - sa;
+    r.sB = t.two ? sb : 0;
+    r.lenB = t.two ? eb + cb - sb : 0;
+    return r;
 }
 
 // Run of column (X, Y) (already wrapped) for the tile cells [z0, z1).

@@ -13,6 +13,7 @@
 //
 // The work is ALU bound (about 300 FP64 distance tests per particle).
 
+#include <cmath>
 #include <type_traits>
 
 #include "md_internal.h"
@@ -85,7 +86,10 @@ __device__ __forceinline__ uint32_t row_start(uint32_t end)
     return sizeof(E) == 2 ? (end + 1u) & ~1u : end;
 }
 
-constexpr int kRowBuf = 1024;   // entries of one cell's rows staged in LDS before the block is written
+#ifndef MD_BUILD_ROWBUF
+#define MD_BUILD_ROWBUF 768
+#endif
+constexpr int kRowBuf = MD_BUILD_ROWBUF;   // entries of one cell's rows staged in LDS before the block is written
 
 template <typename E>
 __device__ __forceinline__ void pad_row(E* blk, uint32_t stride, uint32_t* s_rows, uint32_t end, uint32_t pad)
@@ -210,7 +214,7 @@ __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* b
 // rows.  The order of the slices inside a pool follows the order in which the
 // cells finish.  A cell whose rows outgrow the LDS buffer counts the rest,
 // takes its slice, and computes those rows again straight into it.
-constexpr int kRowBuf16 = 2048;   // 16-bit entries of one tiled cell staged in LDS (the row buffer's 4 KB)
+constexpr int kRowBuf16 = 2 * kRowBuf;   // 16-bit entries of one tiled cell staged in LDS (the row buffer)
 
 template <bool MINIMG, int NACT>
 __device__ __forceinline__ uint32_t tiled_row_lds(const BuildArgs& a, const double4& kp, int self_t, uint32_t w0,
@@ -317,11 +321,13 @@ __device__ __forceinline__ uint32_t tiled_rows_for_chunks(int nact, const BuildA
                                                          const double* cz, const uint32_t* meta, uint16_t* s_rows16,
                                                          uint32_t* s_rowend, uint32_t pad)
 {
-    static_assert(NCH == 8, "one case per chunk count");
-#define MD_TROWS_CASE(N) \
-    case N:              \
-        return tiled_rows_from_registers<MINIMG, N>(a, tblk, tcap, tile_used, T, own_pref, own_cnt, s_key, cx, cy, \
-                                                    cz, meta, s_rows16, s_rowend, pad);
+    static_assert(NCH >= 2 && NCH <= 8, "one case per chunk count");
+#define MD_TROWS_CASE(N)                                                                                              \
+    case N:                                                                                                           \
+        if constexpr (N < NCH)                                                                                        \
+            return tiled_rows_from_registers<MINIMG, N>(a, tblk, tcap, tile_used, T, own_pref, own_cnt, s_key, cx, cy, \
+                                                        cz, meta, s_rows16, s_rowend, pad);                           \
+        break;
     switch (nact) {
         MD_TROWS_CASE(1)
         MD_TROWS_CASE(2)
@@ -331,10 +337,11 @@ __device__ __forceinline__ uint32_t tiled_rows_for_chunks(int nact, const BuildA
         MD_TROWS_CASE(6)
         MD_TROWS_CASE(7)
         default:
-            return tiled_rows_from_registers<MINIMG, 8>(a, tblk, tcap, tile_used, T, own_pref, own_cnt, s_key, cx,
-                                                        cy, cz, meta, s_rows16, s_rowend, pad);
+            break;
     }
 #undef MD_TROWS_CASE
+    return tiled_rows_from_registers<MINIMG, NCH>(a, tblk, tcap, tile_used, T, own_pref, own_cnt, s_key, cx, cy, cz,
+                                                  meta, s_rows16, s_rowend, pad);
 }
 
 // The key loop for the cell's chunk count nact in [1, NCH].
@@ -344,11 +351,13 @@ __device__ __forceinline__ uint32_t rows_for_chunks(int nact, const BuildArgs& a
                                                    const double* cy, const double* cz, const uint32_t* meta,
                                                    uint32_t* s_rows, uint32_t* s_rowend, uint32_t pad)
 {
-    static_assert(NCH == 8, "one case per chunk count");
-#define MD_ROWS_CASE(N) \
-    case N:             \
-        return rows_from_registers<MINIMG, N, E, HALF>(a, blk, stride, T, own_pref, own_cnt, s_key, cx, cy, cz, meta, \
-                                                        s_rows, s_rowend, pad);
+    static_assert(NCH >= 2 && NCH <= 8, "one case per chunk count");
+#define MD_ROWS_CASE(N)                                                                                             \
+    case N:                                                                                                         \
+        if constexpr (N < NCH)                                                                                      \
+            return rows_from_registers<MINIMG, N, E, HALF>(a, blk, stride, T, own_pref, own_cnt, s_key, cx, cy, cz, \
+                                                            meta, s_rows, s_rowend, pad);                           \
+        break;
     switch (nact) {
         MD_ROWS_CASE(1)
         MD_ROWS_CASE(2)
@@ -358,10 +367,11 @@ __device__ __forceinline__ uint32_t rows_for_chunks(int nact, const BuildArgs& a
         MD_ROWS_CASE(6)
         MD_ROWS_CASE(7)
         default:
-            return rows_from_registers<MINIMG, 8, E, HALF>(a, blk, stride, T, own_pref, own_cnt, s_key, cx, cy, cz,
-                                                           meta, s_rows, s_rowend, pad);
+            break;
     }
 #undef MD_ROWS_CASE
+    return rows_from_registers<MINIMG, NCH, E, HALF>(a, blk, stride, T, own_pref, own_cnt, s_key, cx, cy, cz, meta,
+                                                     s_rows, s_rowend, pad);
 }
 
 // Same rows, candidates re-read from memory for every key (neighbourhoods with
@@ -442,23 +452,26 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     __shared__ uint32_t s_rowend[kMaxOwn];
     __shared__ int s_lbase[27];
     __shared__ uint32_t s_pad;
-    // tiled: the tile's 9 column runs (lanes 0..8), loaded together with the
-    // neighbour cells below
+    // Every lane issues its loads before any result is used (a wait inside a
+    // branch would serialise them): the neighbour cell of lanes 0..26, and,
+    // tiled, the cells at the ends of the tile's column runs (lanes 0..8);
+    // lanes without one load cell 0.  Half rows take candidates from the own
+    // cell (code 13) and codes 14 .. 26 only: the other 13 cells count as empty.
     const int z0 = TILED ? (cz / a.tc) * a.tc : 0, z1 = TILED ? min(z0 + a.tc, nz) : 0;
-    TileRun run = {0, 0, 0, 0};
-    if (TILED && lane < 9)
-        run = tile_run(a.start, a.count, wrap_cell(cx + lane / 3 - 1, nx), wrap_cell(cy + lane % 3 - 1, ny), ny, nz,
-                       z0, z1);
-    // half rows take candidates from the own cell (code 13) and codes 14 .. 26
-    // only: the other 13 cells count as empty
-    int cnt = 0, st = 0;
-    if (lane < 27 && (!HALF || lane >= 13)) {
+    const bool has_nb = lane < 27 && (!HALF || lane >= 13);
+    int nb = 0;
+    if (lane < 27) {
         const int ax = wrap_cell(cx + lane / 9 - 1, nx), ay = wrap_cell(cy + (lane / 3) % 3 - 1, ny);
         const int az = wrap_cell(cz + lane % 3 - 1, nz);
-        const int nb = (ax * ny + ay) * nz + az;
-        st = a.start[nb];
-        cnt = a.count[nb];
+        nb = has_nb ? (ax * ny + ay) * nz + az : 0;
     }
+    TileCells tcl;
+    if (TILED) tcl = tile_run_cells(wrap_cell(cx + lane / 3 - 1, nx), wrap_cell(cy + lane % 3 - 1, ny), ny, nz, z0, z1,
+                                    lane < 9);
+    const int st_l = a.start[nb], cnt_l = a.count[nb];
+    TileRun run = {0, 0, 0, 0};
+    if (TILED) run = tile_run_load(a.start, a.count, tcl);
+    const int st = has_nb ? st_l : 0, cnt = has_nb ? cnt_l : 0;
     int incl = cnt;
 #pragma unroll
     for (int o = 1; o < 32; o <<= 1) {
@@ -527,16 +540,20 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     }
 
     if (own_cnt > 0 && T <= NCH * 64 && own_cnt <= kMaxOwn) {
-        // candidate table: entry t = (the candidate's position in the cell
-        // order, its list entry bits), written by the lane of its cell; it
+        // candidate table: for entry t, the candidate's position in the cell
+        // order and (16 bits) its staged index in the tile's neighbourhood
+        // (tiled) or its stencil code, written by the lane of its cell; it
         // lives in the row buffer, which is free until the rows are made
-        static_assert(NCH * 64 * sizeof(uint2) <= sizeof(uint32_t) * (kRowBuf + 2), "table fits the row buffer");
-        uint2* s_tab = reinterpret_cast<uint2*>(s_rows);
+        static_assert(NCH * 64 * (sizeof(uint32_t) + sizeof(uint16_t)) <= sizeof(uint32_t) * (kRowBuf + 2),
+                      "table fits the row buffer");
+        uint32_t* s_tpos = s_rows;
+        uint16_t* s_tcode = reinterpret_cast<uint16_t*>(s_rows + NCH * 64);
         if (lane < 27) {
             const int t0 = incl - cnt;
-            const uint32_t mb = TILED ? (uint32_t)lb << 4 : (uint32_t)lane << kCodeShift;
-            for (int i = 0; i < cnt; ++i)
-                s_tab[t0 + i] = make_uint2((uint32_t)(st + i), TILED ? mb + ((uint32_t)i << 4) : mb);
+            for (int i = 0; i < cnt; ++i) {
+                s_tpos[t0 + i] = (uint32_t)(st + i);
+                s_tcode[t0 + i] = (uint16_t)(TILED ? lb + i : lane);
+            }
         }
         __syncthreads();
         double px[NCH], py[NCH], pz[NCH];
@@ -549,14 +566,15 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
             if (ch * 64 >= T) continue;          // uniform: chunk beyond the neighbourhood
             const int tq = ch * 64 + lane;
             const bool ok = tq < T;
-            const uint2 e = s_tab[ok ? tq : T - 1];   // in-range entry; discarded if tq >= T
-            const int32_t slot = a.order ? a.order[e.x] : (int32_t)e.x;
+            const int te = ok ? tq : T - 1;   // in-range entry; discarded if tq >= T
+            const uint32_t ex = s_tpos[te], ey = s_tcode[te];
+            const int32_t slot = a.order ? a.order[ex] : (int32_t)ex;
             const double4 p = a.pos[slot];
             // a NaN x alone fails the distance test in both forms of it
             px[ch] = ok ? p.x : qnan;
             py[ch] = p.y;
             pz[ch] = p.z;
-            meta[ch] = TILED ? e.y : ((uint32_t)slot | e.y);
+            meta[ch] = TILED ? ey << 4 : ((uint32_t)slot | (ey << kCodeShift));
             const int k = tq - own_pref;
             if (ok && k >= 0 && k < own_cnt) s_key[k] = make_double4(p.x, p.y, p.z, __longlong_as_double((long long)slot));
         }
@@ -672,9 +690,23 @@ hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cel
     if (e != hipSuccess) return e;
     if (tiled && (e = launch_fill_i32(tile_used, 0, g.ntile, s)) != hipSuccess) return e;
     const dim3 grid((unsigned)g.ncell);
-    if (tiled) hipLaunchKernelGGL((k_build<kBuildChunks, true, false>), grid, dim3(64), 0, s, a);
-    else if (half) hipLaunchKernelGGL((k_build<kBuildChunks, false, true>), grid, dim3(64), 0, s, a);
-    else hipLaunchKernelGGL((k_build<kBuildChunks, false, false>), grid, dim3(64), 0, s, a);
+    // candidates held in registers: 6 chunks of 64 (fewer registers, more
+    // waves per SIMD) when a neighbourhood that large is far in the tail at
+    // the mean density (4 standard deviations of a Poisson count above the
+    // mean), else 8; larger neighbourhoods take the path that re-reads
+    // memory for every key
+    const double mean_t = (half ? 14.0 : 27.0) * (double)g.n / (double)g.ncell;
+    const bool small = mean_t + 4.0 * std::sqrt(mean_t) <= (double)(kBuildChunksSmall * 64);
+    if (tiled) {
+        if (small) hipLaunchKernelGGL((k_build<kBuildChunksSmall, true, false>), grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_build<kBuildChunks, true, false>), grid, dim3(64), 0, s, a);
+    } else if (half) {
+        if (small) hipLaunchKernelGGL((k_build<kBuildChunksSmall, false, true>), grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_build<kBuildChunks, false, true>), grid, dim3(64), 0, s, a);
+    } else {
+        if (small) hipLaunchKernelGGL((k_build<kBuildChunksSmall, false, false>), grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_build<kBuildChunks, false, false>), grid, dim3(64), 0, s, a);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = launch_list_stats(a.cell_rows, g.ncell, list.status, (long long*)((char*)ws + L.red), s);
