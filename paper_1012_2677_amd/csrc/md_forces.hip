@@ -128,6 +128,30 @@ __device__ __forceinline__ int group8_max(int v)
     return max(v, __builtin_amdgcn_update_dpp(0, v, kDppXor1, 0xF, 0xF, false));
 }
 
+// Sums over groups of G = 4 or 8 lanes (every lane of a group gets the same,
+// bitwise identical total) and maxima over groups of K = 8 or 16 lanes.
+constexpr int kDppRowMirror = 0x140;   // lane j <-> 15 - j inside each row of 16
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v)
+{
+    if constexpr (G == 8) return group8_sum(v);
+    static_assert(G == 8 || G == 4, "groups of 4 or 8 lanes");
+    if constexpr (sizeof(T) == 4) {
+        v += dpp_f32<kDppXor2>(v);
+        return v + dpp_f32<kDppXor1>(v);
+    } else {
+        v += dpp_f64<kDppXor2>(v);
+        return v + dpp_f64<kDppXor1>(v);
+    }
+}
+template <int K>
+__device__ __forceinline__ int group_max(int v)
+{
+    static_assert(K == 8 || K == 16, "groups of 8 or 16 lanes");
+    if constexpr (K == 16) v = max(v, __builtin_amdgcn_update_dpp(0, v, kDppRowMirror, 0xF, 0xF, false));
+    return group8_max(v);
+}
+
 __device__ __forceinline__ double wrap_coord(double x, double L, double invL)
 {
     double y = x - L * floor(x * invL);
@@ -726,8 +750,9 @@ __global__ __launch_bounds__(kForceBlock) void k_integrate_half(PairArgs a)
 //   displacements take the minimum image in tiles that touch the box
 //   boundary (a no-op for pairs that do not wrap), as in k_pairs_fp64.
 // The tile's keys are split evenly over the waves.  In each 64-key chunk the
-// rows are walked in rounds of 8 keys grouped by row length, the first
-// kPrefetch entries of all 8 rounds loaded up front, two per 32-bit load.  Key
+// rows are walked in rounds of 64 / G keys grouped by row length (G lanes per
+// row: 4 in mixed precision, 8 in FP64), the first kPrefetch entries of all G
+// rounds loaded up front, two per 32-bit load.  Key
 // data reach the round's lanes by shuffles; group sums and the integrator
 // epilogue are those of the other pair kernels.
 #ifndef MD_TILE_STRIP
@@ -738,6 +763,17 @@ constexpr int kTileStrip = MD_TILE_STRIP;       // x-columns per strip of the ti
 #define MD_TILE_PREFETCH 64
 #endif
 constexpr int kPrefetch = MD_TILE_PREFETCH;     // row entries per key loaded up front (multiple of 16)
+#ifndef MD_TILE_LANES_MIXED
+#define MD_TILE_LANES_MIXED 4
+#endif
+#ifndef MD_TILE_LANES_FP64
+#define MD_TILE_LANES_FP64 8
+#endif
+// lanes that walk one row (4 or 8): fewer lanes spread a round's fixed costs
+// (key data, group sums) over more entries per lane; FP64 keeps 8, since with
+// 4 its registers pass 128 and a SIMD holds one wave fewer
+constexpr int kTileLanesMixed = MD_TILE_LANES_MIXED;
+constexpr int kTileLanes64 = MD_TILE_LANES_FP64;
 
 template <bool MIXED>
 struct TileT;
@@ -878,7 +914,10 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     const int64_t colc = ((int64_t)cx * ny + cy) * nz;
     const int64_t kb = a.start[colc + z0];
     const int64_t kend = (int64_t)a.start[colc + z1 - 1] + a.count[colc + z1 - 1];
-    const int wave = tid >> 6, lane = tid & 63, sub = lane & 7, grp = lane >> 3;
+    // G lanes walk each row; a round takes K = 64 / G keys, a chunk of 64
+    // keys G rounds
+    constexpr int G = MIXED ? kTileLanesMixed : kTileLanes64, K = 64 / G;
+    const int wave = tid >> 6, lane = tid & 63, sub = lane & (G - 1), grp = lane / G;
     const R rc2 = (R)a.lj.rc2, A = (R)a.lj.A, B = (R)a.lj.B, C8 = (R)a.lj.C8;
     double pe = 0.0, w = 0.0, ke = 0.0, d2 = 0.0, v2 = 0.0;
     auto nb = [&](uint32_t e) { return *(const S*)((const char*)s_nb + TileT<MIXED>::off(e)); };
@@ -919,7 +958,7 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     const int csz_k = nk >= NW * 64 ? 64 : (int)((((nk + NW - 1) / NW) + 7) & ~(int64_t)7);
     for (int64_t base = kb + wave * csz_k; base < kend; base += NW * csz_k) {
     const int64_t cend = base + csz_k < kend ? base + csz_k : kend;
-    const int nr = (int)((cend - base + 7) >> 3);
+    const int nr = (int)((cend - base + K - 1) / K);
     const int64_t mykey = base + lane;
     const bool myvalid = mykey < cend;
     // the lane's own key: coordinates (mixed: local, with its run position in
@@ -938,13 +977,13 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         own_off = a.offsets[k];
         own_cnt = myvalid ? a.counts[k] : 0;
     }
-    // round order: the chunk's keys grouped by row length in steps of 16
-    // entries (longest first), so that the 8 rows a round walks to a common
-    // bound have similar lengths; lane L's key is walked in round pr >> 3 by
-    // group pr & 7
+    // round order: the chunk's keys grouped by row length in steps of 2G
+    // entries (longest first), so that the K rows a round walks to a common
+    // bound have similar lengths; lane L's key is walked in round pr / K by
+    // group pr % K
     int pr;
     {
-        const int b = min((own_cnt + 15) >> 4, 7);
+        const int b = min((own_cnt + 2 * G - 1) / (2 * G), 7);
         int off = 0;
         pr = 0;
 #pragma unroll
@@ -957,31 +996,32 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     }
     __builtin_amdgcn_wave_barrier();
     // the first kPrefetch entries of the rows each lane walks, two per 32-bit
-    // load: lane j of a group takes entries 2j + 16u and 2j + 16u + 1; all
+    // load: lane j of a group takes entries 2j + 2Gu and 2j + 2Gu + 1; all
     // loads of the chunk go out at once
     // (48 entries when the drift speed is tracked, to stay within 128 VGPRs)
     constexpr int PF = VMAX ? 48 : kPrefetch;
-    constexpr int UP = PF / 16;
+    constexpr int UP = PF / (2 * G);
     const uint32_t dummy2 = dummy | (dummy << 16);
-    uint32_t E[8][UP];
+    uint32_t E[G][UP];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < G; ++r) {
         if (r >= nr) break;
-        const int ks = s_perm[wave][(r << 3) | grp];
+        const int ks = s_perm[wave][r * K + grp];
         const int cnt = __shfl(own_cnt, ks, 64);
         const uint32_t* row2 = (const uint32_t*)((const uint16_t*)a.nbr + __shfl(own_off, ks, 64));
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
-            const int t = 2 * sub + 16 * u;
+            const int t = 2 * sub + 2 * G * u;
             E[r][u] = t < cnt ? row2[t >> 1] : dummy2;
         }
     }
     R kfx = 0, kfy = 0, kfz = 0;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < G; ++r) {
         if (r >= nr) break;
-        const int ks = s_perm[wave][(r << 3) | grp];
-        const int cmax = __builtin_amdgcn_readfirstlane(group8_max(__shfl(own_cnt, s_perm[wave][(r << 3) | sub], 64)));
+        const int ks = s_perm[wave][r * K + grp];
+        const int cmax =
+            __builtin_amdgcn_readfirstlane(group_max<K>(__shfl(own_cnt, s_perm[wave][r * K + (lane & (K - 1))], 64)));
         const int cnt = __shfl(own_cnt, ks, 64);
         V4 li;
         li.x = __shfl(own.x, ks, 64);
@@ -991,7 +1031,7 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         R fx = 0, fy = 0, fz = 0;
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
-            if (16 * u < cmax) {
+            if (2 * G * u < cmax) {
                 const S p0 = nb(E[r][u] & 0xFFFFu), p1 = nb(E[r][u] >> 16);
                 pair(p0, li, fx, fy, fz);
                 pair(p1, li, fx, fy, fz);
@@ -1000,23 +1040,23 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         if (cmax > PF) {
             // the rest of rows longer than the prefetched part
             const uint16_t* row = (const uint16_t*)a.nbr + __shfl(own_off, ks, 64);
-            for (int t0 = PF + sub; t0 - sub < cmax; t0 += 8 * U) {
+            for (int t0 = PF + sub; t0 - sub < cmax; t0 += G * U) {
                 uint32_t e[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int t = t0 + u * 8;
+                    const int t = t0 + u * G;
                     e[u] = t < cnt ? (uint32_t)row[t] : dummy;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (t0 - sub + u * 8 < cmax) pair(nb(e[u]), li, fx, fy, fz);
+                    if (t0 - sub + u * G < cmax) pair(nb(e[u]), li, fx, fy, fz);
             }
         }
-        const int src = (pr & 7) << 3;
-        fx = __shfl(group8_sum(fx), src, 64);
-        fy = __shfl(group8_sum(fy), src, 64);
-        fz = __shfl(group8_sum(fz), src, 64);
-        if ((pr >> 3) == r) {
+        const int src = (pr % K) * G;
+        fx = __shfl(group_sum<G>(fx), src, 64);
+        fy = __shfl(group_sum<G>(fy), src, 64);
+        fz = __shfl(group_sum<G>(fz), src, 64);
+        if (pr / K == r) {
             kfx = fx;
             kfy = fy;
             kfz = fz;
