@@ -40,6 +40,7 @@ struct BuildArgs {
     unsigned long long* tile_max;     // tiled: atomic max of the staged count per tile
     FastDiv div_nz;                   // division by nz and by kBuildStrip * ny (cell order decode)
     FastDiv div_strip;
+    FastDiv div_tc;                   // tiled: division by tc
     int32_t nt;                       // tiled: tiles per column
     int32_t* tile_used;               // tiled: entries taken so far in each tile's pooled block
 };
@@ -57,6 +58,26 @@ __device__ __forceinline__ double pair_r2(const BuildArgs& a, double xj, double 
         dz = dz - a.L[2] * rint(dz * a.invL[2]);
     }
     return __builtin_fma(dz, dz, __builtin_fma(dy, dy, __dmul_rn(dx, dx)));
+}
+
+// Inclusive prefix sums by DPP lane moves (no LDS round trips): over each row
+// of 16 lanes (Hillis-Steele shifts by 1, 2, 4, 8; lanes shifted in from
+// outside the row read 0), and over lanes 0 .. 31 (row 1 then adds lane 15).
+constexpr int kDppRowShr = 0x110;     // row_shr:n is kDppRowShr + n
+constexpr int kDppRowBcast15 = 0x142;
+__device__ __forceinline__ int scan_row16(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 1, 0xF, 0xF, true);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 2, 0xF, 0xF, true);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 4, 0xF, 0xF, true);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 8, 0xF, 0xF, true);
+    return v;
+}
+__device__ __forceinline__ int scan_lanes32(int v)
+{
+    v = scan_row16(v);
+    // rows 1 and 3 take lane 15 of the row below; rows 0 and 2 add nothing
+    return v + __builtin_amdgcn_update_dpp(0, v, kDppRowBcast15, 0xA, 0xF, false);
 }
 
 // Row header of one key.  When the cell block overflows, the row is clipped to
@@ -457,7 +478,8 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     // tiled, the cells at the ends of the tile's column runs (lanes 0..8);
     // lanes without one load cell 0.  Half rows take candidates from the own
     // cell (code 13) and codes 14 .. 26 only: the other 13 cells count as empty.
-    const int z0 = TILED ? (cz / a.tc) * a.tc : 0, z1 = TILED ? min(z0 + a.tc, nz) : 0;
+    const int tz = TILED ? (int)fdiv((uint32_t)cz, a.div_tc) : 0;   // the cell's tile along z
+    const int z0 = tz * a.tc, z1 = TILED ? min(z0 + a.tc, nz) : 0;
     const bool has_nb = lane < 27 && (!HALF || lane >= 13);
     int nb = 0;
     if (lane < 27) {
@@ -472,12 +494,7 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     TileRun run = {0, 0, 0, 0};
     if (TILED) run = tile_run_load(a.start, a.count, tcl);
     const int st = has_nb ? st_l : 0, cnt = has_nb ? cnt_l : 0;
-    int incl = cnt;
-#pragma unroll
-    for (int o = 1; o < 32; o <<= 1) {
-        const int y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-    }
+    const int incl = scan_lanes32(cnt);
     if (lane < 27) {
         s_nstart[lane] = st;
         s_pref[lane + 1] = incl;
@@ -491,12 +508,7 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
         // the column of q)
         const int jw = tile_jw(z0, z1, nz);
         const int len = lane < 9 ? run.lenA + run.lenB : 0;
-        int inc = len;
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
-            const int y = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += y;
-        }
+        const int inc = scan_row16(len);
         const int total = __shfl(inc, 8, 64);
         const int col = lane < 27 ? lane / 3 : 0;
         const int cbase = __shfl(inc - len, col, 64);
@@ -509,7 +521,7 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
         if (lane == 0) {
             s_pad = (uint32_t)total << 4;   // the stand-in partner of the force pass
             if (cz == z0) {
-                const int64_t tile = ((int64_t)cx * ny + cy) * ((nz + a.tc - 1) / a.tc) + cz / a.tc;
+                const int64_t tile = ((int64_t)cx * ny + cy) * a.nt + tz;
                 atomicMax(a.tile_max + (tile & (kTileMaxSlots - 1)), (unsigned long long)total);
             }
         }
@@ -536,7 +548,7 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
         const int64_t colc = (int64_t)cx * ny + cy;
         tblk = (uint16_t*)a.nbr + (colc * nz + z0) * a.stride;
         tcap = (uint64_t)(z1 - z0) * (uint64_t)a.stride;
-        tused = a.tile_used + colc * a.nt + cz / a.tc;
+        tused = a.tile_used + colc * a.nt + tz;
     }
 
     if (own_cnt > 0 && T <= NCH * 64 && own_cnt <= kMaxOwn) {
@@ -681,6 +693,7 @@ hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cel
     a.tile_max = tile_max;
     a.div_nz = make_fastdiv((uint32_t)g.nc[2]);
     a.div_strip = make_fastdiv((uint32_t)(kBuildStrip * g.nc[1]));
+    a.div_tc = make_fastdiv((uint32_t)(g.tc > 0 ? g.tc : 1));
     a.nt = g.nt;
     a.tile_used = tile_used;
     if (tiled && (half || !cells.sorted || g.tc <= 0 || !tile_max)) return hipErrorInvalidValue;
