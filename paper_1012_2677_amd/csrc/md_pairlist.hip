@@ -639,30 +639,36 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
 }
 
 // Stride a tiled list needs: the largest ceil(tile total / cells of the tile)
-// over the tiles, into status[1].
-__global__ __launch_bounds__(1024) void k_tile_need(const int32_t* __restrict__ tile_used, int64_t ntile, int32_t nt,
-                                                    int32_t tc, int32_t nz, int64_t* __restrict__ status)
+// over the tiles (block maxima, then one block), into status[1].  Tile totals
+// and counts stay below 2^31.
+constexpr int kNeedBlocks = 1024;
+__device__ __forceinline__ int block_max_256(int m)
 {
-    __shared__ long long s_m[16];
-    long long m = 0;
-    for (int64_t t = threadIdx.x; t < ntile; t += 1024) {
-        const int tz = (int)(t % nt);
-        const int cells = min(tc, nz - tz * tc);
-        const long long need = ((long long)tile_used[t] + cells - 1) / cells;
-        m = need > m ? need : m;
-    }
+    __shared__ int s_m[4];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const long long y = __shfl_xor(m, o, 64);
-        m = y > m ? y : m;
-    }
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        long long r = 0;
-        for (int w = 0; w < 16; ++w) r = s_m[w] > r ? s_m[w] : r;
-        status[1] = r;
+    return max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
+}
+__global__ __launch_bounds__(256) void k_tile_need(const int32_t* __restrict__ tile_used, int32_t ntile, int32_t nt,
+                                                   int32_t tc, int32_t last_cells, int32_t* __restrict__ part)
+{
+    int m = 0;
+    for (int t = blockIdx.x * 256 + threadIdx.x; t < ntile; t += gridDim.x * 256) {
+        const int cells = (t % nt) == nt - 1 ? last_cells : tc;
+        m = max(m, (tile_used[t] + cells - 1) / cells);
     }
+    m = block_max_256(m);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+__global__ __launch_bounds__(256) void k_tile_need_final(const int32_t* __restrict__ part, int nb,
+                                                         int64_t* __restrict__ status)
+{
+    int m = 0;
+    for (int b = threadIdx.x; b < nb; b += 256) m = max(m, part[b]);
+    m = block_max_256(m);
+    if (threadIdx.x == 0) status[1] = m;
 }
 
 hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cells& cells,
@@ -724,7 +730,13 @@ hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cel
     if (e != hipSuccess) return e;
     e = launch_list_stats(a.cell_rows, g.ncell, list.status, (long long*)((char*)ws + L.red), s);
     if (e != hipSuccess || !tiled) return e;
-    hipLaunchKernelGGL(k_tile_need, dim3(1), dim3(1024), 0, s, tile_used, g.ntile, g.nt, g.tc, g.nc[2], list.status);
+    // the statistics are read: their scratch takes the tiles' block maxima
+    int32_t* part = (int32_t*)((char*)ws + L.red);
+    const int nb = (int)std::min<int64_t>(ceil_div(g.ntile, 256), kNeedBlocks);
+    const int last_cells = g.nc[2] - (g.nt - 1) * g.tc;
+    hipLaunchKernelGGL(k_tile_need, dim3(nb), dim3(256), 0, s, tile_used, (int32_t)g.ntile, g.nt, g.tc, last_cells,
+                       part);
+    hipLaunchKernelGGL(k_tile_need_final, dim3(1), dim3(256), 0, s, (const int32_t*)part, nb, list.status);
     return hipGetLastError();
 }
 
