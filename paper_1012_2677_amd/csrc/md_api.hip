@@ -816,7 +816,8 @@ int md_prepare(const md_params* p, md_state* st, hipStream_t s)
     IntArgs a = int_args(c, p, st, true);
     MD_HIP(launch_integrate(c.g, INT_KE, a, s), "prepare/ke");
     MD_HIP(launch_reduce_energy((double*)((char*)st->ws + c.W.part_a), force_blocks(c.g, st->list_tiled),
-                                (double*)((char*)st->ws + c.W.part_b), c.W.nbi, st->energy, nullptr, s),
+                                (double*)((char*)st->ws + c.W.part_b), c.W.nbi, st->energy, nullptr,
+                                (double*)((char*)st->ws + c.W.red), s),
            "prepare/reduce");
     if ((rc = read_flags(c, st, s, f)) != MD_OK) return rc;
     if ((rc = check_status(f, st)) != MD_OK) return rc;
@@ -838,7 +839,8 @@ int md_energy(const md_params* p, md_state* st, double* out, hipStream_t s)
     IntArgs a = int_args(c, p, st, true);
     MD_HIP(launch_integrate(c.g, INT_KE, a, s), "energy/ke");
     MD_HIP(launch_reduce_energy((double*)((char*)st->ws + c.W.part_a), force_blocks(c.g, st->list_tiled),
-                                (double*)((char*)st->ws + c.W.part_b), c.W.nbi, st->energy, out, s),
+                                (double*)((char*)st->ws + c.W.part_b), c.W.nbi, st->energy, out,
+                                (double*)((char*)st->ws + c.W.red), s),
            "energy/reduce");
     return MD_OK;
 }
@@ -957,7 +959,8 @@ static int step_runs(const Ctx& c, const md_params* p, md_state* st, int64_t nst
             if (sample) {
                 tick(T, MD_T_REDUCE, 0, s);
                 MD_HIP(launch_reduce_energy(part_pw, nfb, part_ke, nfb, st->energy,
-                                            energy_log ? energy_log + 4 * k_run : nullptr, s, g),
+                                            energy_log ? energy_log + 4 * k_run : nullptr,
+                                            (double*)((char*)st->ws + c.W.red), s, g),
                        "step/reduce");
                 tick(T, MD_T_REDUCE, 1, s);
                 ++k_run;
@@ -1116,7 +1119,8 @@ static int step_loop(const md_params* p, md_state* st, int64_t nsteps, int64_t s
             tick(T, MD_T_REDUCE, 0, s);
             const int64_t nfb = force_blocks(c.g, st->list_tiled);
             MD_HIP(launch_reduce_energy(part_pw, nfb, part_ke, nfb, st->energy,
-                                        energy_log ? energy_log + 4 * k_log : nullptr, s),
+                                        energy_log ? energy_log + 4 * k_log : nullptr,
+                                        (double*)((char*)st->ws + c.W.red), s),
                    "step/reduce");
             tick(T, MD_T_REDUCE, 1, s);
             ++k_log;

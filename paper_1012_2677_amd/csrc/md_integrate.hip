@@ -167,20 +167,47 @@ __device__ __forceinline__ double block_sum_1024(double v)
     return t;
 }
 
-// energy[0..3] = (KE, PE, W, KE + PE); also into log_row when given.
-__global__ __launch_bounds__(kReduceBlock) void k_reduce_energy(const double* __restrict__ part_pw, int64_t nbf,
-                                                                const double* __restrict__ part_ke, int64_t nbi,
+// energy[0..3] = (KE, PE, W, KE + PE); also into log_row when given.  Two
+// fixed-order levels: block b sums its contiguous share of the partials into
+// part3[3b .. 3b+2], then one block sums those in block order.
+constexpr int kEnergyBlocks = 256;
+__global__ __launch_bounds__(kReduceBlock) void k_reduce_energy_part(const double* __restrict__ part_pw, int64_t nbf,
+                                                                     const double* __restrict__ part_ke, int64_t nbi,
+                                                                     double* __restrict__ part3,
+                                                                     const int32_t* __restrict__ gate)
+{
+    if (gate && gate[0]) return;
+    const int64_t cf = (nbf + gridDim.x - 1) / gridDim.x, ci = (nbi + gridDim.x - 1) / gridDim.x;
+    const int64_t f0 = (int64_t)blockIdx.x * cf, f1 = min(f0 + cf, nbf);
+    const int64_t i0 = (int64_t)blockIdx.x * ci, i1 = min(i0 + ci, nbi);
+    double pe = 0.0, w = 0.0, ke = 0.0;
+    for (int64_t b = f0 + threadIdx.x; b < f1; b += kReduceBlock) {
+        pe += part_pw[2 * b];
+        w += part_pw[2 * b + 1];
+    }
+    for (int64_t b = i0 + threadIdx.x; b < i1; b += kReduceBlock) ke += part_ke[b];
+    pe = block_sum_1024(pe);
+    w = block_sum_1024(w);
+    ke = block_sum_1024(ke);
+    if (threadIdx.x == 0) {
+        part3[3 * blockIdx.x] = pe;
+        part3[3 * blockIdx.x + 1] = w;
+        part3[3 * blockIdx.x + 2] = ke;
+    }
+}
+
+__global__ __launch_bounds__(kReduceBlock) void k_reduce_energy(const double* __restrict__ part3, int nb,
                                                                 double* __restrict__ energy,
                                                                 double* __restrict__ log_row,
                                                                 const int32_t* __restrict__ gate)
 {
     if (gate && gate[0]) return;
     double pe = 0.0, w = 0.0, ke = 0.0;
-    for (int64_t b = threadIdx.x; b < nbf; b += kReduceBlock) {
-        pe += part_pw[2 * b];
-        w += part_pw[2 * b + 1];
+    if ((int)threadIdx.x < nb) {
+        pe = part3[3 * threadIdx.x];
+        w = part3[3 * threadIdx.x + 1];
+        ke = part3[3 * threadIdx.x + 2];
     }
-    for (int64_t b = threadIdx.x; b < nbi; b += kReduceBlock) ke += part_ke[b];
     pe = block_sum_1024(pe);
     w = block_sum_1024(w);
     ke = block_sum_1024(ke);
@@ -199,10 +226,15 @@ __global__ __launch_bounds__(kReduceBlock) void k_reduce_energy(const double* __
 }
 
 hipError_t launch_reduce_energy(const double* part_pw, int64_t nbf, const double* part_ke, int64_t nbi,
-                                double* energy, double* log_row, hipStream_t s, const int32_t* gate)
+                                double* energy, double* log_row, double* scratch, hipStream_t s,
+                                const int32_t* gate)
 {
-    hipLaunchKernelGGL(k_reduce_energy, dim3(1), dim3(kReduceBlock), 0, s, part_pw, nbf, part_ke, nbi,
-                       energy, log_row, gate);
+    const int64_t most = nbf > nbi ? nbf : nbi;
+    const int nb = (int)std::min<int64_t>(std::max<int64_t>(ceil_div(most, kReduceBlock), 1), kEnergyBlocks);
+    hipLaunchKernelGGL(k_reduce_energy_part, dim3(nb), dim3(kReduceBlock), 0, s, part_pw, nbf, part_ke, nbi,
+                       scratch, gate);
+    hipLaunchKernelGGL(k_reduce_energy, dim3(1), dim3(kReduceBlock), 0, s, (const double*)scratch, nb, energy,
+                       log_row, gate);
     return hipGetLastError();
 }
 

@@ -376,8 +376,9 @@ __device__ __forceinline__ double pinned_len2(double x, double y, double z)
     return __builtin_fma(z, z, __builtin_fma(y, y, __dmul_rn(x, x)));
 }
 hipError_t launch_integrate(const Geo& g, IntMode mode, const IntArgs& a, hipStream_t s);
+// scratch: device double[3 * 256] (block partials)
 hipError_t launch_reduce_energy(const double* part_pw, int64_t nbf, const double* part_ke,
-                                int64_t nbi, double* energy, double* log_row, hipStream_t s,
+                                int64_t nbi, double* energy, double* log_row, double* scratch, hipStream_t s,
                                 const int32_t* gate = nullptr);
 hipError_t launch_reduce_pair(const double* part, int64_t nb, double scale0, double scale1,
                               double* out2, hipStream_t s, bool accumulate = false);
