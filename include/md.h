@@ -13,9 +13,11 @@
  *   - Every pointer argument named as "device" is a device (HBM) address on the
  *     current HIP device; "host" pointers are ordinary host memory.
  *   - The caller allocates and frees every buffer, including the workspace;
- *     the library never allocates device memory.
- *   - All work is enqueued on the given hipStream_t.  Only md_prepare and
- *     md_step synchronise that stream (they read device flags); every other
+ *     the library never allocates device memory (md_forces_noalloc keeps its
+ *     scratch in a fixed array of the library's own, see there).
+ *   - All work is enqueued on the given hipStream_t.  md_prepare, md_step,
+ *     md_step_record and md_ldc_check synchronise that stream (they read
+ *     device flags), md_hbm_probe waits for its timing events; every other
  *     call is asynchronous and returns only errors detectable on the host.
  *   - Return value: MD_OK (0) or a negative MD_ERR_* code; md_last_error()
  *     then returns a message (thread-local, valid until the next call).
@@ -377,8 +379,9 @@ int md_prepare(const md_params* p, md_state* st, hipStream_t stream);
  * after each step sets a device flag once the next step must rebuild, the
  * passes of the run's later steps then do nothing, and the host waits once
  * per run and once per rebuild, resuming where the run stopped.  With
- * MD_REBUILD_DUTC_LDC or a half list it waits once per step.  On MD_ERR_CAPACITY the state stops in
- * phase 1 with st->step steps done; grow the list and call md_step again.
+ * MD_REBUILD_DUTC_LDC or a half list it waits once per step.
+ * On MD_ERR_CAPACITY the state stops in phase 1 with st->step steps done;
+ * grow the list and call md_step again.
  * MD_ERR_NONFINITE stops after the step that produced a non-finite force. */
 int md_step(const md_params* p, md_state* st, int64_t nsteps, int64_t sample_every,
             double* energy_log, hipStream_t stream);
