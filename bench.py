@@ -74,7 +74,7 @@ def force_bytes_per_key(mean_entries: float, mixed: bool, tiled: bool = False, h
     return idx + 32 + (0 if tiled else 4) + 48 + 24 + 32 + fbytes
 
 
-def survey_bytes_per_key(mean_entries: float) -> float:
+def plan_bytes_per_key(mean_entries: float) -> float:
     """Algorithmic bytes per particle of the fused force + integrator pass as
     the hot path's measurement plan counts them, whatever the list layout:
     the force row reads 4 bytes per list entry, an 8-byte row offset and the
@@ -227,7 +227,7 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
     if fl > 0:
         avg_ms = fm / fl
         per_launch = n * force_bytes_per_key(entries / n, precision == "mixed", bool(tiled), bool(half))
-        plan = n * survey_bytes_per_key(entries / n)
+        plan = n * plan_bytes_per_key(entries / n)
         out["force_kernel"] = {"avg_ms": avg_ms, "launches": fl,
                                "algorithmic_bytes_per_launch": plan,
                                "achieved_GBs": plan / (avg_ms * 1e-3) / 1e9,
