@@ -44,6 +44,14 @@ class Field:
         self._own_pos = torch.empty((self.n, 4), dtype=torch.float64, device=self.device)
         self.pos = self._own_pos
         self.out2 = torch.empty(2, dtype=torch.float64, device=self.device)
+        # the cell grid and list the passes use: the field's own, or those of
+        # an engine whose last build was at the positions the field's would
+        # have been built at (use_lists_of)
+        self._cells, self._list = self.grid.c, self.plist.l
+        # deferred list checks (defer_checks): the largest overflow flag of
+        # the builds since the last check, on the device
+        self.deferred = False
+        self.overflow = torch.zeros(1, dtype=torch.int64, device=self.device)
 
     def set_params(self, eps, sigma):
         self.params.eps = float(eps)
@@ -69,9 +77,44 @@ class Field:
         if rebuild:
             self._build()
 
+    def use_lists_of(self, engine: Engine, frame: torch.Tensor):
+        """Positions `frame` (as use_frame) with the cell grid and slot-entry
+        pair list of `engine`, whose last build was at positions that every
+        pair within rc of `frame` was listed at (its list is still valid
+        there): no build.  The engine must not re-sort (slots = particles) and
+        must not move on while the field uses its lists."""
+        assert frame.dtype == torch.float64 and frame.is_contiguous() and tuple(frame.shape) == (self.n, 4)
+        assert engine.n == self.n and int(engine.params.resort_every) == 0 and not engine.state.list.tiled
+        self.pos = frame
+        self._cells, self._list = engine.state.cells, engine.state.list
+
+    def defer_checks(self, on: bool = True):
+        """When on, a build does not wait to read its overflow flag: the flag
+        is folded into `overflow` on the device, for check_lists() to read once
+        for many builds (a list that overflowed has rows cut short, so every
+        pass since must be redone after the list has grown)."""
+        self.deferred = on
+        self.overflow.zero_()
+
+    def check_lists(self) -> bool:
+        """True when no build overflowed since the last check (waits for the
+        stream); otherwise grows the field's list for the next builds."""
+        over = int(self.overflow.item())
+        self.overflow.zero_()
+        if over == 0:
+            return True
+        self.plist.grow_for(max(2 * int(self.plist.cell_stride), int(self.plist.status[1].item())))
+        return False
+
     def _build(self):
+        self._cells, self._list = self.grid.c, self.plist.l
         st = stream_handle(self.device)
         A.md_bin_cells(self.params, self.pos.data_ptr(), self.grid.c, self.ws.ptr, self.ws.nbytes, st)
+        if self.deferred:
+            A.md_build_pairlist(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, self.ws.ptr,
+                                self.ws.nbytes, st)
+            torch.maximum(self.overflow, self.plist.status[2:3], out=self.overflow)
+            return
         for _ in range(4):
             A.md_build_pairlist(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, self.ws.ptr,
                                 self.ws.nbytes, st)
@@ -84,7 +127,7 @@ class Field:
     def energy_forces(self):
         """(U, W, F[N, 3]) at the current positions."""
         F = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
-        A.md_forces(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, F.data_ptr(),
+        A.md_forces(self.params, self.pos.data_ptr(), self._cells, self._list, F.data_ptr(),
                     self.out2.data_ptr(), self.ws.ptr, self.ws.nbytes, stream_handle(self.device))
         pw = self.out2.clone()
         return pw[0], pw[1], F.t()
@@ -93,20 +136,20 @@ class Field:
         """(H u [N, 3], u . dF/d(eps, sigma) [2]) at the current positions."""
         ut = u.detach().to(self.device, torch.float64).t().contiguous()
         Hu = torch.empty_like(ut)
-        A.md_hvp(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, ut.data_ptr(), Hu.data_ptr(),
+        A.md_hvp(self.params, self.pos.data_ptr(), self._cells, self._list, ut.data_ptr(), Hu.data_ptr(),
                  self.out2.data_ptr(), self.ws.ptr, self.ws.nbytes, stream_handle(self.device))
         return Hu.t(), self.out2.clone()
 
     def adjoint_kick(self, u: torch.Tensor, out: torch.Tensor, u_out, coef, acc: torch.Tensor):
         """out = a out + b H u + c F;  acc += cu u.dF/dtheta + cU dU/dtheta;
         u_out = u + dt out (if given).  u, out, u_out: [3, N] float64."""
-        A.md_adjoint_kick(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, u.data_ptr(), out.data_ptr(),
-                          None if u_out is None else u_out.data_ptr(), coef, acc.data_ptr(), self.ws.ptr,
-                          self.ws.nbytes, stream_handle(self.device))
+        A.md_adjoint_kick(self.params, self.pos.data_ptr(), self._cells, self._list, u.data_ptr(),
+                          out.data_ptr(), None if u_out is None else u_out.data_ptr(), coef, acc.data_ptr(),
+                          self.ws.ptr, self.ws.nbytes, stream_handle(self.device))
 
     def param_grad(self):
         """(dU/deps, dU/dsigma) at the current positions."""
-        A.md_param_grad(self.params, self.pos.data_ptr(), self.grid.c, self.plist.l, self.out2.data_ptr(),
+        A.md_param_grad(self.params, self.pos.data_ptr(), self._cells, self._list, self.out2.data_ptr(),
                         self.ws.ptr, self.ws.nbytes, stream_handle(self.device))
         return self.out2.clone()
 
@@ -210,6 +253,10 @@ class TrajectoryMeanPE(torch.autograd.Function):
         # one engine recomputes every segment, reset from each checkpoint
         eng = Engine(np.zeros((n, 3)), np.zeros((n, 3)), cfg["box"], eps=cfg["eps"], sigma=cfg["sigma"],
                      rc=cfg["rc"], rs=cfg["rs"], dt=dt, precision="fp64", resort_every=0, device=dev)
+        # the field's list builds do not wait for their overflow flags: the
+        # flags are read once per segment, and a segment whose list overflowed
+        # is swept again from its saved adjoints with a grown list
+        f.defer_checks(True)
         for si in range(len(ctx.ckpts) - 1, -1, -1):
             qc, vc = ctx.ckpts[si]
             k0 = si * cfg["ckpt"]
@@ -221,38 +268,62 @@ class TrajectoryMeanPE(torch.autograd.Function):
             frame0 = eng.pos.clone()      # state 0 in the library's layout (the prepared positions)
             _, frames, built = eng.step_record(m)
             builds = [0] + [t + 1 for t in range(m) if built[t]]   # states the segment's lists were built at
-            current = None                # state of the field's list
-
-            def place(t):
-                nonlocal current
-                b = max(x for x in builds if x <= t)
-                fb = frame0 if b == 0 else frames[b - 1]
-                if b != current:
-                    f.use_frame(fb)
-                    current = b
-                f.use_frame(frame0 if t == 0 else frames[t - 1], rebuild=False)
-
-            # states k = k0 + t, from the segment's top down to k0 (the top
-            # state k_end was taken by the later segment unless it is q_K)
-            t_top = m if k_end == K else m - 1
-            for t in range(t_top, -1, -1):
-                k = k0 + t
-                place(t)
-                if k == K:
-                    # second kick of the last step and the observable term at q_K,
-                    # with the drift of the velocity adjoint fused in
-                    f.adjoint_kick(av, aq, av_next, (1.0, -h, -w, h, w), acc)
-                    av, av_next = av_next, av
-                elif k > 0:
-                    # the first kick of step k and the second kick of step k - 1
-                    # act at the same q_k with the same velocity adjoint: one
-                    # pass with both (2h), the observable term, and the drift
-                    f.adjoint_kick(av, aq, av_next, (1.0, -2.0 * h, -w, 2.0 * h, w), acc)
-                    av, av_next = av_next, av
-                else:
-                    # first kick of step 0 at q_0
-                    f.adjoint_kick(av, aq, None, (1.0, -h, 0.0, h, 0.0), acc)
+            saved = (aq.clone(), av.clone(), acc.clone())
+            while True:
+                av, av_next = _sweep_segment(f, eng, frame0, frames, builds, aq, av, av_next, acc, k0, m, k_end,
+                                             K, h, w)
+                if f.check_lists():
+                    break
+                aq.copy_(saved[0])
+                av.copy_(saved[1])
+                acc.copy_(saved[2])
             k_end = k0
         ge = acc[0].to(ctx.eps_like) if ctx.eps_like is not None else None
         gs = acc[1].to(ctx.sig_like) if ctx.sig_like is not None else None
         return aq.t(), None, ge, gs, None, None, None, None, None, None
+
+
+def _sweep_segment(f, eng, frame0, frames, builds, aq, av, av_next, acc, k0, m, k_end, K, h, w):
+    """Reverse sweep of one recomputed segment (states k0 .. k0 + m), updating
+    aq and acc in place and av through the two velocity-adjoint buffers;
+    returns (av, av_next), the buffer then holding av first.  The states
+    from the segment's last build on use the recomputing engine's own list
+    (built there, still valid: the engine stands at the segment's end), the
+    earlier ones the field's list built at the same states."""
+    current = None                # build state of the field's own list
+    last = builds[-1]
+
+    def place(t):
+        nonlocal current
+        frame = frame0 if t == 0 else frames[t - 1]
+        b = max(x for x in builds if x <= t)
+        if b == last:
+            f.use_lists_of(eng, frame)
+            return
+        if b != current:
+            f.use_frame(frame0 if b == 0 else frames[b - 1])
+            current = b
+        f.use_frame(frame, rebuild=False)
+
+
+    # states k = k0 + t, from the segment's top down to k0 (the top state
+    # k_end was taken by the later segment unless it is q_K)
+    t_top = m if k_end == K else m - 1
+    for t in range(t_top, -1, -1):
+        k = k0 + t
+        place(t)
+        if k == K:
+            # second kick of the last step and the observable term at q_K,
+            # with the drift of the velocity adjoint fused in
+            f.adjoint_kick(av, aq, av_next, (1.0, -h, -w, h, w), acc)
+            av, av_next = av_next, av
+        elif k > 0:
+            # the first kick of step k and the second kick of step k - 1 act
+            # at the same q_k with the same velocity adjoint: one pass with
+            # both (2h), the observable term, and the drift
+            f.adjoint_kick(av, aq, av_next, (1.0, -2.0 * h, -w, 2.0 * h, w), acc)
+            av, av_next = av_next, av
+        else:
+            # first kick of step 0 at q_0
+            f.adjoint_kick(av, aq, None, (1.0, -h, 0.0, h, 0.0), acc)
+    return av, av_next

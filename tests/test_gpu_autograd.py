@@ -6,7 +6,8 @@
   * LJEnergy: central finite differences (h = 1e-6) of U along a random
     direction and in eps, sigma;
   * TrajectoryMeanPE: O and its gradients equal the oracle's checkpointed
-    reverse sweep on a 500-particle system (1e-8 relative);
+    reverse sweep on a 500-particle system (1e-8 relative), also when the
+    sweep's list overflows and a segment is swept again;
   * TrajectoryMeanPE at the full differentiable workload (N = 256,000, 200
     steps, checkpoints every 20, dt = 0.005): central finite differences with
     h = 1e-6 along a random direction in q0 and in eps, sigma.
@@ -91,6 +92,35 @@ def test_trajectory_gradient_matches_oracle(ref):
     O.backward()
     Or, gqr, gpr = ref.traj_mean_pe_grad(q, v, L, K, ckpt=ck)
     assert O.item() == pytest.approx(Or, rel=1e-12)
+    gq = qt.grad.cpu().numpy()
+    assert np.abs(gq - gqr).max() <= 1e-8 * np.abs(gqr).max()
+    assert eps.grad.item() == pytest.approx(gpr[0], rel=1e-8)
+    assert sig.grad.item() == pytest.approx(gpr[1], rel=1e-8)
+
+
+def test_trajectory_gradient_redoes_a_segment_whose_list_overflowed(ref, monkeypatch):
+    # the reverse sweep reads its lists' overflow flags once per segment; a
+    # field list made too small from the start overflows, the segment is swept
+    # again from its saved adjoints with a grown list, and the gradients are
+    # those of the oracle
+    from paper_1012_2677_amd import TrajectoryMeanPE, autograd
+
+    made = []
+
+    class TinyList(autograd.PairList):
+        def __init__(self, params, ncell, device, cell_stride=None, entry_bits=32):
+            super().__init__(params, ncell, device, 8, entry_bits)
+            made.append(self)
+
+    monkeypatch.setattr(autograd, "PairList", TinyList)
+    q, L = li.fcc_lattice(5)
+    v = li.maxwell_boltzmann(q.shape[0], seed=44)
+    K, ck = 30, 10
+    qt, eps, sig = _t(q, True), _t(1.0, True), _t(1.0, True)
+    O = TrajectoryMeanPE.apply(qt, _t(v), eps, sig, L, K, ck)
+    O.backward()
+    assert made and made[0].cell_stride > 8      # the field's list grew
+    Or, gqr, gpr = ref.traj_mean_pe_grad(q, v, L, K, ckpt=ck)
     gq = qt.grad.cpu().numpy()
     assert np.abs(gq - gqr).max() <= 1e-8 * np.abs(gqr).max()
     assert eps.grad.item() == pytest.approx(gpr[0], rel=1e-8)
