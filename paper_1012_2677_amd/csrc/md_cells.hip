@@ -202,12 +202,88 @@ __global__ __launch_bounds__(kStreamBlock) void k_sort_cells(int64_t ncell, cons
     }
 }
 
+// ---- the same for small systems in one block --------------------------------
+// Label, count (LDS atomics), exclusive scan, place and per-cell sort in one
+// launch of one block: the same count, start, cell_of, cell_xyz and (sorted)
+// order as the kernels above, without their seven launches, which dominate
+// a rebuild of a few thousand particles.
+constexpr int kBinSmallThreads = 1024;
+constexpr int64_t kBinSmallN = 65536;
+constexpr int64_t kBinSmallCells = 4096;
+
+__global__ __launch_bounds__(kBinSmallThreads) void k_bin_small(Geo g, const double4* __restrict__ pos,
+                                                                int32_t* __restrict__ cell_of,
+                                                                int32_t* __restrict__ cell_xyz,
+                                                                int32_t* __restrict__ count,
+                                                                int32_t* __restrict__ start,
+                                                                int32_t* __restrict__ order,
+                                                                int32_t* __restrict__ rank,
+                                                                int64_t* __restrict__ err)
+{
+    __shared__ int32_t s_cnt[kBinSmallCells];
+    __shared__ int32_t s_wave[kBinSmallThreads / 64];
+    const int tid = threadIdx.x;
+    const int nc = (int)g.ncell;
+    const int n = (int)g.n;
+    for (int c = tid; c < nc; c += kBinSmallThreads) s_cnt[c] = 0;
+    __syncthreads();
+    bool outside = false;
+    for (int i = tid; i < n; i += kBinSmallThreads) {
+        const double4 p = pos[i];
+        outside |= !(p.x >= 0.0 && p.x < g.L[0] && p.y >= 0.0 && p.y < g.L[1] && p.z >= 0.0 && p.z < g.L[2]);
+        const int cx = cell_coord(p.x, g.inv[0], g.nc[0]);
+        const int cy = cell_coord(p.y, g.inv[1], g.nc[1]);
+        const int cz = cell_coord(p.z, g.inv[2], g.nc[2]);
+        const int32_t c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
+        cell_of[i] = c;
+        cell_xyz[i] = cx | (cy << 10) | (cz << 20);
+        rank[i] = atomicAdd(&s_cnt[c], 1);
+    }
+    if (outside) atomicOr((unsigned long long*)err, 2ull);
+    __syncthreads();
+    // exclusive scan of the counts: each thread takes a contiguous run of
+    // cells, then a scan of the runs' totals over the block
+    const int per = (nc + kBinSmallThreads - 1) / kBinSmallThreads;
+    const int c0 = min(tid * per, nc), c1 = min(c0 + per, nc);
+    int32_t run = 0;
+    for (int c = c0; c < c1; ++c) run += s_cnt[c];
+    const int lane = tid & 63, wave = tid >> 6;
+    int32_t x = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    int32_t base = x - run;
+    for (int w2 = 0; w2 < wave; ++w2) base += s_wave[w2];
+    __syncthreads();
+    for (int c = c0; c < c1; ++c) {
+        const int32_t v = s_cnt[c];
+        count[c] = v;
+        start[c] = base;
+        s_cnt[c] = base;
+        base += v;
+    }
+    if (tid == 0) start[nc] = n;
+    __syncthreads();
+    for (int i = tid; i < n; i += kBinSmallThreads) order[s_cnt[cell_of[i]] + rank[i]] = i;
+    __syncthreads();
+    for (int c = tid; c < nc; c += kBinSmallThreads) insertion_sort(order + start[c], count[c]);
+}
+
 hipError_t launch_bin(const Geo& g, const double* pos, const md_cells& cells, void* ws,
                       const WsLayout& L, int64_t* err_flags, hipStream_t s)
 {
     char* w = (char*)ws;
     int32_t* rank = (int32_t*)(w + L.rank);
     int32_t* bsum = (int32_t*)(w + L.bsum);
+    if (g.n <= kBinSmallN && g.ncell <= kBinSmallCells) {
+        hipLaunchKernelGGL(k_bin_small, dim3(1), dim3(kBinSmallThreads), 0, s, g, (const double4*)pos,
+                           cells.cell_of, cells.cell_xyz, cells.count, cells.start, cells.order, rank, err_flags);
+        return hipGetLastError();
+    }
     hipError_t e = launch_fill_i32(cells.count, 0, g.ncell, s);
     if (e != hipSuccess) return e;
     const unsigned nbn = (unsigned)ceil_div(g.n, kStreamBlock);
