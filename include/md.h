@@ -72,6 +72,12 @@ extern "C" {
 
 #define MD_STEP_RUN_MAX 64       /* most steps md_step queues per host wait (md_params.step_run) */
 
+/* waves of the tiled list build (md_params.build_waves) */
+#define MD_BUILD_AUTO       0   /* a wave per tile from MD_BUILD_TILE_MIN tiles on, else a wave per cell */
+#define MD_BUILD_CELL_WAVES 1   /* a wave per cell; the cells of a tile reserve their rows by atomics   */
+#define MD_BUILD_TILE_WAVES 2   /* a wave per tile, building its cells one after another along z        */
+#define MD_BUILD_TILE_MIN   32768
+
 /* Model and run parameters.
  *   V(r) = 4 eps [ (sigma/r)^12 - (sigma/r)^6 + c2 (r/sigma)^2 + c0 ] for r < rc,
  *   with c2, c0 fixed by V(rc) = V'(rc) = 0 (Sec. 2.1, eq. lj_cutoff); rc and rs
@@ -113,7 +119,12 @@ extern "C" {
  *   queues before it waits for the device (0 = automatic: the steps the list
  *   is expected to last, from its age and the growth of the largest
  *   displacement, plus one, at most MD_STEP_RUN_MAX; 1 = a wait after every
- *   step).  The results do not depend on it. */
+ *   step).  The results do not depend on it.
+ *   build_waves: how the build of a tiled list spreads its work (MD_BUILD_*).
+ *   The rows are the same either way; only the order of the cells' rows
+ *   inside their tile's block differs (cell order with a wave per tile, the
+ *   order in which the cells finish with a wave per cell), so forces and
+ *   runs do not depend on it. */
 typedef struct md_params {
     int64_t n;
     double  box[3];
@@ -127,6 +138,7 @@ typedef struct md_params {
     int32_t list_layout;   /* MD_LIST_AUTO, MD_LIST_SLOTS or MD_LIST_HALF */
     int32_t tile_cells;    /* 0 = automatic, else 1 .. 1023 */
     int32_t step_run;      /* 0 = automatic, else 1 .. MD_STEP_RUN_MAX steps per wait */
+    int32_t build_waves;   /* MD_BUILD_AUTO, MD_BUILD_CELL_WAVES or MD_BUILD_TILE_WAVES */
 } md_params;
 
 /* Cell grid (Sec. 2.2): GridParticleNumber = count, GridPointer = start,

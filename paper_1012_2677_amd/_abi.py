@@ -32,6 +32,8 @@ MD_LIST_HALF = 2
 MD_REBUILD_HALF_SKIN = 0
 MD_REBUILD_DUTC_LDC = 1
 MD_STEP_RUN_MAX = 64
+MD_BUILD_AUTO, MD_BUILD_CELL_WAVES, MD_BUILD_TILE_WAVES = 0, 1, 2
+MD_BUILD_TILE_MIN = 32768
 
 MD_T_FORCE, MD_T_INTEGRATE, MD_T_BIN, MD_T_RESORT, MD_T_BUILD, MD_T_REDUCE, MD_T_CHECK, MD_T_COUNT = range(8)
 TIMER_NAMES = ["force", "integrate", "bin", "resort", "build", "reduce", "check"]
@@ -54,7 +56,8 @@ class MdParams(C.Structure):
     _fields_ = [("n", C.c_int64), ("box", C.c_double * 3), ("eps", C.c_double), ("sigma", C.c_double),
                 ("rc", C.c_double), ("rs", C.c_double), ("dt", C.c_double), ("precision", C.c_int32),
                 ("resort_every", C.c_int32), ("rebuild_rule", C.c_int32), ("ldc_max", C.c_int32),
-                ("list_layout", C.c_int32), ("tile_cells", C.c_int32), ("step_run", C.c_int32)]
+                ("list_layout", C.c_int32), ("tile_cells", C.c_int32), ("step_run", C.c_int32),
+                ("build_waves", C.c_int32)]
 
 
 class MdCells(C.Structure):

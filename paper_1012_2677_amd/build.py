@@ -22,6 +22,12 @@ LIB = os.path.join(HERE, "libmd355.so")
 SOURCES = ["md_api.hip", "md_cells.hip", "md_pairlist.hip", "md_forces.hip", "md_integrate.hip", "md_validity.hip",
            "md_adjoint.hip", "md_probe.hip"]
 ARCH = "gfx950"
+# Per-source flags.  The list build keeps loop-invariant constants and lane
+# addresses out of registers when machine-level loop-invariant code motion is
+# off: the wave that builds a tile's cells one after another otherwise holds
+# them live across its cell loop (72 instead of 82 registers, 7 waves per SIMD
+# instead of 5, and the shorter build measured).
+EXTRA_FLAGS = {"md_pairlist.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
 def hipcc() -> str:
@@ -39,7 +45,7 @@ def common_flags():
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), "-c", os.path.join(CSRC, src), "-o", obj] + common_flags()
+    cmd = [hipcc(), "-c", os.path.join(CSRC, src), "-o", obj] + common_flags() + EXTRA_FLAGS.get(src, [])
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -55,6 +55,8 @@ static int check_params(const md_params* p, int32_t nc[3])
     if (p->tile_cells < 0 || p->tile_cells > 1023) return fail(MD_ERR_ARG, "tile_cells must be in [0, 1023]");
     if (p->step_run < 0 || p->step_run > MD_STEP_RUN_MAX)
         return fail(MD_ERR_ARG, "step_run must be in [0, %d]", MD_STEP_RUN_MAX);
+    if (p->build_waves < MD_BUILD_AUTO || p->build_waves > MD_BUILD_TILE_WAVES)
+        return fail(MD_ERR_ARG, "build_waves must be 0, 1 or 2");
     for (int k = 0; k < 3; ++k) {
         const double m = std::floor(p->box[k] / p->rs);
         if (m < 3.0) return fail(MD_ERR_BOX, "axis %d has %.0f cells (< 3): box too small for rs", k, m);
@@ -364,7 +366,7 @@ int md_build_pairlist(const md_params* p, const double* pos, const md_cells* cel
     if ((rc = check_list(c, list)) != MD_OK) return rc;
     if ((rc = check_ws(c, ws, ws_bytes)) != MD_OK) return rc;
     const bool half = p->list_layout == MD_LIST_HALF;
-    MD_HIP(launch_build(c.g, p->rs, pos, *cells, *list, ws, c.W, false, half, nullptr, stream),
+    MD_HIP(launch_build(c.g, p->rs, pos, *cells, *list, ws, c.W, false, half, nullptr, MD_BUILD_AUTO, stream),
            "md_build_pairlist");
     list->tiled = 0;
     list->half = half ? 1 : 0;
@@ -574,7 +576,7 @@ static int build_list(const Ctx& c, const md_params* p, md_state* st, bool tiled
     tick(T, MD_T_BUILD, 0, s);
     const bool half = p->list_layout == MD_LIST_HALF;
     MD_HIP(launch_build(c.g, p->rs, st->pos, st->cells, st->list, st->ws, c.W, tiled, half,
-                        (unsigned long long*)tmax, s),
+                        (unsigned long long*)tmax, p->build_waves, s),
            "rebuild/build");
     tick(T, MD_T_BUILD, 1, s);
     st->list_tiled = tiled ? 1 : 0;

@@ -304,10 +304,11 @@ hipError_t launch_ref_copy(const Geo& g, const double* pos, const int32_t* cell_
 // tiled: write 16-bit entries that index the staged copy of the key's tile
 // (slots must be in cell order); the largest staged count of any tile goes to
 // tile_max[0 .. kTileMaxSlots) (atomic max into slot tile % kTileMaxSlots, so
-// that the atomics do not all meet at one address).
+// that the atomics do not all meet at one address).  waves: MD_BUILD_* (tiled
+// builds only).
 hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cells& cells,
                         const md_pairlist& list, void* ws, const WsLayout& L, bool tiled, bool half,
-                        unsigned long long* tile_max, hipStream_t s);
+                        unsigned long long* tile_max, int waves, hipStream_t s);
 
 // md_forces.hip
 struct ForceOut {

@@ -43,6 +43,8 @@ struct BuildArgs {
     FastDiv div_tc;                   // tiled: division by tc
     int32_t nt;                       // tiled: tiles per column
     int32_t* tile_used;               // tiled: entries taken so far in each tile's pooled block
+    int64_t ntile;                    // tiled: tiles in all
+    FastDiv div_nt;                   // tiled: division by nt (tile order decode)
 };
 
 // r^2 of the pinned predicate: d = q_j - q_i, optional minimum image,
@@ -53,8 +55,12 @@ __device__ __forceinline__ double pair_r2(const BuildArgs& a, double xj, double 
 {
     double dx = xj - xi, dy = yj - yi, dz = zj - zi;
     if (MINIMG) {
+        // one component after another (scheduling barriers): interleaved,
+        // their temporaries would set the kernel's register count
         dx = dx - a.L[0] * rint(dx * a.invL[0]);
+        __builtin_amdgcn_sched_barrier(0);
         dy = dy - a.L[1] * rint(dy * a.invL[1]);
+        __builtin_amdgcn_sched_barrier(0);
         dz = dz - a.L[2] * rint(dz * a.invL[2]);
     }
     return __builtin_fma(dz, dz, __builtin_fma(dy, dy, __dmul_rn(dx, dx)));
@@ -133,6 +139,17 @@ __device__ __forceinline__ void pad_row(E* blk, uint32_t stride, uint32_t* s_row
 // then the cells of codes 14 .. 26, so "partner slot > key slot in the own
 // cell" is "candidate number > self_t"; candidates up to self_t are dropped.
 //
+// The key's lane in chunk ch (candidate self_t), formed by the scalar unit:
+// compared with the lane number as it is, the test then needs no per-chunk
+// vector register of lane + 64 ch (which the compiler would otherwise keep for
+// every chunk, live across the key loop).
+__device__ __forceinline__ int scalar_lane_of(int self_t, int ch)
+{
+    int sl = self_t - ch * 64;
+    asm("" : "+s"(sl));
+    return sl;
+}
+
 // Fast form (the key's row surely fits in the LDS row buffer): the row mask is
 // the ballot of the distance test minus the key's own lane; every lane stores,
 // those outside the mask into a spare LDS word, so there is no branch and no
@@ -151,7 +168,8 @@ __device__ __forceinline__ uint32_t row_chunks_lds(const BuildArgs& a, const dou
     for (int ch = 0; ch < NACT; ++ch) {
         const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
         const bool in = r2 < a.rs2;
-        const bool drop = HALF ? lane <= self_t - ch * 64 : lane == self_t - ch * 64;
+        const int sl = scalar_lane_of(self_t, ch);
+        const bool drop = HALF ? lane <= sl : lane == sl;
         const uint64_t m = __builtin_amdgcn_ballot_w64(in) & ~__builtin_amdgcn_ballot_w64(drop);
         const uint32_t wb = (mbcnt64(m) + wpos) << 2;   // byte offset in the row buffer
         *(uint32_t*)((char*)s_rows + (__builtin_amdgcn_inverse_ballot_w64(m) ? wb : 4u * kRowBuf)) = meta[ch];
@@ -235,22 +253,48 @@ __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* b
 // rows.  The order of the slices inside a pool follows the order in which the
 // cells finish.  A cell whose rows outgrow the LDS buffer counts the rest,
 // takes its slice, and computes those rows again straight into it.
-constexpr int kRowBuf16 = 2 * kRowBuf;   // 16-bit entries of one tiled cell staged in LDS (the row buffer)
 
-template <bool MINIMG, int NACT>
-__device__ __forceinline__ uint32_t tiled_row_lds(const BuildArgs& a, const double4& kp, int self_t, uint32_t w0,
-                                                  const double* cx, const double* cy, const double* cz,
+// 16-bit entries of one tiled cell staged in LDS (the row buffer, which first
+// holds the candidate table): with the smaller register set of candidates,
+// sized so that the block's LDS stays within 5 KB (32 blocks, 8 waves per SIMD)
+template <int NCH>
+constexpr int tiled_rowbuf_words()
+{
+    return NCH <= kBuildChunksSmall ? 608 : kRowBuf;
+}
+template <int NCH>
+constexpr int rowbuf16()
+{
+    return 2 * tiled_rowbuf_words<NCH>();
+}
+
+// A cell's slice of its tile's pool: one atomic add on the tile's counter when
+// every cell has a wave of its own; when one wave builds the tile's cells one
+// after another (SEQ), the slices follow in cell order and the wave keeps the
+// running offset itself.
+template <bool SEQ>
+__device__ __forceinline__ uint32_t reserve_slice(int lane, int32_t* tile_used, uint32_t seq_base, uint32_t used)
+{
+    if (SEQ) return seq_base;
+    uint32_t base = 0;
+    if (lane == 0) base = (uint32_t)atomicAdd(tile_used, (int32_t)used);
+    return __builtin_amdgcn_readfirstlane(base);
+}
+
+template <bool MINIMG, int NACT, int NCH>
+__device__ __forceinline__ uint32_t tiled_row_lds(const BuildArgs& a, int lane, const double4& kp, int self_t,
+                                                  uint32_t w0, const double* cx, const double* cy, const double* cz,
                                                   const uint32_t* meta, uint16_t* s_rows16)
 {
-    const int lane = (int)lane_id();
     uint32_t wpos = w0;
 #pragma unroll
     for (int ch = 0; ch < NACT; ++ch) {
         const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
         const bool in = r2 < a.rs2;
-        const uint64_t m = __builtin_amdgcn_ballot_w64(in) & ~__builtin_amdgcn_ballot_w64(lane == self_t - ch * 64);
+        const uint64_t m =
+            __builtin_amdgcn_ballot_w64(in) & ~__builtin_amdgcn_ballot_w64(lane == scalar_lane_of(self_t, ch));
         const uint32_t wb = (mbcnt64(m) + wpos) << 1;   // byte offset in the row buffer
-        *(uint16_t*)((char*)s_rows16 + (__builtin_amdgcn_inverse_ballot_w64(m) ? wb : 2u * kRowBuf16)) =
+        *(uint16_t*)((char*)s_rows16 + (__builtin_amdgcn_inverse_ballot_w64(m) ? wb : 2u * rowbuf16<NCH>())) =
             (uint16_t)meta[ch];
         wpos += (uint32_t)__popcll(m);
     }
@@ -259,11 +303,10 @@ __device__ __forceinline__ uint32_t tiled_row_lds(const BuildArgs& a, const doub
 
 // the same row, counted only (STORE = false) or written to dst[w0 ..]
 template <bool MINIMG, int NACT, bool STORE>
-__device__ __forceinline__ uint32_t tiled_row_direct(const BuildArgs& a, const double4& kp, int self_t, uint32_t w0,
-                                                     const double* cx, const double* cy, const double* cz,
-                                                     const uint32_t* meta, uint16_t* dst)
+__device__ __forceinline__ uint32_t tiled_row_direct(const BuildArgs& a, int lane, const double4& kp, int self_t,
+                                                     uint32_t w0, const double* cx, const double* cy,
+                                                     const double* cz, const uint32_t* meta, uint16_t* dst)
 {
-    const int lane = (int)lane_id();
     uint32_t wpos = w0;
 #pragma unroll
     for (int ch = 0; ch < NACT; ++ch) {
@@ -278,20 +321,19 @@ __device__ __forceinline__ uint32_t tiled_row_direct(const BuildArgs& a, const d
 
 // One tiled cell: rows, its slice of the tile's pool and the row headers.
 // Returns the entries the cell takes (even).
-template <bool MINIMG, int NACT>
-__device__ __forceinline__ uint32_t tiled_rows_from_registers(const BuildArgs& a, uint16_t* tblk, uint64_t tcap,
-                                                             int32_t* tile_used, int T, int own_pref, int own_cnt,
-                                                             const double4* s_key, const double* cx,
-                                                             const double* cy, const double* cz,
+template <bool MINIMG, int NACT, int NCH, bool SEQ>
+__device__ __forceinline__ uint32_t tiled_rows_from_registers(const BuildArgs& a, int lane, uint16_t* tblk,
+                                                             uint64_t tcap, int32_t* tile_used, uint32_t seq_base,
+                                                             int T, int own_pref, int own_cnt, const double4* s_key,
+                                                             const double* cx, const double* cy, const double* cz,
                                                              const uint32_t* meta, uint16_t* s_rows16,
                                                              uint32_t* s_rowend, uint32_t pad)
 {
-    const int lane = (int)lane_id();
     uint32_t used = 0;
     int kk = 0;
     // rows staged while they surely fit: a row adds at most T - 1 entries
-    for (; kk < own_cnt && used + (uint32_t)T <= (uint32_t)kRowBuf16; ++kk) {
-        used = tiled_row_lds<MINIMG, NACT>(a, s_key[kk], own_pref + kk, used, cx, cy, cz, meta, s_rows16);
+    for (; kk < own_cnt && used + (uint32_t)T <= (uint32_t)rowbuf16<NCH>(); ++kk) {
+        used = tiled_row_lds<MINIMG, NACT, NCH>(a, lane, s_key[kk], own_pref + kk, used, cx, cy, cz, meta, s_rows16);
         if (lane == 0) {
             s_rowend[kk] = used;
             if (used & 1u) s_rows16[used] = (uint16_t)pad;
@@ -302,13 +344,11 @@ __device__ __forceinline__ uint32_t tiled_rows_from_registers(const BuildArgs& a
     const uint32_t staged = used;
     // the rest counted, then computed again into the slice below
     for (int k2 = ks; k2 < own_cnt; ++k2) {
-        used = tiled_row_direct<MINIMG, NACT, false>(a, s_key[k2], own_pref + k2, used, cx, cy, cz, meta, nullptr);
+        used = tiled_row_direct<MINIMG, NACT, false>(a, lane, s_key[k2], own_pref + k2, used, cx, cy, cz, meta, nullptr);
         if (lane == 0) s_rowend[k2] = used;
         used = (used + 1u) & ~1u;
     }
-    uint32_t base = 0;
-    if (lane == 0) base = (uint32_t)atomicAdd(tile_used, (int32_t)used);
-    base = __builtin_amdgcn_readfirstlane(base);
+    const uint32_t base = reserve_slice<SEQ>(lane, tile_used, seq_base, used);
     const bool fits = (uint64_t)base + used <= tcap;
     if (!fits && lane == 0) atomicOr((unsigned long long*)&a.status[2], 1ull);
     __syncthreads();
@@ -320,7 +360,7 @@ __device__ __forceinline__ uint32_t tiled_rows_from_registers(const BuildArgs& a
         for (uint32_t t = lane; 2 * t < staged; t += 64) dst2[t] = src2[t];
         uint32_t w = staged;
         for (int k2 = ks; k2 < own_cnt; ++k2) {
-            w = tiled_row_direct<MINIMG, NACT, true>(a, s_key[k2], own_pref + k2, w, cx, cy, cz, meta, dst);
+            w = tiled_row_direct<MINIMG, NACT, true>(a, lane, s_key[k2], own_pref + k2, w, cx, cy, cz, meta, dst);
             if (lane == 0 && (w & 1u)) dst[w] = (uint16_t)pad;
             w = (w + 1u) & ~1u;
         }
@@ -335,19 +375,20 @@ __device__ __forceinline__ uint32_t tiled_rows_from_registers(const BuildArgs& a
     return used;
 }
 
-template <bool MINIMG, int NCH>
-__device__ __forceinline__ uint32_t tiled_rows_for_chunks(int nact, const BuildArgs& a, uint16_t* tblk, uint64_t tcap,
-                                                         int32_t* tile_used, int T, int own_pref, int own_cnt,
-                                                         const double4* s_key, const double* cx, const double* cy,
-                                                         const double* cz, const uint32_t* meta, uint16_t* s_rows16,
-                                                         uint32_t* s_rowend, uint32_t pad)
+template <bool MINIMG, int NCH, bool SEQ>
+__device__ __forceinline__ uint32_t tiled_rows_for_chunks(int nact, const BuildArgs& a, int lane, uint16_t* tblk,
+                                                         uint64_t tcap, int32_t* tile_used, uint32_t seq_base, int T,
+                                                         int own_pref, int own_cnt, const double4* s_key,
+                                                         const double* cx, const double* cy, const double* cz,
+                                                         const uint32_t* meta, uint16_t* s_rows16, uint32_t* s_rowend,
+                                                         uint32_t pad)
 {
     static_assert(NCH >= 2 && NCH <= 8, "one case per chunk count");
 #define MD_TROWS_CASE(N)                                                                                              \
     case N:                                                                                                           \
         if constexpr (N < NCH)                                                                                        \
-            return tiled_rows_from_registers<MINIMG, N>(a, tblk, tcap, tile_used, T, own_pref, own_cnt, s_key, cx, cy, \
-                                                        cz, meta, s_rows16, s_rowend, pad);                           \
+            return tiled_rows_from_registers<MINIMG, N, NCH, SEQ>(a, lane, tblk, tcap, tile_used, seq_base, T, own_pref,  \
+                                                             own_cnt, s_key, cx, cy, cz, meta, s_rows16, s_rowend, pad); \
         break;
     switch (nact) {
         MD_TROWS_CASE(1)
@@ -361,8 +402,8 @@ __device__ __forceinline__ uint32_t tiled_rows_for_chunks(int nact, const BuildA
             break;
     }
 #undef MD_TROWS_CASE
-    return tiled_rows_from_registers<MINIMG, NCH>(a, tblk, tcap, tile_used, T, own_pref, own_cnt, s_key, cx, cy, cz,
-                                                  meta, s_rows16, s_rowend, pad);
+    return tiled_rows_from_registers<MINIMG, NCH, NCH, SEQ>(a, lane, tblk, tcap, tile_used, seq_base, T, own_pref, own_cnt, s_key,
+                                                       cx, cy, cz, meta, s_rows16, s_rowend, pad);
 }
 
 // The key loop for the cell's chunk count nact in [1, NCH].
@@ -440,28 +481,65 @@ __device__ uint32_t rows_from_memory(const BuildArgs& a, E* blk, uint32_t stride
     return used;
 }
 
-template <int NCH, bool TILED, bool HALF>
-__global__ __launch_bounds__(64) void k_build(BuildArgs a)
+// What a tiled build takes from the cell's tile: its z range, the pooled block
+// of its list (the first cell's block and the blocks after it) and, for lane
+// q < 27 (neighbour cell q, in column q / 3 of the tile's 3 x 3 columns), the
+// two offsets that turn the start of that neighbour cell into the staged index
+// of its first particle in the tile's neighbourhood: the staged layout is the 9
+// column runs one after another (exclusive prefix of the run lengths), and a
+// run that wraps around the box has a second segment.
+struct TileCtx {
+    int z0 = 0, z1 = 0, jw = 0;
+    int offA = 0, offB = 0;
+    uint32_t pad = 0;            // the stand-in partner of the force pass (staged total << 4)
+    uint32_t total = 0;          // staged particles of the tile's neighbourhood
+    uint16_t* tblk = nullptr;
+    uint64_t tcap = 0;
+    int32_t* tused = nullptr;    // entries taken so far in the tile's pool
+    int64_t tile = 0;
+};
+
+// Lanes 0..8 hold the run of column `lane` as tile_run_load gives it.
+__device__ __forceinline__ TileCtx tile_ctx(const BuildArgs& a, int cx, int cy, int tz, int z0, int z1,
+                                            const TileRun& run)
+{
+    const int lane = (int)lane_id();
+    TileCtx t;
+    t.z0 = z0;
+    t.z1 = z1;
+    t.jw = tile_jw(z0, z1, a.nc[2]);
+    const int len = lane < 9 ? run.lenA + run.lenB : 0;
+    const int inc = scan_row16(len);
+    t.total = (uint32_t)__builtin_amdgcn_readlane(inc, 8);
+    const int col = lane < 27 ? lane / 3 : 0;
+    const int cbase = __shfl(inc - len, col, 64);
+    const int sA = __shfl(run.sA, col, 64), lenA = __shfl(run.lenA, col, 64), sB = __shfl(run.sB, col, 64);
+    t.offA = cbase - sA;
+    t.offB = cbase + lenA - sB;
+    t.pad = t.total << 4;
+    const int64_t colc = (int64_t)cx * a.nc[1] + cy;
+    t.tblk = (uint16_t*)a.nbr + (colc * a.nc[2] + z0) * a.stride;
+    t.tcap = (uint64_t)(z1 - z0) * (uint64_t)a.stride;
+    t.tile = colc * a.nt + tz;
+    t.tused = a.tile_used + t.tile;
+    return t;
+}
+
+// The rows of one cell (cx, cy, cz), from the starts and counts of its 27
+// neighbour cells (lane q < 27 holds those of cell q; half rows use q >= 13
+// only).  Tiled: the cell's slice of the tile's pool is reserved by an atomic
+// add or, SEQ, starts at seq_base.  Returns the entries the cell takes.
+template <int NCH, bool TILED, bool HALF, bool SEQ>
+__device__ __forceinline__ uint32_t build_cell(const BuildArgs& a, int cx, int cy, int cz, int st_l, int cnt_l,
+                                               const TileCtx& tx, uint32_t seq_base)
 {
     using E = typename std::conditional<TILED, uint16_t, uint32_t>::type;
-    const int64_t tb = xcd_remap(blockIdx.x, gridDim.x);
-    if (tb >= a.ncell) return;
-    const int lane = (int)threadIdx.x;
+    int lane = (int)lane_id();
+    // opaque to the compiler when a wave builds several cells: the per-lane
+    // addresses below are then formed per cell instead of being hoisted out of
+    // the cell loop into registers that stay live across it
+    if (SEQ) asm volatile("" : "+v"(lane));
     const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
-    // cells in strips of kBuildStrip x-columns walked along y (a column's
-    // cells consecutive), so that cells built close in time share their
-    // neighbour cells in L2 (cell ids < 2^31: 32-bit arithmetic, divisions by
-    // the launch's multiply-shift divisors)
-    const uint32_t t = (uint32_t)tb;
-    const uint32_t seq = fdiv(t, a.div_nz);
-    const int cz = (int)(t - seq * (uint32_t)nz);
-    const uint32_t strip = fdiv(seq, a.div_strip);
-    const uint32_t in = seq - strip * (uint32_t)(kBuildStrip * ny);
-    const int sw = min(kBuildStrip, nx - (int)strip * kBuildStrip);
-    uint32_t cyu;
-    if (sw == kBuildStrip) cyu = in / (uint32_t)kBuildStrip;   // a power of two
-    else cyu = in / (uint32_t)sw;                              // the last, narrower strip
-    const int cy = (int)cyu, cx = (int)(strip * kBuildStrip + (in - cyu * (uint32_t)sw));
     const int64_t c = ((int64_t)cx * ny + cy) * nz + cz;
 
     __shared__ int s_nstart[27];
@@ -469,30 +547,11 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     __shared__ double4 s_key[kMaxOwn];
     // rows of the cell's keys before the block is written (+ a spare word for
     // lanes that store nothing); before that, the candidate table
-    __shared__ __align__(8) uint32_t s_rows[kRowBuf + 2];
+    constexpr int kRows = TILED ? tiled_rowbuf_words<NCH>() : kRowBuf;
+    __shared__ __align__(8) uint32_t s_rows[kRows + 2];
     __shared__ uint32_t s_rowend[kMaxOwn];
     __shared__ int s_lbase[27];
-    __shared__ uint32_t s_pad;
-    // Every lane issues its loads before any result is used (a wait inside a
-    // branch would serialise them): the neighbour cell of lanes 0..26, and,
-    // tiled, the cells at the ends of the tile's column runs (lanes 0..8);
-    // lanes without one load cell 0.  Half rows take candidates from the own
-    // cell (code 13) and codes 14 .. 26 only: the other 13 cells count as empty.
-    const int tz = TILED ? (int)fdiv((uint32_t)cz, a.div_tc) : 0;   // the cell's tile along z
-    const int z0 = tz * a.tc, z1 = TILED ? min(z0 + a.tc, nz) : 0;
     const bool has_nb = lane < 27 && (!HALF || lane >= 13);
-    int nb = 0;
-    if (lane < 27) {
-        const int ax = wrap_cell(cx + lane / 9 - 1, nx), ay = wrap_cell(cy + (lane / 3) % 3 - 1, ny);
-        const int az = wrap_cell(cz + lane % 3 - 1, nz);
-        nb = has_nb ? (ax * ny + ay) * nz + az : 0;
-    }
-    TileCells tcl;
-    if (TILED) tcl = tile_run_cells(wrap_cell(cx + lane / 3 - 1, nx), wrap_cell(cy + lane % 3 - 1, ny), ny, nz, z0, z1,
-                                    lane < 9);
-    const int st_l = a.start[nb], cnt_l = a.count[nb];
-    TileRun run = {0, 0, 0, 0};
-    if (TILED) run = tile_run_load(a.start, a.count, tcl);
     const int st = has_nb ? st_l : 0, cnt = has_nb ? cnt_l : 0;
     const int incl = scan_lanes32(cnt);
     if (lane < 27) {
@@ -501,35 +560,15 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     }
     if (lane == 0) s_pref[0] = 0;
     int lb = 0;   // tiled: staged index of the first particle of this lane's cell
-    if (TILED) {
-        // the tile's staged layout: the bases of the 9 column runs (exclusive
-        // prefix of the run lengths), then the staged index of
-        // the first particle of each neighbour cell q (lanes 0..26; q / 3 is
-        // the column of q)
-        const int jw = tile_jw(z0, z1, nz);
-        const int len = lane < 9 ? run.lenA + run.lenB : 0;
-        const int inc = scan_row16(len);
-        const int total = __shfl(inc, 8, 64);
-        const int col = lane < 27 ? lane / 3 : 0;
-        const int cbase = __shfl(inc - len, col, 64);
-        const int sA = __shfl(run.sA, col, 64), lenA = __shfl(run.lenA, col, 64), sB = __shfl(run.sB, col, 64);
-        if (lane < 27) {
-            const int j = cz + lane % 3 - 1 - z0 + 1;
-            lb = cbase + (j < jw ? st - sA : lenA + st - sB);
-            s_lbase[lane] = lb;
-        }
-        if (lane == 0) {
-            s_pad = (uint32_t)total << 4;   // the stand-in partner of the force pass
-            if (cz == z0) {
-                const int64_t tile = ((int64_t)cx * ny + cy) * a.nt + tz;
-                atomicMax(a.tile_max + (tile & (kTileMaxSlots - 1)), (unsigned long long)total);
-            }
-        }
+    if (TILED && lane < 27) {
+        const int j = cz + lane % 3 - tx.z0;   // place of the neighbour cell in its column run
+        lb = st + (j < tx.jw ? tx.offA : tx.offB);
+        s_lbase[lane] = lb;
     }
     __syncthreads();
 
     const int T = s_pref[27];
-    const uint32_t pad = TILED ? s_pad : 0u;
+    const uint32_t pad = TILED ? tx.pad : 0u;
     const int own_pref = s_pref[13];
     const int own_start = s_nstart[13];
     const int own_cnt = s_pref[14] - own_pref;
@@ -539,24 +578,13 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     // capped so that byte offsets (entries << 2) fit in 32 bits
     const uint32_t stride = (uint32_t)(a.stride < (1 << 29) ? a.stride : (1 << 29));
     uint32_t used = 0;
-    // tiled: the pooled block of the tile (its first cell's block and the
-    // blocks after it) and the tile's count of entries taken
-    uint16_t* tblk = nullptr;
-    uint64_t tcap = 0;
-    int32_t* tused = nullptr;
-    if (TILED) {
-        const int64_t colc = (int64_t)cx * ny + cy;
-        tblk = (uint16_t*)a.nbr + (colc * nz + z0) * a.stride;
-        tcap = (uint64_t)(z1 - z0) * (uint64_t)a.stride;
-        tused = a.tile_used + colc * a.nt + tz;
-    }
 
     if (own_cnt > 0 && T <= NCH * 64 && own_cnt <= kMaxOwn) {
         // candidate table: for entry t, the candidate's position in the cell
         // order and (16 bits) its staged index in the tile's neighbourhood
         // (tiled) or its stencil code, written by the lane of its cell; it
         // lives in the row buffer, which is free until the rows are made
-        static_assert(NCH * 64 * (sizeof(uint32_t) + sizeof(uint16_t)) <= sizeof(uint32_t) * (kRowBuf + 2),
+        static_assert(NCH * 64 * (sizeof(uint32_t) + sizeof(uint16_t)) <= sizeof(uint32_t) * (kRows + 2),
                       "table fits the row buffer");
         uint32_t* s_tpos = s_rows;
         uint16_t* s_tcode = reinterpret_cast<uint16_t*>(s_rows + NCH * 64);
@@ -594,10 +622,12 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
         const int nact = (T + 63) >> 6;
         if constexpr (TILED) {
             uint16_t* s_rows16 = reinterpret_cast<uint16_t*>(s_rows);
-            used = minimg ? tiled_rows_for_chunks<true, NCH>(nact, a, tblk, tcap, tused, T, own_pref, own_cnt, s_key,
-                                                             px, py, pz, meta, s_rows16, s_rowend, pad)
-                          : tiled_rows_for_chunks<false, NCH>(nact, a, tblk, tcap, tused, T, own_pref, own_cnt,
-                                                              s_key, px, py, pz, meta, s_rows16, s_rowend, pad);
+            used = minimg ? tiled_rows_for_chunks<true, NCH, SEQ>(nact, a, lane, tx.tblk, tx.tcap, tx.tused, seq_base, T,
+                                                                  own_pref, own_cnt, s_key, px, py, pz, meta,
+                                                                  s_rows16, s_rowend, pad)
+                          : tiled_rows_for_chunks<false, NCH, SEQ>(nact, a, lane, tx.tblk, tx.tcap, tx.tused, seq_base, T,
+                                                                   own_pref, own_cnt, s_key, px, py, pz, meta,
+                                                                   s_rows16, s_rowend, pad);
         } else {
             used = minimg ? rows_for_chunks<true, NCH, E, HALF>(nact, a, blk, stride, T, own_pref, own_cnt, s_key,
                                                                 px, py, pz, meta, s_rows, s_rowend, pad)
@@ -612,13 +642,11 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
                                                                 s_nstart, s_lbase, pad)
                        : rows_from_memory<false, E, false, true>(a, nullptr, 0, T, own_start, own_cnt, s_pref,
                                                                  s_nstart, s_lbase, pad);
-            uint32_t base = 0;
-            if (lane == 0) base = (uint32_t)atomicAdd(tused, (int32_t)total);
-            base = __builtin_amdgcn_readfirstlane(base);
-            const bool fits = (uint64_t)base + total <= tcap;
+            const uint32_t base = reserve_slice<SEQ>(lane, tx.tused, seq_base, total);
+            const bool fits = (uint64_t)base + total <= tx.tcap;
             if (!fits && lane == 0) atomicOr((unsigned long long*)&a.status[2], 1ull);
             // an overflowed cell writes empty rows (capacity 0)
-            E* cblk = (E*)(fits ? tblk + base : tblk);
+            E* cblk = (E*)(fits ? tx.tblk + base : tx.tblk);
             const uint32_t cap = fits ? total : 0u;
             if (minimg)
                 rows_from_memory<true, E, false>(a, cblk, cap, T, own_start, own_cnt, s_pref, s_nstart, s_lbase, pad);
@@ -635,6 +663,85 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     if (lane == 0) {
         a.cell_rows[c] = used > 0x7FFFFFFFu ? 0x7FFFFFFF : (int32_t)used;
         if (!TILED && used > stride) atomicOr((unsigned long long*)&a.status[2], 1ull);
+    }
+    return used;
+}
+
+// One wave per cell, or (SEQ, tiled lists of large grids) one wave per tile
+// that builds the tile's cells one after another along z: the cells' slices
+// of the tile's pool then follow in cell order with no atomic, the tile's runs
+// and staged layout are worked out once, and the next cell's neighbour starts
+// and counts load while a cell is built.
+template <int NCH, bool TILED, bool HALF, bool SEQ>
+__global__ __launch_bounds__(64) void k_build(BuildArgs a)
+{
+    static_assert(!SEQ || (TILED && !HALF), "tile-sequential builds write tiled full rows");
+    const int64_t tb = xcd_remap(blockIdx.x, gridDim.x);
+    if (tb >= (SEQ ? a.ntile : a.ncell)) return;
+    const int lane = (int)threadIdx.x;
+    const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
+    // cells (tiles) in strips of kBuildStrip x-columns walked along y (a
+    // column's cells consecutive), so that cells built close in time share
+    // their neighbour cells in L2 (ids < 2^31: 32-bit arithmetic, divisions
+    // by the launch's multiply-shift divisors)
+    const uint32_t t = (uint32_t)tb;
+    const uint32_t seq = fdiv(t, SEQ ? a.div_nt : a.div_nz);
+    const int zi = (int)(t - seq * (uint32_t)(SEQ ? a.nt : nz));   // the tile along z (SEQ), else the cell's z
+    const uint32_t strip = fdiv(seq, a.div_strip);
+    const uint32_t in = seq - strip * (uint32_t)(kBuildStrip * ny);
+    const int sw = min(kBuildStrip, nx - (int)strip * kBuildStrip);
+    uint32_t cyu;
+    if (sw == kBuildStrip) cyu = in / (uint32_t)kBuildStrip;   // a power of two
+    else cyu = in / (uint32_t)sw;                              // the last, narrower strip
+    const int cy = (int)cyu, cx = (int)(strip * kBuildStrip + (in - cyu * (uint32_t)sw));
+
+    // Every lane issues its loads before any result is used (a wait inside a
+    // branch would serialise them): the neighbour cell of lanes 0..26, and,
+    // tiled, the cells at the ends of the tile's column runs (lanes 0..8);
+    // lanes without one load cell 0.  Half rows take candidates from the own
+    // cell (code 13) and codes 14 .. 26 only: the other 13 cells count as empty.
+    const bool has_nb = lane < 27 && (!HALF || lane >= 13);
+    int colb = 0;   // first cell of the neighbour column of lane q < 27
+    if (lane < 27) {
+        const int ax = wrap_cell(cx + lane / 9 - 1, nx), ay = wrap_cell(cy + (lane / 3) % 3 - 1, ny);
+        colb = (ax * ny + ay) * nz;
+    }
+    const int dz = lane % 3 - 1;
+    const int tz = SEQ ? zi : (TILED ? (int)fdiv((uint32_t)zi, a.div_tc) : 0);
+    const int z0 = tz * a.tc, z1 = TILED ? min(z0 + a.tc, nz) : 0;
+    const int cz0 = SEQ ? z0 : zi;   // the (first) cell built
+    const int nb = has_nb ? colb + wrap_cell(cz0 + dz, nz) : 0;
+    TileCells tcl;
+    if (TILED) tcl = tile_run_cells(wrap_cell(cx + lane / 3 - 1, nx), wrap_cell(cy + lane % 3 - 1, ny), ny, nz, z0, z1,
+                                    lane < 9);
+    int st_l = a.start[nb], cnt_l = a.count[nb];
+    TileRun run = {0, 0, 0, 0};
+    if (TILED) run = tile_run_load(a.start, a.count, tcl);
+    TileCtx tx;
+    if (TILED) {
+        tx = tile_ctx(a, cx, cy, tz, z0, z1, run);
+        if (lane == 0 && cz0 == z0)
+            atomicMax(a.tile_max + (tx.tile & (kTileMaxSlots - 1)), (unsigned long long)tx.total);
+    }
+    if constexpr (!SEQ) {
+        build_cell<NCH, TILED, HALF, false>(a, cx, cy, cz0, st_l, cnt_l, tx, 0u);
+    } else {
+        uint32_t off = 0;
+        for (int cz = z0; cz < z1; ++cz) {
+            // the next cell's neighbour starts and counts, loaded while this
+            // cell is built
+            int st_n = 0, cnt_n = 0;
+            if (cz + 1 < z1) {
+                const int nbn = has_nb ? colb + wrap_cell(cz + 1 + dz, nz) : 0;
+                st_n = a.start[nbn];
+                cnt_n = a.count[nbn];
+            }
+            off += build_cell<NCH, true, false, true>(a, cx, cy, cz, st_l, cnt_l, tx, off);
+            st_l = st_n;
+            cnt_l = cnt_n;
+            __syncthreads();
+        }
+        if (lane == 0) tx.tused[0] = (int32_t)off;
     }
 }
 
@@ -673,7 +780,7 @@ __global__ __launch_bounds__(256) void k_tile_need_final(const int32_t* __restri
 
 hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cells& cells,
                         const md_pairlist& list, void* ws, const WsLayout& L, bool tiled, bool half,
-                        unsigned long long* tile_max, hipStream_t s)
+                        unsigned long long* tile_max, int waves, hipStream_t s)
 {
     int32_t* tile_used = (int32_t*)((char*)ws + L.tile_used);
     BuildArgs a;
@@ -702,13 +809,19 @@ hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cel
     a.div_tc = make_fastdiv((uint32_t)(g.tc > 0 ? g.tc : 1));
     a.nt = g.nt;
     a.tile_used = tile_used;
+    a.ntile = g.ntile;
+    a.div_nt = make_fastdiv((uint32_t)(g.nt > 0 ? g.nt : 1));
     if (tiled && (half || !cells.sorted || g.tc <= 0 || !tile_max)) return hipErrorInvalidValue;
+    // one wave per tile where the tiles alone fill the GPU several times over
+    // (below that, the cells' own waves keep more of it busy)
+    const bool seq =
+        tiled && (waves == MD_BUILD_TILE_WAVES || (waves == MD_BUILD_AUTO && g.ntile >= MD_BUILD_TILE_MIN));
     // status[2] (overflow) is cleared by the statistics kernel of the previous
     // build or by the caller; clear it here on the stream before the build.
     hipError_t e = launch_fill_i32((int32_t*)list.status, 0, 8, s);
     if (e != hipSuccess) return e;
-    if (tiled && (e = launch_fill_i32(tile_used, 0, g.ntile, s)) != hipSuccess) return e;
-    const dim3 grid((unsigned)g.ncell);
+    if (tiled && !seq && (e = launch_fill_i32(tile_used, 0, g.ntile, s)) != hipSuccess) return e;
+    const dim3 grid((unsigned)(seq ? g.ntile : g.ncell));
     // candidates held in registers: 6 chunks of 64 (fewer registers, more
     // waves per SIMD) when a neighbourhood that large is far in the tail at
     // the mean density (4 standard deviations of a Poisson count above the
@@ -716,15 +829,18 @@ hipError_t launch_build(const Geo& g, double rs, const double* pos, const md_cel
     // memory for every key
     const double mean_t = (half ? 14.0 : 27.0) * (double)g.n / (double)g.ncell;
     const bool small = mean_t + 4.0 * std::sqrt(mean_t) <= (double)(kBuildChunksSmall * 64);
-    if (tiled) {
-        if (small) hipLaunchKernelGGL((k_build<kBuildChunksSmall, true, false>), grid, dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_build<kBuildChunks, true, false>), grid, dim3(64), 0, s, a);
+    if (seq) {
+        if (small) hipLaunchKernelGGL((k_build<kBuildChunksSmall, true, false, true>), grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_build<kBuildChunks, true, false, true>), grid, dim3(64), 0, s, a);
+    } else if (tiled) {
+        if (small) hipLaunchKernelGGL((k_build<kBuildChunksSmall, true, false, false>), grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_build<kBuildChunks, true, false, false>), grid, dim3(64), 0, s, a);
     } else if (half) {
-        if (small) hipLaunchKernelGGL((k_build<kBuildChunksSmall, false, true>), grid, dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_build<kBuildChunks, false, true>), grid, dim3(64), 0, s, a);
+        if (small) hipLaunchKernelGGL((k_build<kBuildChunksSmall, false, true, false>), grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_build<kBuildChunks, false, true, false>), grid, dim3(64), 0, s, a);
     } else {
-        if (small) hipLaunchKernelGGL((k_build<kBuildChunksSmall, false, false>), grid, dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_build<kBuildChunks, false, false>), grid, dim3(64), 0, s, a);
+        if (small) hipLaunchKernelGGL((k_build<kBuildChunksSmall, false, false, false>), grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_build<kBuildChunks, false, false, false>), grid, dim3(64), 0, s, a);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -25,9 +25,12 @@ REBUILD_RULES = {"half_skin": A.MD_REBUILD_HALF_SKIN, "dutc_ldc": A.MD_REBUILD_D
 LIST_LAYOUTS = {"auto": A.MD_LIST_AUTO, "slots": A.MD_LIST_SLOTS, "half": A.MD_LIST_HALF}
 
 
+BUILD_WAVES = {"auto": A.MD_BUILD_AUTO, "cell": A.MD_BUILD_CELL_WAVES, "tile": A.MD_BUILD_TILE_WAVES}
+
+
 def make_params(n, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precision="fp64",
                 resort_every=1, rebuild_rule="half_skin", ldc_max=8192, list_layout="auto",
-                tile_cells=0, step_run=0) -> A.MdParams:
+                tile_cells=0, step_run=0, build_waves="auto") -> A.MdParams:
     p = A.MdParams()
     p.n = int(n)
     b = np.broadcast_to(np.asarray(box, dtype=np.float64), (3,))
@@ -41,6 +44,7 @@ def make_params(n, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precisi
     p.list_layout = LIST_LAYOUTS[list_layout] if isinstance(list_layout, str) else int(list_layout)
     p.tile_cells = int(tile_cells)
     p.step_run = int(step_run)
+    p.build_waves = BUILD_WAVES[build_waves] if isinstance(build_waves, str) else int(build_waves)
     return p
 
 
@@ -163,12 +167,14 @@ class Engine:
     the partner's force added by device atomics, the integrator in a pass of
     its own; much slower on this GPU, kept for comparison); tile_cells: tile
     length along z in cells (0 = automatic); step_run: steps queued per wait
-    for the device (0 = automatic, 1 = a wait after every step).
+    for the device (0 = automatic, 1 = a wait after every step); build_waves:
+    "auto", "cell" or "tile" (the tiled list build's waves: one per cell, or
+    one per tile building its cells in turn; the same rows either way).
     """
 
     def __init__(self, pos, vel, box, *, eps=1.0, sigma=1.0, rc=2.5, rs=2.8, dt=0.005, precision="fp64",
                  resort_every=1, rebuild_rule="half_skin", ldc_max=8192, list_layout="auto", tile_cells=0,
-                 step_run=0, device="cuda", cell_stride=None, timers=False):
+                 step_run=0, build_waves="auto", device="cuda", cell_stride=None, timers=False):
         pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64))
         vel = np.ascontiguousarray(np.asarray(vel, dtype=np.float64))
         n = pos.shape[0]
@@ -177,7 +183,8 @@ class Engine:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.params = make_params(n, box, eps=eps, sigma=sigma, rc=rc, rs=rs, dt=dt, precision=precision,
                                   resort_every=resort_every, rebuild_rule=rebuild_rule, ldc_max=ldc_max,
-                                  list_layout=list_layout, tile_cells=tile_cells, step_run=step_run)
+                                  list_layout=list_layout, tile_cells=tile_cells, step_run=step_run,
+                                  build_waves=build_waves)
         self.n = n
         self.mixed = self.params.precision == A.MD_MIXED
         dev = self.device

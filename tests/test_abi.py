@@ -74,7 +74,7 @@ int main() {
   OFF(md_state, cells); OFF(md_state, list); OFF(md_state, energy); OFF(md_state, ws_bytes);
   OFF(md_state, timers); OFF(md_state, step); OFF(md_state, phase); OFF(md_state, list_valid);
   OFF(md_params, list_layout); OFF(md_params, tile_cells); OFF(md_state, list_tiled); OFF(md_state, tile_stage);
-  OFF(md_state, tile_cells); OFF(md_params, step_run);
+  OFF(md_state, tile_cells); OFF(md_params, step_run); OFF(md_params, build_waves);
   return 0;
 }
 """
@@ -121,13 +121,14 @@ def test_cell_dims_and_workspace(A):
     (dict(n=0), -1), (dict(n=1 << 27), -1), (dict(L=8.0), -2), (dict(L=3000.0), -2),
     (dict(rc=3.0, rs=2.8), -1), (dict(eps=-1.0), -1), (dict(precision=7), -1),
     (dict(list_layout=3), -1), (dict(tile_cells=-1), -1), (dict(tile_cells=1024), -1),
-    (dict(step_run=-1), -1), (dict(step_run=65), -1),
+    (dict(step_run=-1), -1), (dict(step_run=65), -1), (dict(build_waves=-1), -1), (dict(build_waves=3), -1),
 ])
 def test_validation_codes(A, kw, code):
-    p = _params(A, **{k: v for k, v in kw.items() if k not in ("precision", "list_layout", "tile_cells", "step_run")})
+    fields = ("list_layout", "tile_cells", "step_run", "build_waves")
+    p = _params(A, **{k: v for k, v in kw.items() if k != "precision" and k not in fields})
     if kw.get("precision") == 7:
         p.precision = 7
-    for f in ("list_layout", "tile_cells", "step_run"):
+    for f in fields:
         if f in kw:
             setattr(p, f, kw[f])
     with pytest.raises(A.MdError) as e:

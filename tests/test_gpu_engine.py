@@ -228,22 +228,24 @@ def _close_logs(log, rlog, precision, n):
     return np.abs(log[:, 1] - rlog[:, 1]).max() / n < 1e-5 and np.abs(log[:, 3] - rlog[:, 3]).max() / n < 1e-5
 
 
+@pytest.mark.parametrize("waves", ["cell", "tile"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_capacity_overflow_resumes(ref, precision):
+def test_capacity_overflow_resumes(ref, precision, waves):
     q, L = li.fcc_lattice(10)
     v = li.maxwell_boltzmann(q.shape[0], seed=0)
-    e = _engine(q, v, L, cell_stride=64, precision=precision)
+    e = _engine(q, v, L, cell_stride=64, precision=precision, build_waves=waves)
     log = e.step(30, sample_every=10)
     assert e.plist.cell_stride > 64
     _, _, rlog, _ = ref.run(q, v, L, 30, sample_every=10)
     assert _close_logs(log, rlog, precision, q.shape[0])
 
 
+@pytest.mark.parametrize("waves", ["cell", "tile"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_overflow_mid_run_resumes(ref, precision):
+def test_overflow_mid_run_resumes(ref, precision, waves):
     q, L = li.fcc_lattice(10)
     v = li.maxwell_boltzmann(q.shape[0], seed=5)
-    e = _engine(q, v, L, precision=precision)
+    e = _engine(q, v, L, precision=precision, build_waves=waves)
     e.prepare()
     need = int(e.plist.status[1].item())
     # shrink the list to the lattice's exact need: a later rebuild of the

@@ -66,12 +66,14 @@ def test_layout_selection():
         assert int(f.state.list_tiled) == 0, kw
 
 
+@pytest.mark.parametrize("waves", ["cell", "tile"])
 @pytest.mark.parametrize("precision,tile_cells", [("mixed", 0), ("mixed", 1), ("mixed", 2), ("mixed", 3),
                                                   ("fp64", 0), ("fp64", 4)])
-def test_tiled_rows_equal_slot_rows_and_oracle(ref, precision, tile_cells):
+def test_tiled_rows_equal_slot_rows_and_oracle(ref, precision, tile_cells, waves):
+    # both ways of spreading the build (a wave per cell, a wave per tile)
     q, L = _jittered(10, seed=11)
     v = li.maxwell_boltzmann(q.shape[0], seed=11)
-    t = _engine(q, v, L, precision=precision, tile_cells=tile_cells)
+    t = _engine(q, v, L, precision=precision, tile_cells=tile_cells, build_waves=waves)
     s = _engine(q, v, L, precision=precision, list_layout="slots")
     t.prepare()
     s.prepare()
@@ -214,9 +216,10 @@ def test_standalone_force_pass_refuses_a_tiled_state_list(precision):
         assert np.abs(got - want).max() <= tol * np.abs(want).max()
 
 
+@pytest.mark.parametrize("waves", ["cell", "tile"])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 @pytest.mark.parametrize("name", ["clump", "dense", "slab"])
-def test_tiled_rows_in_crowded_or_empty_cells(ref, precision, name):
+def test_tiled_rows_in_crowded_or_empty_cells(ref, precision, name, waves):
     # cells beyond the build's LDS key buffer and neighbourhoods beyond its
     # register chunks (the tiled rows come from the path that re-reads the
     # candidates), or empty cells and tiles without keys: rows must still
@@ -225,7 +228,7 @@ def test_tiled_rows_in_crowded_or_empty_cells(ref, precision, name):
 
     q, L = _case(name)
     v = np.zeros_like(q)
-    t = _engine(q, v, L, precision=precision)
+    t = _engine(q, v, L, precision=precision, build_waves=waves)
     s = _engine(q, v, L, precision=precision, list_layout="slots")
     t.prepare()
     s.prepare()
