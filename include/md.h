@@ -109,7 +109,7 @@ extern "C" {
  *   Newton's third law), in md_build_pairlist as well as in the state: the
  *   row of key i holds the partners in its own cell with a larger slot, then
  *   those in the 13 neighbour cells of stencil codes 14 .. 26, in the order
- *   of a full row (code, then slot).  The force passes add each pair's force
+ *   of a full row (own cell, then codes 14 .. 26; slots ascending).  The force passes add each pair's force
  *   to the key in registers and to the partner with a device atomic, so the
  *   rounding of a force sum depends on the order of the atomics; in a
  *   simulation state the integrator then runs as a pass of its own.
@@ -167,8 +167,9 @@ typedef struct md_cells {
  * directions): the row of key slot i is nbr[offsets[i] .. offsets[i]+counts[i]).
  * Each entry is (partner slot) | (stencil code << 27), where the stencil code
  * (sx+1)*9 + (sy+1)*3 + (sz+1) names the neighbour cell of the partner relative
- * to the key's cell at build time (s in {-1,0,1}^3).  Rows list partners in
- * stencil-code order, then ascending slot.  Rows of the keys of cell c live in
+ * to the key's cell at build time (s in {-1,0,1}^3).  Rows list the partners
+ * cell by cell, the key's own cell (code 13) first, then codes 14 .. 26 and
+ * 0 .. 12, each cell's partners in ascending slot.  Rows of the keys of cell c live in
  * the block nbr[c*cell_stride .. (c+1)*cell_stride).
  *   offsets   device int64[n]
  *   counts    device int32[n]

@@ -6,8 +6,9 @@
 // walks the keys of its own cell: each lane tests its candidates against the
 // key with the exact FP64 predicate, a ballot gives the passing lanes, and the
 // prefix popcount below each lane gives its output position, so every row is
-// written compactly in candidate order (stencil code, then ascending slot)
-// with no atomics.  Rows of one cell are packed one after another into the
+// written compactly in candidate order (the key's own cell first, then the
+// neighbour cells of stencil codes 14 .. 26 and 0 .. 12, each in ascending
+// slot) with no atomics.  Rows of one cell are packed one after another into the
 // cell's block of the list; the block base is the cell id times a fixed stride,
 // so cells never have to wait for each other.
 //
@@ -98,7 +99,13 @@ __device__ __forceinline__ void write_row(const BuildArgs& a, int32_t kslot, int
     a.counts[kslot] = (int32_t)(wpos < room ? wpos : room);
 }
 
-constexpr int kMaxOwn = 64;     // own-cell particles kept in LDS for the key loop
+constexpr int kMaxOwn = 64;     // own-cell particles kept in LDS for the key loop (all in the first chunk)
+
+// The neighbour cells in candidate order: rank 0 is the own cell (stencil code
+// 13), ranks 1 .. 13 codes 14 .. 26, ranks 14 .. 26 codes 0 .. 12, so that the
+// candidates of a half row (own cell, codes 14 .. 26) are the first 14 ranks.
+// Code (sx+1)*9 + (sy+1)*3 + (sz+1) for the offsets s in {-1, 0, 1}^3.
+__device__ __forceinline__ int code_of_rank(int r) { return r < 14 ? r + 13 : r - 14; }
 #ifndef MD_BUILD_STRIP
 #define MD_BUILD_STRIP 8
 #endif
@@ -131,31 +138,22 @@ __device__ __forceinline__ void pad_row(E* blk, uint32_t stride, uint32_t* s_row
 // (the cell's neighbourhood rounded up; the key loop is instantiated per
 // chunk count, so the unrolled chunk sequence carries no branch).  Empty
 // candidate slots carry a NaN x coordinate, so r2 < rs2 fails for them in
-// both the plain and the minimum-image form of the test.  The key itself is
-// candidate number self_t.  Output positions come from mbcnt of the row mask,
-// counted on from the row's start.
+// both the plain and the minimum-image form of the test.  The own cell's
+// particles come first among the candidates, so the key itself is candidate
+// self_t < 64 of the first chunk, and only that chunk needs the test that
+// drops it.  Output positions come from mbcnt of the row mask, counted on from
+// the row's start.
 //
-// Half rows (HALF): the candidates are the own cell first (ascending slots),
-// then the cells of codes 14 .. 26, so "partner slot > key slot in the own
-// cell" is "candidate number > self_t"; candidates up to self_t are dropped.
+// Half rows (HALF): the candidates are the own cell (ascending slots), then
+// the cells of codes 14 .. 26, so "partner slot > key slot in the own cell" is
+// "candidate number > self_t"; candidates up to self_t are dropped.
 //
-// The key's lane in chunk ch (candidate self_t), formed by the scalar unit:
-// compared with the lane number as it is, the test then needs no per-chunk
-// vector register of lane + 64 ch (which the compiler would otherwise keep for
-// every chunk, live across the key loop).
-__device__ __forceinline__ int scalar_lane_of(int self_t, int ch)
-{
-    int sl = self_t - ch * 64;
-    asm("" : "+s"(sl));
-    return sl;
-}
-
 // Fast form (the key's row surely fits in the LDS row buffer): the row mask is
-// the ballot of the distance test minus the key's own lane; every lane stores,
-// those outside the mask into a spare LDS word, so there is no branch and no
-// exec-mask change per chunk.  The drop test is one vector compare of the
-// lane against the key's place in the chunk (a scalar mask built from that
-// place would cost several scalar instructions per chunk, and the scalar unit
+// the ballot of the distance test (minus the key's own lane in the first
+// chunk); every lane stores, those outside the mask into a spare LDS word, so
+// there is no branch and no exec-mask change per chunk.  The drop test is one
+// vector compare of the lane against the key's place (a scalar mask built
+// from that place would cost several scalar instructions, and the scalar unit
 // is as busy as the vector unit here).
 template <bool MINIMG, int NACT, bool HALF>
 __device__ __forceinline__ uint32_t row_chunks_lds(const BuildArgs& a, const double4& kp, int self_t,
@@ -168,9 +166,8 @@ __device__ __forceinline__ uint32_t row_chunks_lds(const BuildArgs& a, const dou
     for (int ch = 0; ch < NACT; ++ch) {
         const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
         const bool in = r2 < a.rs2;
-        const int sl = scalar_lane_of(self_t, ch);
-        const bool drop = HALF ? lane <= sl : lane == sl;
-        const uint64_t m = __builtin_amdgcn_ballot_w64(in) & ~__builtin_amdgcn_ballot_w64(drop);
+        uint64_t m = __builtin_amdgcn_ballot_w64(in);
+        if (ch == 0) m &= ~__builtin_amdgcn_ballot_w64(HALF ? lane <= self_t : lane == self_t);
         const uint32_t wb = (mbcnt64(m) + wpos) << 2;   // byte offset in the row buffer
         *(uint32_t*)((char*)s_rows + (__builtin_amdgcn_inverse_ballot_w64(m) ? wb : 4u * kRowBuf)) = meta[ch];
         wpos += (uint32_t)__popcll(m);
@@ -190,12 +187,11 @@ __device__ __forceinline__ uint32_t row_chunks(const BuildArgs& a, E* blk, uint3
 #pragma unroll
     for (int ch = 0; ch < NACT; ++ch) {
         const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
-        const bool in = r2 < a.rs2;
-        const int sl = self_t - ch * 64;          // the key's own lane in this chunk, if any
-        const bool drop = HALF ? lane <= sl : lane == sl;
-        const uint64_t m = __builtin_amdgcn_ballot_w64(in) & ~__builtin_amdgcn_ballot_w64(drop);
+        const bool drop = ch == 0 && (HALF ? lane <= self_t : lane == self_t);
+        const bool in = r2 < a.rs2 && !drop;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(in);
         const uint32_t w = mbcnt64(m) + wpos;
-        if (in && !drop) {
+        if (in) {
             if (w < (uint32_t)kRowBuf) s_rows[w] = meta[ch];
             else if (w < stride) blk[w] = (E)meta[ch];
         }
@@ -291,8 +287,8 @@ __device__ __forceinline__ uint32_t tiled_row_lds(const BuildArgs& a, int lane, 
     for (int ch = 0; ch < NACT; ++ch) {
         const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
         const bool in = r2 < a.rs2;
-        const uint64_t m =
-            __builtin_amdgcn_ballot_w64(in) & ~__builtin_amdgcn_ballot_w64(lane == scalar_lane_of(self_t, ch));
+        uint64_t m = __builtin_amdgcn_ballot_w64(in);
+        if (ch == 0) m &= ~__builtin_amdgcn_ballot_w64(lane == self_t);
         const uint32_t wb = (mbcnt64(m) + wpos) << 1;   // byte offset in the row buffer
         *(uint16_t*)((char*)s_rows16 + (__builtin_amdgcn_inverse_ballot_w64(m) ? wb : 2u * rowbuf16<NCH>())) =
             (uint16_t)meta[ch];
@@ -311,7 +307,7 @@ __device__ __forceinline__ uint32_t tiled_row_direct(const BuildArgs& a, int lan
 #pragma unroll
     for (int ch = 0; ch < NACT; ++ch) {
         const double r2 = pair_r2<MINIMG>(a, cx[ch], cy[ch], cz[ch], kp.x, kp.y, kp.z);
-        const bool in = r2 < a.rs2 && lane != self_t - ch * 64;
+        const bool in = r2 < a.rs2 && (ch != 0 || lane != self_t);
         const uint64_t m = __builtin_amdgcn_ballot_w64(in);
         if (STORE && in) dst[mbcnt64(m) + wpos] = (uint16_t)meta[ch];
         wpos += (uint32_t)__popcll(m);
@@ -463,9 +459,10 @@ __device__ uint32_t rows_from_memory(const BuildArgs& a, E* blk, uint32_t stride
                 const int32_t slot = a.order ? a.order[idx] : idx;
                 const double4 p = a.pos[slot];
                 const double r2 = pair_r2<MINIMG>(a, p.x, p.y, p.z, kp.x, kp.y, kp.z);
-                pass = r2 < a.rs2 && (HALF ? (q > 13 || slot > kslot) : slot != kslot);
+                // q ranks the neighbour cells (rank 0 the own cell)
+                pass = r2 < a.rs2 && (HALF ? (q > 0 || slot > kslot) : slot != kslot);
                 meta = s_lbase ? (uint32_t)(s_lbase[q] + (t - s_pref[q])) << 4
-                               : (uint32_t)slot | ((uint32_t)q << kCodeShift);
+                               : (uint32_t)slot | ((uint32_t)code_of_rank(q) << kCodeShift);
             }
             const uint64_t m = __ballot(pass);
             const uint32_t w = used + wpos + mbcnt64(m);
@@ -511,7 +508,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const BuildArgs& a, int cx, int cy, 
     const int len = lane < 9 ? run.lenA + run.lenB : 0;
     const int inc = scan_row16(len);
     t.total = (uint32_t)__builtin_amdgcn_readlane(inc, 8);
-    const int col = lane < 27 ? lane / 3 : 0;
+    const int col = lane < 27 ? code_of_rank(lane) / 3 : 0;
     const int cbase = __shfl(inc - len, col, 64);
     const int sA = __shfl(run.sA, col, 64), lenA = __shfl(run.lenA, col, 64), sB = __shfl(run.sB, col, 64);
     t.offA = cbase - sA;
@@ -551,7 +548,7 @@ __device__ __forceinline__ uint32_t build_cell(const BuildArgs& a, int cx, int c
     __shared__ __align__(8) uint32_t s_rows[kRows + 2];
     __shared__ uint32_t s_rowend[kMaxOwn];
     __shared__ int s_lbase[27];
-    const bool has_nb = lane < 27 && (!HALF || lane >= 13);
+    const bool has_nb = lane < 27 && (!HALF || lane <= 13);
     const int st = has_nb ? st_l : 0, cnt = has_nb ? cnt_l : 0;
     const int incl = scan_lanes32(cnt);
     if (lane < 27) {
@@ -561,7 +558,7 @@ __device__ __forceinline__ uint32_t build_cell(const BuildArgs& a, int cx, int c
     if (lane == 0) s_pref[0] = 0;
     int lb = 0;   // tiled: staged index of the first particle of this lane's cell
     if (TILED && lane < 27) {
-        const int j = cz + lane % 3 - tx.z0;   // place of the neighbour cell in its column run
+        const int j = cz + code_of_rank(lane) % 3 - tx.z0;   // place of the neighbour cell in its column run
         lb = st + (j < tx.jw ? tx.offA : tx.offB);
         s_lbase[lane] = lb;
     }
@@ -569,9 +566,9 @@ __device__ __forceinline__ uint32_t build_cell(const BuildArgs& a, int cx, int c
 
     const int T = s_pref[27];
     const uint32_t pad = TILED ? tx.pad : 0u;
-    const int own_pref = s_pref[13];
-    const int own_start = s_nstart[13];
-    const int own_cnt = s_pref[14] - own_pref;
+    const int own_pref = 0;   // the own cell's particles are the first candidates
+    const int own_start = s_nstart[0];
+    const int own_cnt = s_pref[1];
     const bool minimg = a.exact_all || cx == 0 || cx == nx - 1 || cy == 0 || cy == ny - 1 || cz == 0 ||
                         cz == nz - 1;
     E* blk = (E*)a.nbr + c * a.stride;
@@ -588,11 +585,17 @@ __device__ __forceinline__ uint32_t build_cell(const BuildArgs& a, int cx, int c
                       "table fits the row buffer");
         uint32_t* s_tpos = s_rows;
         uint16_t* s_tcode = reinterpret_cast<uint16_t*>(s_rows + NCH * 64);
-        if (lane < 27) {
-            const int t0 = incl - cnt;
-            for (int i = 0; i < cnt; ++i) {
-                s_tpos[t0 + i] = (uint32_t)(st + i);
-                s_tcode[t0 + i] = (uint16_t)(TILED ? lb + i : lane);
+        // two lanes per neighbour cell (lanes q and q + 32 for q < 27), each
+        // writing every other entry of it
+        {
+            const int q = lane & 31;
+            const int t0 = __shfl(incl - cnt, q, 64), stq = __shfl(st, q, 64), cq = __shfl(cnt, q, 64);
+            const int eq = TILED ? __shfl(lb, q, 64) : code_of_rank(q);
+            if (q < 27) {
+                for (int i = lane >> 5; i < cq; i += 2) {
+                    s_tpos[t0 + i] = (uint32_t)(stq + i);
+                    s_tcode[t0 + i] = (uint16_t)(TILED ? eq + i : eq);
+                }
             }
         }
         __syncthreads();
@@ -615,8 +618,7 @@ __device__ __forceinline__ uint32_t build_cell(const BuildArgs& a, int cx, int c
             py[ch] = p.y;
             pz[ch] = p.z;
             meta[ch] = TILED ? ey << 4 : ((uint32_t)slot | (ey << kCodeShift));
-            const int k = tq - own_pref;
-            if (ok && k >= 0 && k < own_cnt) s_key[k] = make_double4(p.x, p.y, p.z, __longlong_as_double((long long)slot));
+            if (ch == 0 && tq < own_cnt) s_key[tq] = make_double4(p.x, p.y, p.z, __longlong_as_double((long long)slot));
         }
         __syncthreads();
         const int nact = (T + 63) >> 6;
@@ -700,13 +702,14 @@ __global__ __launch_bounds__(64) void k_build(BuildArgs a)
     // tiled, the cells at the ends of the tile's column runs (lanes 0..8);
     // lanes without one load cell 0.  Half rows take candidates from the own
     // cell (code 13) and codes 14 .. 26 only: the other 13 cells count as empty.
-    const bool has_nb = lane < 27 && (!HALF || lane >= 13);
-    int colb = 0;   // first cell of the neighbour column of lane q < 27
+    const bool has_nb = lane < 27 && (!HALF || lane <= 13);
+    const int code = code_of_rank(lane);   // lanes 0 .. 26: the neighbour cells in candidate order
+    int colb = 0;                          // first cell of the lane's neighbour column
     if (lane < 27) {
-        const int ax = wrap_cell(cx + lane / 9 - 1, nx), ay = wrap_cell(cy + (lane / 3) % 3 - 1, ny);
+        const int ax = wrap_cell(cx + code / 9 - 1, nx), ay = wrap_cell(cy + (code / 3) % 3 - 1, ny);
         colb = (ax * ny + ay) * nz;
     }
-    const int dz = lane % 3 - 1;
+    const int dz = code % 3 - 1;
     const int tz = SEQ ? zi : (TILED ? (int)fdiv((uint32_t)zi, a.div_tc) : 0);
     const int z0 = tz * a.tc, z1 = TILED ? min(z0 + a.tc, nz) : 0;
     const int cz0 = SEQ ? z0 : zi;   // the (first) cell built

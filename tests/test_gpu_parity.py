@@ -118,9 +118,11 @@ def _check_rows_structure(s, keys, partners, codes, cell_of_slot):
     sx, sy, sz = off(kx, px, nx), off(ky, py, ny), off(kz, pz, nz)
     assert np.all(np.abs(sx) <= 1) and np.all(np.abs(sy) <= 1) and np.all(np.abs(sz) <= 1)
     assert np.array_equal(codes, (sx + 1) * 9 + (sy + 1) * 3 + (sz + 1))
-    # rows ordered by (code, partner slot) -- strictly increasing within a row
+    # rows ordered by neighbour cell -- the key's own cell (code 13) first, then
+    # codes 14 .. 26 and 0 .. 12 -- then partner slot: strictly increasing
+    # within a row
     key_change = np.concatenate([[True], keys[1:] != keys[:-1]])
-    comp = codes * (1 << 32) + partners
+    comp = ((codes - 13) % 27) * (1 << 32) + partners
     inc = np.concatenate([[True], comp[1:] > comp[:-1]])
     assert np.all(inc | key_change)
 
