@@ -150,11 +150,12 @@ __device__ __forceinline__ void pad_row(E* blk, uint32_t stride, uint32_t* s_row
 //
 // Fast form (the key's row surely fits in the LDS row buffer): the row mask is
 // the ballot of the distance test (minus the key's own lane in the first
-// chunk); every lane stores, those outside the mask into a spare LDS word, so
-// there is no branch and no exec-mask change per chunk.  The drop test is one
-// vector compare of the lane against the key's place (a scalar mask built
-// from that place would cost several scalar instructions, and the scalar unit
-// is as busy as the vector unit here).
+// chunk), and the lanes in it store under that mask as the execution mask, at
+// byte offsets formed by one shift-add from mbcnt (the mask moves to the
+// scalar unit, which has room here, while the vector unit, which bounds the
+// build, saves the select of a spare address per chunk).  The drop test is
+// one vector compare of the lane against the key's place (a scalar mask built
+// from that place would cost several scalar instructions).
 template <bool MINIMG, int NACT, bool HALF>
 __device__ __forceinline__ uint32_t row_chunks_lds(const BuildArgs& a, const double4& kp, int self_t,
                                                    uint32_t w0, const double* cx, const double* cy,
@@ -168,8 +169,8 @@ __device__ __forceinline__ uint32_t row_chunks_lds(const BuildArgs& a, const dou
         const bool in = r2 < a.rs2;
         uint64_t m = __builtin_amdgcn_ballot_w64(in);
         if (ch == 0) m &= ~__builtin_amdgcn_ballot_w64(HALF ? lane <= self_t : lane == self_t);
-        const uint32_t wb = (mbcnt64(m) + wpos) << 2;   // byte offset in the row buffer
-        *(uint32_t*)((char*)s_rows + (__builtin_amdgcn_inverse_ballot_w64(m) ? wb : 4u * kRowBuf)) = meta[ch];
+        if (__builtin_amdgcn_inverse_ballot_w64(m))
+            *(uint32_t*)((char*)s_rows + ((mbcnt64(m) << 2) + 4u * wpos)) = meta[ch];
         wpos += (uint32_t)__popcll(m);
     }
     return wpos;
@@ -289,9 +290,8 @@ __device__ __forceinline__ uint32_t tiled_row_lds(const BuildArgs& a, int lane, 
         const bool in = r2 < a.rs2;
         uint64_t m = __builtin_amdgcn_ballot_w64(in);
         if (ch == 0) m &= ~__builtin_amdgcn_ballot_w64(lane == self_t);
-        const uint32_t wb = (mbcnt64(m) + wpos) << 1;   // byte offset in the row buffer
-        *(uint16_t*)((char*)s_rows16 + (__builtin_amdgcn_inverse_ballot_w64(m) ? wb : 2u * rowbuf16<NCH>())) =
-            (uint16_t)meta[ch];
+        if (__builtin_amdgcn_inverse_ballot_w64(m))
+            *(uint16_t*)((char*)s_rows16 + ((mbcnt64(m) << 1) + 2u * wpos)) = (uint16_t)meta[ch];
         wpos += (uint32_t)__popcll(m);
     }
     return wpos;
@@ -542,8 +542,8 @@ __device__ __forceinline__ uint32_t build_cell(const BuildArgs& a, int cx, int c
     __shared__ int s_nstart[27];
     __shared__ int s_pref[28];
     __shared__ double4 s_key[kMaxOwn];
-    // rows of the cell's keys before the block is written (+ a spare word for
-    // lanes that store nothing); before that, the candidate table
+    // rows of the cell's keys before the block is written (and two words of
+    // margin); before that, the candidate table
     constexpr int kRows = TILED ? tiled_rowbuf_words<NCH>() : kRowBuf;
     __shared__ __align__(8) uint32_t s_rows[kRows + 2];
     __shared__ uint32_t s_rowend[kMaxOwn];
