@@ -750,8 +750,8 @@ __global__ __launch_bounds__(kForceBlock) void k_integrate_half(PairArgs a)
 //   displacements take the minimum image in tiles that touch the box
 //   boundary (a no-op for pairs that do not wrap), as in k_pairs_fp64.
 // The tile's keys are split evenly over the waves.  In each 64-key chunk the
-// rows are walked in rounds of 64 / G keys grouped by row length (G lanes per
-// row: 4 in mixed precision, 8 in FP64), the first kPrefetch entries of all G
+// rows are walked in rounds of 64 / G keys grouped by row length (G = 4 lanes
+// per row), the first kPrefetch (mixed) or kPrefetch64 (FP64) entries of all G
 // rounds loaded up front, two per 32-bit load.  Key
 // data reach the round's lanes by shuffles; group sums and the integrator
 // epilogue are those of the other pair kernels.
@@ -763,15 +763,20 @@ constexpr int kTileStrip = MD_TILE_STRIP;       // x-columns per strip of the ti
 #define MD_TILE_PREFETCH 64
 #endif
 constexpr int kPrefetch = MD_TILE_PREFETCH;     // row entries per key loaded up front (multiple of 16)
+#ifndef MD_TILE_PREFETCH_FP64
+#define MD_TILE_PREFETCH_FP64 56
+#endif
+// the same in FP64 (a multiple of 2 x its lanes per row), short enough that the
+// pass stays within 128 registers (4 waves per SIMD); 48 in its energy variant
+constexpr int kPrefetch64 = MD_TILE_PREFETCH_FP64;
 #ifndef MD_TILE_LANES_MIXED
 #define MD_TILE_LANES_MIXED 4
 #endif
 #ifndef MD_TILE_LANES_FP64
-#define MD_TILE_LANES_FP64 8
+#define MD_TILE_LANES_FP64 4
 #endif
 // lanes that walk one row (4 or 8): fewer lanes spread a round's fixed costs
-// (key data, group sums) over more entries per lane; FP64 keeps 8, since with
-// 4 its registers pass 128 and a SIMD holds one wave fewer
+// (key data, group sums) over more entries per lane
 constexpr int kTileLanesMixed = MD_TILE_LANES_MIXED;
 constexpr int kTileLanes64 = MD_TILE_LANES_FP64;
 
@@ -997,9 +1002,9 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     __builtin_amdgcn_wave_barrier();
     // the first kPrefetch entries of the rows each lane walks, two per 32-bit
     // load: lane j of a group takes entries 2j + 2Gu and 2j + 2Gu + 1; all
-    // loads of the chunk go out at once
-    // (48 entries when the drift speed is tracked, to stay within 128 VGPRs)
-    constexpr int PF = VMAX ? 48 : kPrefetch;
+    // loads of the chunk go out at once (48 entries in the energy variants and
+    // when the drift speed is tracked, to stay within 128 VGPRs)
+    constexpr int PF = (VMAX || ENERGY) ? 48 : (MIXED ? kPrefetch : kPrefetch64);
     constexpr int UP = PF / (2 * G);
     const uint32_t dummy2 = dummy | (dummy << 16);
     uint32_t E[G][UP];
