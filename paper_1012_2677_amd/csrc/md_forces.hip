@@ -915,13 +915,13 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         }
     }
     __syncthreads();
+    // G lanes walk each row; a round takes K = 64 / G keys, a chunk of 64
+    // keys G rounds
+    constexpr int G = MIXED ? kTileLanesMixed : kTileLanes64, K = 64 / G;
     const uint32_t dummy = (uint32_t)s_base[9] << 4;   // entry of the stand-in partner
     const int64_t colc = ((int64_t)cx * ny + cy) * nz;
     const int64_t kb = a.start[colc + z0];
     const int64_t kend = (int64_t)a.start[colc + z1 - 1] + a.count[colc + z1 - 1];
-    // G lanes walk each row; a round takes K = 64 / G keys, a chunk of 64
-    // keys G rounds
-    constexpr int G = MIXED ? kTileLanesMixed : kTileLanes64, K = 64 / G;
     const int wave = tid >> 6, lane = tid & 63, sub = lane & (G - 1), grp = lane / G;
     const R rc2 = (R)a.lj.rc2, A = (R)a.lj.A, B = (R)a.lj.B, C8 = (R)a.lj.C8;
     double pe = 0.0, w = 0.0, ke = 0.0, d2 = 0.0, v2 = 0.0;
@@ -958,9 +958,11 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         }
     };
     // the tile's keys split evenly over the waves, in chunks of at most 64
-    // (a multiple of 8): nr rounds per chunk instead of always 8
+    // keys and a whole number of rounds (a multiple of K, so that only a
+    // wave's last chunk has a round with empty key slots): nr rounds per
+    // chunk instead of always G
     const int64_t nk = kend - kb;
-    const int csz_k = nk >= NW * 64 ? 64 : (int)((((nk + NW - 1) / NW) + 7) & ~(int64_t)7);
+    const int csz_k = nk >= NW * 64 ? 64 : (int)((((nk + NW - 1) / NW) + K - 1) / K * K);
     for (int64_t base = kb + wave * csz_k; base < kend; base += NW * csz_k) {
     const int64_t cend = base + csz_k < kend ? base + csz_k : kend;
     const int nr = (int)((cend - base + K - 1) / K);
