@@ -248,3 +248,78 @@ def test_tiled_rows_in_crowded_or_empty_cells(ref, precision, name, waves):
         idx = np.arange(n, dtype=np.int64)
         Fr, S, _, _, _ = ref.forces_sample(t.positions(), L, idx)
         assert G.force_error(t.forces(), Fr, S) <= 1e-12
+
+
+def _radius_pairs(rs=2.8, L=48.0):
+    """Pairs in interior cells whose pinned r^2 lies within three ulp steps of
+    the free coordinate below and above rs^2 (r^2 < rs^2 listed), along x, y, z
+    and a diagonal, each pair at its own anchor more than rs from the others."""
+    from tests.test_oracle_cells import predicate_r2
+
+    rs2 = rs * rs
+    dirs = [((2.77, 0.3, 0.2), 0), ((0.3, 2.77, 0.1), 1), ((0.2, 0.1, 2.78), 2), ((1.6, 1.6, 1.62), 0)]
+    anchors = iter([(x, y, z) for x in (6.0, 14.0, 22.0, 30.0, 38.0) for y in (6.0, 14.0, 22.0, 30.0, 38.0)
+                    for z in (6.0, 14.0, 22.0, 30.0)])
+    q, expect = [], set()
+    for d, free in dirs:
+        a0 = next(anchors)
+        qi = list(a0)
+        qj = [a0[k] + d[k] for k in range(3)]
+        other = sum((qj[k] - qi[k]) ** 2 for k in range(3) if k != free)
+        qj[free] = qi[free] + float(np.sqrt(rs2 - other))
+        # step the free coordinate to the last value with r^2 < rs^2
+        while predicate_r2(qi, qj, L) >= rs2:
+            qj[free] = float(np.nextafter(qj[free], -1e3))
+        while True:
+            nxt = float(np.nextafter(qj[free], 1e3))
+            if predicate_r2(qi, qj[:free] + [nxt] + qj[free + 1:], L) >= rs2:
+                break
+            qj[free] = nxt
+        vals = [qj[free]]
+        for _ in range(2):
+            vals.insert(0, float(np.nextafter(vals[0], -1e3)))
+        for _ in range(3):
+            vals.append(float(np.nextafter(vals[-1], 1e3)))
+        for v in vals:
+            a = list(next(anchors))
+            pi = [a[k] for k in range(3)]
+            pj = [a[k] + (qj[k] - qi[k]) for k in range(3)]
+            # the same offset from another anchor: re-tune the free coordinate's
+            # difference exactly (anchors are integers, so the offsets carry over)
+            pj[free] = a[free] + (v - qi[free])
+            i = len(q)
+            q += [pi, pj]
+            if predicate_r2(pi, pj, L) < rs2:
+                expect.add((i, i + 1))
+    q = np.array(q, dtype=np.float64)
+    for p in range(0, len(q), 2):
+        r2 = [predicate_r2(list(q[p]), list(q[b]), L) for b in range(len(q)) if b not in (p, p + 1)]
+        assert min(r2) > 3.0 * 3.0
+    return q, expect, L
+
+
+@pytest.mark.parametrize("waves", ["cell", "tile"])
+def test_tiled_rows_decide_pairs_at_the_search_radius_bit_exactly(waves):
+    # interior pairs a few ulps of r^2 inside and outside rs^2 (the tiled
+    # build's own code path, with both ways of spreading its waves) must be
+    # decided as the pinned predicate decides them, as the slot rows are
+    from tests.test_oracle_cells import predicate_r2
+
+    q, expect, L = _radius_pairs()
+    n = q.shape[0]
+    rs2 = 2.8 * 2.8
+    near = sum(1 for p in range(0, n, 2) if abs(predicate_r2(list(q[p]), list(q[p + 1]), L) - rs2) < 1e-13)
+    assert len(expect) >= 8 and n - 2 * len(expect) >= 16 and near >= 16
+    for precision in ("fp64", "mixed"):
+        t = _engine(q, np.zeros_like(q), L, precision=precision, build_waves=waves)
+        s = _engine(q, np.zeros_like(q), L, precision=precision, list_layout="slots")
+        t.prepare()
+        s.prepare()
+        assert int(t.state.list_tiled) == 1
+        slots = np.arange(n)
+        kt, pt = G.rows_for_slots_state(t, slots)
+        ks, ps = G.rows_for_slots_state(s, slots)
+        assert np.array_equal(kt, ks) and np.array_equal(pt, ps)
+        ids = t.id.cpu().numpy()
+        got = {(int(min(ids[k], ids[p])), int(max(ids[k], ids[p]))) for k, p in zip(kt, pt)}
+        assert got == expect, precision
