@@ -48,6 +48,7 @@ struct PairArgs {
     const int64_t* offsets;
     const int32_t* counts;
     const uint32_t* nbr;
+    int64_t nbr_entries;       // 16-bit entries the list buffer holds (tiled: bound of the row prefetch)
     int64_t n;
     double L[3], invL[3], cs[3];
     int32_t nc[3];
@@ -1015,11 +1016,21 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         if (r >= nr) break;
         const int ks = s_perm[wave][r * K + grp];
         const int cnt = __shfl(own_cnt, ks, 64);
-        const uint32_t* row2 = (const uint32_t*)((const uint16_t*)a.nbr + __shfl(own_off, ks, 64));
+        const int64_t roff = __shfl(own_off, ks, 64);
+        const uint32_t* row2 = (const uint32_t*)((const uint16_t*)a.nbr + roff);
+        if (__all(roff + PF <= a.nbr_entries)) {
+            // every lane's window of PF entries lies in the buffer: plain loads
+            // at constant offsets (entries past the row are replaced by the
+            // stand-in where they are used)
+            const uint32_t* rp = row2 + sub;
 #pragma unroll
-        for (int u = 0; u < UP; ++u) {
-            const int t = 2 * sub + 2 * G * u;
-            E[r][u] = t < cnt ? row2[t >> 1] : dummy2;
+            for (int u = 0; u < UP; ++u) E[r][u] = rp[G * u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < UP; ++u) {
+                const int t = 2 * sub + 2 * G * u;
+                E[r][u] = t < cnt ? row2[t >> 1] : dummy2;
+            }
         }
     }
     R kfx = 0, kfy = 0, kfz = 0;
@@ -1030,6 +1041,7 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         const int cmax =
             __builtin_amdgcn_readfirstlane(group_max<K>(__shfl(own_cnt, s_perm[wave][r * K + (lane & (K - 1))], 64)));
         const int cnt = __shfl(own_cnt, ks, 64);
+        const int lim = cnt - 2 * sub;   // entries 2 G u + 2 sub + (0, 1) are the row's where 2 G u < lim
         V4 li;
         li.x = __shfl(own.x, ks, 64);
         li.y = __shfl(own.y, ks, 64);
@@ -1039,7 +1051,8 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
             if (2 * G * u < cmax) {
-                const S p0 = nb(E[r][u] & 0xFFFFu), p1 = nb(E[r][u] >> 16);
+                const uint32_t e2 = 2 * G * u < lim ? E[r][u] : dummy2;
+                const S p0 = nb(e2 & 0xFFFFu), p1 = nb(e2 >> 16);
                 pair(p0, li, fx, fy, fz);
                 pair(p1, li, fx, fy, fz);
             }
@@ -1104,6 +1117,7 @@ static PairArgs make_pair_args(const Geo& g, const LJ& lj, const double* pos, co
     a.offsets = list.offsets;
     a.counts = list.counts;
     a.nbr = list.nbr;
+    a.nbr_entries = 2 * list.capacity;
     a.n = g.n;
     for (int k = 0; k < 3; ++k) {
         a.L[k] = g.L[k];
