@@ -1,5 +1,6 @@
 // Pair-list construction (Sec. 2.3 bookkeeping with search length rs; Sec. 2.4
-// key-sorted list), one 64-lane wavefront per cell.
+// key-sorted list), one 64-lane wavefront per cell (or, for the tiled list of
+// a large grid, per tile of cells built one after another).
 //
 // The wave stages the particles of the 27 surrounding cells (~300 at
 // rho = 0.5) in its registers, one candidate per lane per 64-chunk.  It then
@@ -10,7 +11,8 @@
 // neighbour cells of stencil codes 14 .. 26 and 0 .. 12, each in ascending
 // slot) with no atomics.  Rows of one cell are packed one after another into the
 // cell's block of the list; the block base is the cell id times a fixed stride,
-// so cells never have to wait for each other.
+// so cells never have to wait for each other (tiled lists pool the blocks of a
+// tile's cells, below).
 //
 // The work is ALU bound (about 300 FP64 distance tests per particle).
 
@@ -245,10 +247,11 @@ __device__ __forceinline__ uint32_t rows_from_registers(const BuildArgs& a, E* b
 // Tiled rows.  The cells of a tile share one pooled block of tile_cells *
 // cell_stride 16-bit entries (the first cell's block and those after it): a
 // cell stages its rows in LDS as 16-bit entries, then takes its slice of the
-// pool with one atomic add and writes it with full-wave 32-bit stores, so the
-// pool has to hold the tile's total rather than every cell the largest cell's
-// rows.  The order of the slices inside a pool follows the order in which the
-// cells finish.  A cell whose rows outgrow the LDS buffer counts the rest,
+// pool (one atomic add, or in cell order when one wave builds the tile) and
+// writes it with full-wave 32-bit stores, so the pool has to hold the tile's
+// total rather than every cell the largest cell's rows.  With a wave per cell
+// the order of the slices inside a pool follows the order in which the cells
+// finish.  A cell whose rows outgrow the LDS buffer counts the rest,
 // takes its slice, and computes those rows again straight into it.
 
 // 16-bit entries of one tiled cell staged in LDS (the row buffer, which first
