@@ -114,7 +114,7 @@ extern "C" {
  *   rounding of a force sum depends on the order of the atomics; in a
  *   simulation state the integrator then runs as a pass of its own.
  *   tile_cells: cells per tile along z (0 = about 200 keys per tile at the
- *   mean density in MD_MIXED, 135 in MD_FP64); clipped to [1, nz - 2].
+ *   mean density in MD_MIXED, 146 in MD_FP64); clipped to [1, nz - 2].
  *   step_run: with MD_REBUILD_HALF_SKIN and a full list, the steps md_step
  *   queues before it waits for the device (0 = automatic: the steps the list
  *   is expected to last, from its age and the growth of the largest

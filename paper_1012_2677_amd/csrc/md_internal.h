@@ -51,9 +51,9 @@ constexpr int kCodeShift = 27;
 constexpr int kTileBlock = MD_TILE_BLOCK;     // threads of the tiled force kernel (one block per tile)
 constexpr int kTileKeys = MD_TILE_KEYS;       // target keys per tile (automatic tile length)
 #ifndef MD_TILE_KEYS_FP64
-#define MD_TILE_KEYS_FP64 135
+#define MD_TILE_KEYS_FP64 146
 #endif
-constexpr int kTileKeys64 = MD_TILE_KEYS_FP64;  // same for FP64 (32-byte staged particles)
+constexpr int kTileKeys64 = MD_TILE_KEYS_FP64;  // same for FP64 (24-byte staged particles; 13 cells at rho = 0.5)
 constexpr int kTileMaxStage = 3500;      // staged particles per tile: 16-bit byte offsets, under 64 KB of LDS
 constexpr int kTileMaxStage64 = 1950;    // FP64: 32 bytes per staged particle, under 64 KB of LDS
 static_assert((kTileMaxStage + 1) * 16 < 65536, "tiled entries are 16-bit byte offsets");
