@@ -1048,9 +1048,21 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         li.z = __shfl(own.z, ks, 64);
         if constexpr (MIXED) li.w = __shfl(own.w, ks, 64);
         R fx = 0, fy = 0, fz = 0;
+        // mixed: four partners (two words) per step where the round's bound
+        // allows, so that four LDS reads and pair chains overlap (FP64 stays at
+        // two: four take it past 128 VGPRs, 3.24 -> 3.79 ms)
+        constexpr bool QUAD = MIXED && !(ENERGY && VMAX);
 #pragma unroll
-        for (int u = 0; u < UP; ++u) {
-            if (2 * G * u < cmax) {
+        for (int u = 0; u < UP; u += QUAD ? 2 : 1) {
+            if (QUAD && u + 1 < UP && 2 * G * (u + 1) < cmax) {
+                const uint32_t e2 = 2 * G * u < lim ? E[r][u] : dummy2;
+                const uint32_t e3 = 2 * G * (u + 1) < lim ? E[r][u + 1] : dummy2;
+                const S p0 = nb(e2 & 0xFFFFu), p1 = nb(e2 >> 16), p2 = nb(e3 & 0xFFFFu), p3 = nb(e3 >> 16);
+                pair(p0, li, fx, fy, fz);
+                pair(p1, li, fx, fy, fz);
+                pair(p2, li, fx, fy, fz);
+                pair(p3, li, fx, fy, fz);
+            } else if (2 * G * u < cmax) {
                 const uint32_t e2 = 2 * G * u < lim ? E[r][u] : dummy2;
                 const S p0 = nb(e2 & 0xFFFFu), p1 = nb(e2 >> 16);
                 pair(p0, li, fx, fy, fz);
