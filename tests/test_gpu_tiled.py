@@ -15,6 +15,8 @@ reads partners from LDS.  These tests check:
   * runs with the tiled list match the oracle's run (FP64: energy log to
     1e-10 relative, same rebuilds; mixed: energy per particle to 1e-5) and the
     slot-layout run;
+  * FP64 tiles on the box faces after particles crossed the faces since the
+    build;
   * anisotropic boxes with 3-cell axes (3 neighbour columns, one-cell tiles);
   * crowded cells (a clump, a rho = 1.6 box), where the build re-reads its
     candidates from memory, and a half-empty box (tiles without keys): rows
@@ -137,6 +139,38 @@ def test_tiled_run_tracks_oracle_and_slot_run(ref, precision):
             assert np.abs(log[:, 1] - rlog[:, 1]).max() / n < 1e-5
         assert np.abs(lt - ls).max() / n < 1e-5
     assert t.rebuilds == s.rebuilds
+
+
+@pytest.mark.parametrize("tile_cells", [3, 4])
+def test_fp64_boundary_tiles_after_particles_cross_the_box_faces(ref, tile_cells):
+    # 11 cells per axis, tiles of 3 and 4 cells (the z faces cut different
+    # tiles).  Particles within 0.02 of a face in x or z are sent across it, so
+    # that two steps later (no rebuild) the list holds partners whose
+    # coordinates wrapped since the build; the step's forces and those of the
+    # energy pass match the oracle at the current positions.
+    q, L = _jittered(16, seed=5, amp=0.05)   # no close pairs: no rebuild in two steps
+    n = q.shape[0]
+    v = li.maxwell_boltzmann(n, T=1.0, seed=5)
+    moved = 0
+    for ax in (0, 2):
+        lo, hi = q[:, ax] < 0.02, q[:, ax] > L - 0.02
+        v[lo, ax] = -2.0
+        v[hi, ax] = 2.0
+        moved += int(lo.sum() + hi.sum())
+    assert moved > 100
+    e = _engine(q, v, L, precision="fp64", tile_cells=tile_cells)
+    e.step(2)
+    assert int(e.state.list_tiled) == 1 and int(e.state.tile_cells) == tile_cells
+    assert e.rebuilds == 1
+    crossed = np.abs(e.positions() - q).max(axis=1) > 0.5 * L
+    assert crossed.sum() > 100
+    idx = np.arange(n, dtype=np.int64)
+    Fr, S, pe_i, w_i, _ = ref.forces_sample(e.positions(), L, idx)
+    assert G.force_error(e.forces(), Fr, S) <= 1e-12
+    en = e.energies()
+    assert G.force_error(e.forces(), Fr, S) <= 1e-12
+    assert en[1] == pytest.approx(pe_i.sum(), rel=1e-12)
+    assert en[2] == pytest.approx(w_i.sum(), rel=1e-12)
 
 
 @pytest.mark.parametrize("precision,tile_cells", [("mixed", 18), ("fp64", 10)])
