@@ -30,6 +30,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -164,6 +165,12 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
     import lj_inputs as li
     from paper_1012_2677_amd import Engine
 
+    # the mode's footprint is its peak above what the process held before
+    # (a previous mode's state, freed here first)
+    gc.collect()
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    held_before = torch.cuda.memory_allocated()
     t0 = time.perf_counter()
     q, L = li.fcc_lattice(cfg["n_fcc"], cfg["rho"])
     v = li.initial_velocities(cfg, q.shape[0], seed=seed)
@@ -263,8 +270,13 @@ def run_mode(cfg, precision, steps, warmup, sample_every, seed, resort_every=1, 
         out["drift_per_1000_steps"] = out["protocol"]["drift_per_1000_steps"]
         log(f"[bench] {precision}: protocol {lead} + {psteps} steps: {out['protocol']['ms_per_step']:.3f} ms/step, "
             f"drift {out['drift_per_1000_steps']:.3e} per particle per 1000 steps")
-    out["hbm_footprint_bytes"] = int(torch.cuda.max_memory_allocated())
+    out["hbm_footprint_bytes"] = int(torch.cuda.max_memory_allocated() - held_before)
+    # the list grows (a larger cell stride) when a tile's rows outgrow it
+    out["list_cell_stride_end"] = int(e.plist.cell_stride)
+    if held_before:
+        out["hbm_held_before_bytes"] = int(held_before)
     del e
+    gc.collect()
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
     return out

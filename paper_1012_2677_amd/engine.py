@@ -137,7 +137,10 @@ class PairList:
         l.status = self.status.data_ptr()
 
     def grow_for(self, needed: int):
-        self.resize(int(64 * math.ceil(1.25 * needed / 64.0)))
+        # needed is the largest block (tiled: a tile's per-cell average) of the
+        # build that overflowed, already a tail value of the fluid's
+        # fluctuations: 10% above it, rounded up to 64 entries
+        self.resize(int(64 * math.ceil(1.1 * needed / 64.0)))
 
     def handle_capacity_error(self):
         """After MD_ERR_CAPACITY from a state call: a cell block overflowed
