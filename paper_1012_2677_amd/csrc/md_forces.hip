@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_fp64(
                         dz -= a.L[2] * rint(dz * a.invL[2]);
                     }
                     const double r2 = dx * dx + dy * dy + dz * dz;
-                    const double r2i = rcp64(r2);
+                    const double r2i = rcp64_1(r2);
                     const double r6i = r2i * r2i * r2i;
                     double g = r2i * r6i * (A * r6i - B) - C8;
                     const bool in = r2 < rc2;
@@ -633,7 +633,7 @@ __global__ __launch_bounds__(kForceBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_half(
                     const R r2 = dx * dx + dy * dy + dz * dz;
                     R r2i;
                     if constexpr (MIXED) r2i = __builtin_amdgcn_rcpf(r2);
-                    else r2i = rcp64(r2);
+                    else r2i = rcp64_1(r2);
                     const R r6i = r2i * r2i * r2i;
                     R g = r2i * r6i * (A * r6i - B) - C8;
                     const bool in = r2 < rc2;
@@ -944,7 +944,7 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         const R r2 = dx * dx + dy * dy + dz * dz;
         R r2i;
         if constexpr (MIXED) r2i = __builtin_amdgcn_rcpf(r2);
-        else r2i = rcp64(r2);
+        else r2i = rcp64_1(r2);
         const R r6i = r2i * r2i * r2i;
         R g = r2i * r6i * (A * r6i - B) - C8;
         const bool in = r2 < rc2;
