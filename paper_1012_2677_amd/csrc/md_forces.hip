@@ -963,15 +963,23 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
     // wave's last chunk has a round with empty key slots): nr rounds per
     // chunk instead of always G
     const int64_t nk = kend - kb;
+    // the tile's keys are cells z0 .. z1 - 1 of the centre column (run 4), in
+    // slot order: key slot k is staged at key0 + (k - kb); the run's first part
+    // starts at cell z0 - 1, or, when the tile starts the column, is the
+    // wrapped cell nz - 1 alone and the keys open its second part
+    const int key0 = s_base[4] + (z0 == 0 ? s_run[4][1] + (int)(kb - s_run[4][2]) : (int)(kb - s_run[4][0]));
     const int csz_k = nk >= NW * 64 ? 64 : (int)((((nk + NW - 1) / NW) + K - 1) / K * K);
     for (int64_t base = kb + wave * csz_k; base < kend; base += NW * csz_k) {
     const int64_t cend = base + csz_k < kend ? base + csz_k : kend;
     const int nr = (int)((cend - base + K - 1) / K);
     const int64_t mykey = base + lane;
     const bool myvalid = mykey < cend;
-    // the lane's own key: coordinates (mixed: local, with its run position in
-    // w), row offset and length; rounds fetch them from the owner lane
-    V4 own;
+    // the lane's own key: row offset and length (mixed: also its local
+    // coordinates with its run position in w); rounds fetch them from the
+    // owner lane.  FP64 rounds read the key's coordinates from its staged
+    // copy instead (two LDS reads against six cross-lane permutes; in mixed
+    // precision that takes the pass past 128 VGPRs)
+    float4 own;
     int64_t own_off;
     int own_cnt;
     {
@@ -979,8 +987,6 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         if constexpr (MIXED) {
             own = a.pos32[k];
             own.w = (float)(((__float_as_int(own.w) >> 20) & 1023) - z0 + 1);
-        } else {
-            own = a.pos[k];
         }
         own_off = a.offsets[k];
         own_cnt = myvalid ? a.counts[k] : 0;
@@ -1043,10 +1049,18 @@ __global__ __launch_bounds__(kTileBlock, MD_PAIR_MIN_BLOCKS) void k_pairs_tiled(
         const int cnt = __shfl(own_cnt, ks, 64);
         const int lim = cnt - 2 * sub;   // entries 2 G u + 2 sub + (0, 1) are the row's where 2 G u < lim
         V4 li;
-        li.x = __shfl(own.x, ks, 64);
-        li.y = __shfl(own.y, ks, 64);
-        li.z = __shfl(own.z, ks, 64);
-        if constexpr (MIXED) li.w = __shfl(own.w, ks, 64);
+        if constexpr (MIXED) {
+            li.x = __shfl(own.x, ks, 64);
+            li.y = __shfl(own.y, ks, 64);
+            li.z = __shfl(own.z, ks, 64);
+            li.w = __shfl(own.w, ks, 64);
+        } else {
+            // empty key slots read the tile's last key
+            const S lk = s_nb[key0 + (int)(min(base + ks, kend - 1) - kb)];
+            li.x = lk.x;
+            li.y = lk.y;
+            li.z = lk.z;
+        }
         R fx = 0, fy = 0, fz = 0;
         // mixed: four partners (two words) per step where the round's bound
         // allows, so that four LDS reads and pair chains overlap (FP64 stays at
